@@ -1,0 +1,177 @@
+"""Pins of the oracle's PDFs: normalisation by brute-force quadrature, the
+angular x time table against squared helicity amplitudes with B_s mixing,
+special cases, and the dual-number gradient against finite differences."""
+import numpy as np
+import pytest
+
+import pins
+from oracle import models as M
+from oracle import nll as N
+
+THETA_VARIANTS = {
+    1: [M.THETA_GEN[1], (0.7, 5300.0, 25.0, -0.003), (0.1, 5450.0, 8.0, 0.0), (1.0, 5367.0, 15.0, 0.01)],
+    2: [M.THETA_GEN[2], (0.6, 5320.0, 20.0, 0.0, 2.0, 0.4, 1.6), (0.05, 5367.0, 15.0, -0.002, 1.2, 1.9, 0.7)],
+    3: [M.THETA_GEN[3],
+        (0.45, 0.3, 0.2, 2.5, 0.4, -1.0, 0.7, 0.12, 17.0, 0.4, 5370.0, 12.0),
+        (0.6, 0.1, 0.0, 3.0, 3.0, 0.0, 0.6, -0.05, 18.5, -0.7, 5360.0, 18.0)],
+}
+
+
+def _mass_grid():
+    return pins.gl_composite(M.M_LO, M.M_HI, 10, 16)
+
+
+def _time_grid():
+    return pins.gl_composite(M.T_LO, M.T_HI, 60, 12)
+
+
+@pytest.mark.parametrize("theta", THETA_VARIANTS[1])
+def test_mass_pdf_integrates_to_one(theta):
+    m, w = _mass_grid()
+    assert abs(np.sum(w * M.pdf(1, [m], theta)) - 1.0) < 1e-13
+
+
+@pytest.mark.parametrize("theta", THETA_VARIANTS[2])
+@pytest.mark.parametrize("sigma_t", [0.03, 0.045, 0.06])
+def test_masstime_pdf_integrates_to_one(theta, sigma_t):
+    m, wm = _mass_grid()
+    t, wt = _time_grid()
+    MM, TT = np.meshgrid(m, t, indexing="ij")
+    W = wm[:, None] * wt[None, :]
+    p = M.pdf(2, [MM.ravel(), TT.ravel(), np.full(MM.size, sigma_t)], theta)
+    assert abs(np.sum(W.ravel() * p) - 1.0) < 1e-12
+
+
+def test_angular_integrals_by_quadrature():
+    ck, cl, ph, w = pins.angular_grid()
+    fk = M.angular_functions(ck, cl, ph)
+    xi = np.array([np.sum(w * f) for f in fk])
+    assert np.allclose(xi, M.ANGULAR_INTEGRALS, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("theta", THETA_VARIANTS[3])
+@pytest.mark.parametrize("sigma_t", [0.03, 0.06])
+def test_angtime_pdf_integrates_to_one(theta, sigma_t):
+    # The mass factor is independent of (Omega, t), so the 6-D integral is
+    # [integral over (Omega, t) at m0] x [integral over m at (Omega0, t0)] / P(Omega0, t0, m0).
+    ck, cl, ph, wa = pins.angular_grid(4, 6)
+    t, wt = pins.gl_composite(M.T_LO, M.T_HI, 60, 12)
+    m, wm = _mass_grid()
+    m0, x0 = 5371.0, (0.3, -0.2, 0.7, 1.1)
+    A = np.repeat(np.arange(ck.size), t.size)
+    Tt = np.tile(t, ck.size)
+    st = np.full(Tt.size, sigma_t)
+    p_ot = M.pdf(3, [ck[A], cl[A], ph[A], Tt, st, np.full(Tt.size, m0)], theta)
+    i_ot = np.sum(wa[A] * np.tile(wt, ck.size) * p_ot)
+    ones = np.ones(m.size)
+    p_m = M.pdf(3, [x0[0] * ones, x0[1] * ones, x0[2] * ones, x0[3] * ones, sigma_t * ones, m], theta)
+    p_00 = M.pdf(3, [np.array([v]) for v in x0] + [np.array([sigma_t]), np.array([m0])], theta)[0]
+    total = i_ot * np.sum(wm * p_m) / p_00
+    assert abs(total - 1.0) < 1e-11
+
+
+@pytest.mark.parametrize("lam_abs", [1.0, 0.8, 1.3])
+@pytest.mark.parametrize("theta", THETA_VARIANTS[3])
+def test_angular_time_table_equals_squared_helicity_amplitudes(theta, lam_abs, monkeypatch):
+    """sum_k f_k(Omega) sum_j C_kj h_j(t) must be proportional, with the same
+    constant (1+|lambda|^2)/4 at every (Omega, t), to the squared sum of
+    helicity amplitudes evolved with B_s mixing (no resolution)."""
+    monkeypatch.setattr(M, "LAMBDA_ABS", lam_abs)
+    ratio = _helicity_ratio(theta)
+    assert np.max(np.abs(ratio / ((1 + lam_abs ** 2) / 4) - 1)) < 1e-12
+
+
+def _helicity_ratio(theta, n=400, seed=3):
+    fL, fpe, Fs, dpa, dpe, dS, G, DG, DM, phis, _, _ = theta
+    rng = np.random.default_rng(seed)
+    ck, cl = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n)
+    ph, t = rng.uniform(-np.pi, np.pi, n), rng.uniform(0.0, 6.0, n)
+    A = pins.mixing_amplitudes(fL, fpe, Fs, dpa, dpe, dS, G, DG, DM, phis, M.LAMBDA_ABS, t)
+    lhs = pins.helicity_density(A["0"], A["pa"], A["pe"], A["S"], ck, cl, ph)
+    Cm = M.time_coefficients(fL, fpe, Fs, dpa, dpe, dS, phis)
+    fk = M.angular_functions(ck, cl, ph)
+    e = np.exp(-G * t)
+    h = [e * np.cosh(DG * t / 2), e * np.sinh(DG * t / 2), e * np.cos(DM * t), e * np.sin(DM * t)]
+    rhs = sum(fk[k] * sum(Cm[k][j] * h[j] for j in range(4)) for k in range(10))
+    return lhs / rhs
+
+
+def test_time_functions_without_resolution_reduce_to_exponentials():
+    # sigma -> 0: T_j -> e^{-G t} (cosh, sinh, cos, sin)
+    t = np.linspace(M.T_LO, M.T_HI, 40)
+    G, DG, DM = 0.66, 0.08, 17.8
+    T = M.time_functions(t, G, DG, DM, 1e-6)
+    e = np.exp(-G * t)
+    ref = [e * np.cosh(DG * t / 2), e * np.sinh(DG * t / 2), e * np.cos(DM * t), e * np.sin(DM * t)]
+    for a, b in zip(T, ref):
+        assert np.allclose(a, b, rtol=0, atol=1e-7 * e.max())
+
+
+def test_special_cases():
+    t = np.linspace(M.T_LO, 5.0, 25)
+    sig = np.full(t.size, 0.045)
+    # Delta Gamma = 0: no sinh term
+    T = M.time_functions(t, 0.66, 0.0, 17.8, sig)
+    assert np.all(T[1] == 0.0)
+    # Fs = 0: the S-wave rows k = 7..10 vanish
+    Cm = M.time_coefficients(0.52, 0.25, 0.0, 3.26, 3.08, 0.35, -0.03)
+    assert all(c == 0.0 for row in Cm[6:] for c in row)
+    # |lambda| = 1: no direct CP violation, C = 0, so the k = 1 cos weight is 0
+    assert Cm[0][2] == 0.0
+    # phis = 0: the k = 1 term is a pure e^{-Gamma_L t} (a = 1, b = D = -1)
+    Cm0 = M.time_coefficients(0.52, 0.25, 0.0, 3.26, 3.08, 0.35, 0.0)
+    assert Cm0[0][0] == pytest.approx(0.52 * 1.0) and Cm0[0][1] == pytest.approx(-0.52)
+    assert Cm0[0][3] == pytest.approx(0.0, abs=1e-18)
+    # lambda -> 0 background: exponential normalisation is the range length
+    assert M.exp_norm(0.0) == M.M_HI - M.M_LO
+
+
+def test_resolution_damps_oscillation():
+    # at large t the convolved cos term is damped by exp(-DM^2 sigma^2/2)
+    t = np.array([5.0, 7.0, 9.0])
+    G, DM, s = 0.66, 17.8, 0.05
+    Fc = M.conv_exp(t, G - 1j * DM, s)
+    ref = np.exp(((G - 1j * DM) ** 2) * s * s / 2 - (G - 1j * DM) * t)
+    assert np.allclose(Fc, ref, rtol=1e-14)
+    assert np.allclose(np.abs(Fc) / np.exp(-G * t),
+                       np.exp(-DM * DM * s * s / 2) * np.exp(G * G * s * s / 2), rtol=1e-13)
+
+
+@pytest.mark.parametrize("model", [1, 2, 3])
+def test_dual_gradient_matches_central_differences(model):
+    rng = np.random.default_rng(11 + model)
+    n = 300
+    m = rng.uniform(M.M_LO, M.M_HI, n)
+    t = M.T_LO + rng.exponential(1.2, n) % (M.T_HI - M.T_LO)
+    st = rng.uniform(0.03, 0.06, n)
+    cols = {1: [m], 2: [m, t, st],
+            3: [rng.uniform(-1, 1, n), rng.uniform(-1, 1, n), rng.uniform(-np.pi, np.pi, n), t, st, m]}[model]
+    w = rng.uniform(0.8, 1.0, n) if model == 3 else None
+    theta = np.array(M.THETA_GEN[model]) * (1 + 0.02 * rng.standard_normal(M.NPARAMS[model]))
+    f, g = N.nll_grad(model, cols, theta, w)
+    assert f == N.nll(model, cols, theta, w)
+    for j in range(len(theta)):
+        # 4th-order central difference
+        h = 1e-4 * max(1.0, abs(theta[j]))
+        def fj(dx):
+            th = theta.copy()
+            th[j] += dx
+            return N.nll(model, cols, th, w)
+        fd = (8 * (fj(h) - fj(-h)) - (fj(2 * h) - fj(-2 * h))) / (12 * h)
+        scale = np.sum(np.abs(N.event_grad(model, cols, theta)[j]))
+        roundoff = 1e-14 * abs(f) / h      # rounding of the NLL values in the stencil
+        assert abs(g[j] - fd) <= 1e-6 * abs(fd) + 1e-8 * scale + roundoff, (j, g[j], fd)
+
+
+def test_invalid_theta_gives_inf():
+    cols = [np.array([5300.0])]
+    assert N.nll(1, cols, (1.2, 5367.0, 15.0, 0.002)) == np.inf
+    assert N.nll(1, cols, (0.3, 5367.0, -1.0, 0.002)) == np.inf
+    assert N.nll(1, cols, (0.3, np.nan, 15.0, 0.002)) == np.inf
+    c3 = [np.array([0.1]), np.array([0.2]), np.array([0.3]), np.array([1.0]), np.array([0.04]), np.array([5360.0])]
+    bad = list(M.THETA_GEN[3])
+    bad[0], bad[1] = 0.7, 0.4      # fL + fperp > 1
+    assert N.nll(3, c3, bad) == np.inf
+    bad = list(M.THETA_GEN[3])
+    bad[7] = 2.0                   # Gamma_H < 0
+    assert N.nll(3, c3, bad) == np.inf
