@@ -1,0 +1,149 @@
+"""Benchmark: NLL + gradient evaluations per second on one MI355X.
+
+One step = one nll_grad call over the angular x decay-time workload
+(N = 4,000,000 events, 6 FP64 columns + weights, 12 free parameters): parameter
+hoisting, the per-event PDF / normalisation / weighted log / adjoint kernel, the
+two-level tile reduction, the 53-double readback and the host Jacobian.
+The event sample is resident in HBM before the timed region starts.
+
+Prints one JSON line.  Usage:
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "NLL+grad evaluations/sec and events/sec (FP64); fits/sec batched vs plain; p99"
+PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 FLOP/clk
+PEAK_HBM_GBS = 8000.0
+
+# Algorithmic FP64 operations per event of the per-event kernels, counted on
+# the formula (not on the generated code); the derivation is in the design doc.
+FLOP_PER_EVENT = {
+    (1, False): 58, (1, True): 80,
+    (2, False): 560, (2, True): 900,
+    (3, False): 800, (3, True): 1140,
+}
+BYTES_PER_EVENT = {1: 8, 2: 24, 3: 56}
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=50)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-extra", action="store_true", help="skip the secondary per-model rates")
+    return p.parse_args()
+
+
+def timed_rate(ipx, ctx, ds, theta, steps, warmup, grad):
+    import torch
+    call = (lambda: ipx.nll_grad(ctx, ds, theta)) if grad else (lambda: ipx.nll_eval(ctx, ds, theta))
+    for _ in range(warmup):
+        call()
+    torch.cuda.synchronize()
+    ipx.ipx_timing_read(ctx, reset=True)
+    ipx.ipx_timing_enable(ctx, True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        call()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ipx.ipx_timing_enable(ctx, False)
+    kms, launches = ipx.ipx_timing_read(ctx, reset=True)
+    return (t1 - t0) / steps, kms / max(launches, 1) / 1e3
+
+
+def cpu_baseline(cols, w, theta, n_total, sample):
+    import numpy as np
+    from oracle import nll as N
+    sub = [c[:sample] for c in cols]
+    ws = None if w is None else w[:sample]
+    t0 = time.perf_counter()
+    N.nll_grad(3, sub, np.asarray(theta), ws)
+    dt = time.perf_counter() - t0
+    per_eval = dt * n_total / sample
+    return {"value": 1.0 / per_eval, "unit": "NLL+grad evals/s", "cores": 1, "kind": "oracle",
+            "sample": "oracle nll_grad (numpy/scipy FP64, one thread) on the first %d of the %d events, "
+                      "%.2f s, scaled to the full sample" % (sample, n_total, dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the likelihood path is measured on a single MI355X "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_1706_01420_amd import ipx, workloads
+
+    model = 3
+    n = workloads.WORKLOAD_SIZES[model]
+    cols, w = workloads.events(model, n)
+    theta = np.array(workloads.THETA_GEN[model])
+    ctx = ipx.ipx_create(0)
+    ds = ipx.ipx_dataset_create(ctx, model, cols, w)
+    torch.cuda.synchronize()
+
+    step_s, kernel_s = timed_rate(ipx, ctx, ds, theta, args.steps, args.warmup, grad=True)
+    value = 1.0 / step_s
+    flops = FLOP_PER_EVENT[(model, True)] * n
+    achieved = flops / kernel_s / 1e12
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "NLL+grad evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_s * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded numpy draws with the workload's ranges and distributions)",
+        "config": {"workload": "angular x decay-time unbinned NLL+gradient, N=4,000,000 events, "
+                               "12 free parameters, per-event weights U(0.8,1)",
+                   "n_events": n, "parallelism": "single GPU"},
+        "events_per_s": value * n,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "kernel": "k_nll_tiles<3,true>", "kernel_us": kernel_s * 1e6,
+                     "flop_per_event": FLOP_PER_EVENT[(model, True)]},
+    }
+    extra = {}
+    if not args.no_extra:
+        e_step, e_kern = timed_rate(ipx, ctx, ds, theta, max(args.steps // 2, 5), 2, grad=False)
+        extra["angtime_nll_eval"] = {"evals_per_s": 1 / e_step, "kernel_us": e_kern * 1e6,
+                                     "tflops": FLOP_PER_EVENT[(3, False)] * n / e_kern / 1e12}
+    ipx.ipx_dataset_destroy(ctx, ds)
+    if not args.no_extra:
+        for m in (1, 2):
+            nm = workloads.WORKLOAD_SIZES[m]
+            c, wm = workloads.events(m, nm)
+            d = ipx.ipx_dataset_create(ctx, m, c, wm)
+            th = np.array(workloads.THETA_GEN[m])
+            for grad in (False, True):
+                s, k = timed_rate(ipx, ctx, d, th, max(args.steps // 2, 5), 2, grad)
+                key = ("mass" if m == 1 else "masstime") + ("_nll_grad" if grad else "_nll_eval")
+                extra[key] = {"n_events": nm, "evals_per_s": 1 / s, "us_per_eval": s * 1e6,
+                              "kernel_us": k * 1e6,
+                              "tflops": FLOP_PER_EVENT[(m, grad)] * nm / k / 1e12,
+                              "hbm_gbs": BYTES_PER_EVENT[m] * nm / k / 1e9}
+            ipx.ipx_dataset_destroy(ctx, d)
+        out["extra"] = extra
+    ipx.ipx_destroy(ctx)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cols, w, theta, n, 150_000)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

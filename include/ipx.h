@@ -1,0 +1,159 @@
+/*
+ * ipx.h -- C ABI of libipx, an FP64 unbinned maximum-likelihood engine for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates NLL(theta) = -sum_i w_i ln P(x_i | theta) over an
+ * event sample resident in device memory, and its gradient, for three
+ * probability density families.  It is the per-call work that a minimizer or
+ * sampler performs once per parameter vector (Ipanema-beta, arXiv:1706.01420,
+ * Example 1: the FCN handed to Minuit; Example 2: the simultaneous angular fit
+ * driven through the same FCN).
+ *
+ * Conventions (apply to every function below):
+ *   - Every function returns ipx_status (0 = IPX_OK, negative = error) and
+ *     never throws or aborts.  The message of the last error on the calling
+ *     thread is returned by ipx_last_error().
+ *   - theta, nll and grad are caller-owned HOST memory, read/written before the
+ *     call returns.  theta holds the parameters in the order listed for the
+ *     model (IPX_MODEL_*).
+ *   - stream is a hipStream_t cast to void*; NULL selects the context's own
+ *     stream.  Calls that return a value synchronise that stream before
+ *     returning.
+ *   - Parameters outside the model's domain return IPX_EDOMAIN with
+ *     *nll = +inf and launch nothing.  An event with P <= 0 or a non-finite
+ *     contribution makes the sum non-finite: the call returns IPX_EDOMAIN
+ *     with *nll = +inf.
+ *   - NLL is -ln L (not -2 ln L); a minimizer uses errordef 0.5.
+ */
+#ifndef IPX_H
+#define IPX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IPX_API __attribute__((visibility("default")))
+
+typedef enum {
+  IPX_OK = 0,
+  IPX_EINVAL = -1,    /* bad argument (null pointer, size, model, column count) */
+  IPX_ENOMEM = -2,    /* device or pinned-host allocation failed, or budget exceeded */
+  IPX_EDEVICE = -3,   /* a HIP runtime call failed */
+  IPX_EBUSY = -4,     /* resource busy (queue full, result not ready) */
+  IPX_ENOTFOUND = -5, /* unknown handle or ticket */
+  IPX_ETIMEOUT = -6,  /* wait timed out */
+  IPX_EDOMAIN = -7    /* parameters outside the domain, or a non-finite likelihood */
+} ipx_status;
+
+/*
+ * Models.  Columns are FP64, one contiguous array per observable, in the
+ * order given; parameters are FP64 in the order given.
+ *
+ * IPX_MODEL_MASS (Example 1: signal peak on an exponential background)
+ *   columns: m [MeV], range [5200, 5500]
+ *   theta:   f, mu, sigma, lambda            (4)
+ *   P(m) = f G(m)/N_G + (1-f) E(m)/N_E, G = exp(-(m-mu)^2/(2 sigma^2)),
+ *   E = exp(-lambda (m - 5200)), both normalised on the range (lambda = 0
+ *   handled exactly).
+ *
+ * IPX_MODEL_MASSTIME (mass x decay time with per-event Gaussian resolution)
+ *   columns: m, t [ps] in [0.3, 15], sigma_t [ps]
+ *   theta:   f, mu, sigma_m, lambda, tau_s, tau_b, s     (7)
+ *   P = f [G/N_G][F(t;1/tau_s,s sigma_t)/I] + (1-f)[E/N_E][F(t;1/tau_b,s sigma_t)/I]
+ *   F = e^{-t/tau} convolved with a Gaussian of width s sigma_t, I = its
+ *   integral over [0.3, 15]; conditional on sigma_t.
+ *
+ * IPX_MODEL_ANGTIME (Example 2: B_s -> J/psi KK time-dependent angular PDF,
+ *   P wave + S wave, one flavour, |lambda| = 1, C_SP = 1, delta_0 = 0)
+ *   columns: cos_k, cos_l, phi [rad], t [ps], sigma_t [ps], m [MeV]
+ *   theta:   fL, fperp, Fs, delta_par, delta_perp, delta_S, Gamma, DeltaGamma,
+ *            Delta_m, phi_s, mu_m, sigma_m                              (12)
+ *   P = [sum_k f_k(Omega) sum_j C_kj T_j(t|sigma_t)] / [sum_j D_j I_j(sigma_t)]
+ *       x G(m)/N_G, T_j the resolution-convolved e^{-Gamma t} x
+ *       (cosh, sinh)(DeltaGamma t/2), (cos, sin)(Delta_m t), I_j their integrals
+ *       over [0.3, 15], D_j = sum_k (integral f_k dOmega) C_kj.
+ */
+typedef enum {
+  IPX_MODEL_MASS = 1,
+  IPX_MODEL_MASSTIME = 2,
+  IPX_MODEL_ANGTIME = 3
+} ipx_model;
+
+/* dataset creation flags */
+#define IPX_COPY_HOST 0u     /* cols/w are host pointers; data are copied to the device */
+#define IPX_COPY_DEVICE 1u   /* cols/w are device pointers; data are copied device-to-device */
+#define IPX_BORROW_DEVICE 2u /* cols/w are device pointers used in place; the caller keeps them alive */
+
+typedef struct ipx_ctx ipx_ctx;
+typedef struct ipx_dataset ipx_dataset;
+
+/* Create a context on HIP device `device` (owns a stream and small buffers). */
+IPX_API ipx_status ipx_create(int device, ipx_ctx **out);
+/* Destroy a context; datasets created on it must be destroyed first. */
+IPX_API void ipx_destroy(ipx_ctx *ctx);
+/* Message of the last failed call on this thread ("" if none). */
+IPX_API const char *ipx_last_error(void);
+/* Number of parameters / columns of a model, or -1 for an unknown model. */
+IPX_API int ipx_model_nparams(int model);
+IPX_API int ipx_model_ncols(int model);
+
+/*
+ * Create a dataset of n >= 0 events for `model`.
+ *   cols:  ncols (= ipx_model_ncols(model)) pointers to n doubles each, in the
+ *          model's column order (host or device memory per `flags`).
+ *   w:     optional per-event weights (n doubles, same memory kind), NULL for 1.
+ * With IPX_COPY_*, the library owns the device copy (one allocation, columns
+ * padded to 256-byte boundaries).  The dataset also holds the scratch for its
+ * reduction partials, so calls on different datasets may run concurrently on
+ * different streams; calls on one dataset must not overlap.
+ */
+IPX_API ipx_status ipx_dataset_create(ipx_ctx *ctx, int model, int64_t n, const double *const *cols,
+                              int ncols, const double *w, unsigned flags, ipx_dataset **out);
+IPX_API ipx_status ipx_dataset_destroy(ipx_ctx *ctx, ipx_dataset *ds);
+/* Device bytes held by the dataset (columns, weights, scratch). */
+IPX_API size_t ipx_dataset_bytes(const ipx_dataset *ds);
+IPX_API int64_t ipx_dataset_size(const ipx_dataset *ds);
+IPX_API int ipx_dataset_model(const ipx_dataset *ds);
+/* Device pointer of column `col` (0..ncols-1) or of the weights (col = ncols,
+ * NULL when unweighted). */
+IPX_API ipx_status ipx_dataset_column(const ipx_dataset *ds, int col, const double **dev_ptr);
+
+/*
+ * NLL of the dataset at theta (np = ipx_model_nparams(model) doubles).
+ * The per-event terms are summed in a fixed order that depends only on the
+ * dataset size: per-lane sequential sums over fixed event strides, a fixed
+ * wave/workgroup tree per tile of events, then the tiles in index order.  The
+ * result is therefore bitwise reproducible for the same dataset and theta,
+ * whatever the launch size or concurrent traffic.
+ */
+IPX_API ipx_status nll_eval(ipx_ctx *ctx, const ipx_dataset *ds, const double *theta, int np, double *nll,
+                    void *stream);
+
+/*
+ * NLL and its gradient dNLL/dtheta (np doubles written to grad), from a
+ * hand-written adjoint kernel: each event accumulates the derivatives of its
+ * term with respect to the per-call hoisted quantities (coefficients,
+ * normalisations, decay constants); the host applies the Jacobian of the
+ * hoisting.  The NLL value is bitwise equal to nll_eval's.
+ */
+IPX_API ipx_status nll_grad(ipx_ctx *ctx, const ipx_dataset *ds, const double *theta, int np, double *nll,
+                    double *grad, void *stream);
+
+/*
+ * Timing of the dominant kernel of nll_eval/nll_grad, measured with HIP events
+ * recorded on the stream the kernel is launched on.  While enabled, each call
+ * records a start/stop event pair around its per-event kernel; ipx_timing_read
+ * returns the summed kernel milliseconds and the number of launches since the
+ * last reset (it synchronises the recorded events).
+ */
+IPX_API ipx_status ipx_timing_enable(ipx_ctx *ctx, int enable);
+IPX_API ipx_status ipx_timing_read(ipx_ctx *ctx, double *total_ms, int64_t *launches, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IPX_H */

@@ -1,0 +1,270 @@
+// Host-side hoisting: from theta to the per-call constants the kernels read,
+// and the Jacobian that maps the kernels' adjoint sums back to dNLL/dtheta.
+#pragma once
+
+#include <cmath>
+
+#include "ipx_models.h"
+
+namespace ipx {
+
+// ---------------------------------------------------------------------------
+// Small forward-mode dual number on the host (value + N derivatives), used to
+// differentiate the angular coefficient table with respect to its parameters.
+// ---------------------------------------------------------------------------
+template <int N>
+struct HD {
+  double v;
+  double d[N];
+  HD() : v(0.0) { for (int i = 0; i < N; ++i) d[i] = 0.0; }
+  HD(double x) : v(x) { for (int i = 0; i < N; ++i) d[i] = 0.0; }  // NOLINT: constant
+  static HD var(double x, int j) { HD r(x); r.d[j] = 1.0; return r; }
+};
+template <int N> inline HD<N> operator+(const HD<N>& a, const HD<N>& b) { HD<N> r; r.v = a.v + b.v; for (int i = 0; i < N; ++i) r.d[i] = a.d[i] + b.d[i]; return r; }
+template <int N> inline HD<N> operator-(const HD<N>& a, const HD<N>& b) { HD<N> r; r.v = a.v - b.v; for (int i = 0; i < N; ++i) r.d[i] = a.d[i] - b.d[i]; return r; }
+template <int N> inline HD<N> operator-(const HD<N>& a) { HD<N> r; r.v = -a.v; for (int i = 0; i < N; ++i) r.d[i] = -a.d[i]; return r; }
+template <int N> inline HD<N> operator*(const HD<N>& a, const HD<N>& b) { HD<N> r; r.v = a.v * b.v; for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * b.v + a.v * b.d[i]; return r; }
+template <int N> inline HD<N> operator*(double s, const HD<N>& a) { HD<N> r; r.v = s * a.v; for (int i = 0; i < N; ++i) r.d[i] = s * a.d[i]; return r; }
+template <int N> inline HD<N> hsin(const HD<N>& a) { HD<N> r; r.v = std::sin(a.v); const double c = std::cos(a.v); for (int i = 0; i < N; ++i) r.d[i] = c * a.d[i]; return r; }
+template <int N> inline HD<N> hcos(const HD<N>& a) { HD<N> r; r.v = std::cos(a.v); const double s = -std::sin(a.v); for (int i = 0; i < N; ++i) r.d[i] = s * a.d[i]; return r; }
+// sqrt with a zero derivative at 0 (the amplitude moduli enter squared there)
+template <int N> inline HD<N> hsqrt(const HD<N>& a) { HD<N> r; r.v = std::sqrt(a.v); const double h = r.v > 0.0 ? 0.5 / r.v : 0.0; for (int i = 0; i < N; ++i) r.d[i] = h * a.d[i]; return r; }
+
+// ---------------------------------------------------------------------------
+// Mass normalisations and their derivatives
+// ---------------------------------------------------------------------------
+struct GaussNorm {
+  double N, dmu, dsig;  // N_G and its partial derivatives
+};
+inline GaussNorm gauss_norm(double mu, double sig) {
+  const double r2s = std::sqrt(2.0) * sig;
+  GaussNorm g;
+  g.N = sig * std::sqrt(M_PI / 2.0) * (std::erfc((kMLo - mu) / r2s) - std::erfc((kMHi - mu) / r2s));
+  const double za = (kMLo - mu) / sig, zb = (kMHi - mu) / sig;
+  const double Ga = std::exp(-0.5 * za * za), Gb = std::exp(-0.5 * zb * zb);
+  g.dmu = Ga - Gb;
+  g.dsig = g.N / sig + za * Ga - zb * Gb;
+  return g;
+}
+
+struct ExpNorm {
+  double N, dlam;
+};
+inline ExpNorm exp_norm(double lam) {
+  const double L = kMHi - kMLo;
+  const double x = lam * L;
+  ExpNorm e;
+  if (std::fabs(x) < 1e-3) {
+    // series of (1 - e^{-x})/x and its derivative, truncation < 1e-19 relative
+    e.N = L * (1.0 - x / 2.0 + x * x / 6.0 - x * x * x / 24.0 + x * x * x * x / 120.0);
+    e.dlam = L * L * (-0.5 + x / 3.0 - x * x / 8.0 + x * x * x / 30.0 - x * x * x * x / 144.0);
+  } else {
+    e.N = -std::expm1(-x) / lam;
+    e.dlam = L * std::exp(-x) / lam - e.N / lam;
+  }
+  return e;
+}
+
+// ---------------------------------------------------------------------------
+// Parameter domains
+// ---------------------------------------------------------------------------
+inline bool all_finite(const double* th, int n) {
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(th[i])) return false;
+  return true;
+}
+inline bool theta_valid(int model, const double* th) {
+  if (model == 1) return all_finite(th, 4) && th[0] >= 0.0 && th[0] <= 1.0 && th[2] > 0.0;
+  if (model == 2)
+    return all_finite(th, 7) && th[0] >= 0.0 && th[0] <= 1.0 && th[2] > 0.0 && th[4] > 0.0 && th[5] > 0.0 &&
+           th[6] > 0.0;
+  if (model == 3)
+    return all_finite(th, 12) && th[0] >= 0.0 && th[1] >= 0.0 && th[0] + th[1] <= 1.0 && th[2] >= 0.0 &&
+           th[2] <= 1.0 && th[11] > 0.0 && th[6] - std::fabs(th[7]) / 2.0 > 0.0;
+  return false;
+}
+
+// ---------------------------------------------------------------------------
+// Model 1
+// ---------------------------------------------------------------------------
+struct MassHoist {
+  MassConst k;
+  GaussNorm ng;
+  ExpNorm ne;
+};
+inline MassHoist hoist_mass(const double* th) {
+  MassHoist h;
+  const double f = th[0], mu = th[1], sig = th[2], lam = th[3];
+  h.ng = gauss_norm(mu, sig);
+  h.ne = exp_norm(lam);
+  h.k.cS = f / h.ng.N;
+  h.k.cB = (1.0 - f) / h.ne.N;
+  h.k.mu = mu;
+  h.k.q = 1.0 / (2.0 * sig * sig);
+  h.k.lam = lam;
+  return h;
+}
+// a: adjoint sums (component 0 = sum w ln P); g: dNLL/dtheta
+inline void grad_mass(const MassHoist& h, const double* th, const double* a, double* g) {
+  const double f = th[0], sig = th[2];
+  const double NG = h.ng.N, NE = h.ne.N;
+  const double dl_f = a[1] / NG - a[2] / NE;
+  const double dl_mu = a[3] - a[1] * f / (NG * NG) * h.ng.dmu;
+  const double dl_sig = a[4] * (-1.0 / (sig * sig * sig)) - a[1] * f / (NG * NG) * h.ng.dsig;
+  const double dl_lam = a[5] - a[2] * (1.0 - f) / (NE * NE) * h.ne.dlam;
+  g[0] = -dl_f; g[1] = -dl_mu; g[2] = -dl_sig; g[3] = -dl_lam;
+}
+
+// ---------------------------------------------------------------------------
+// Model 2
+// ---------------------------------------------------------------------------
+struct MassTimeHoist {
+  MassTimeConst k;
+  GaussNorm ng;
+  ExpNorm ne;
+};
+inline MassTimeHoist hoist_masstime(const double* th) {
+  MassTimeHoist h;
+  const double f = th[0], mu = th[1], sig = th[2], lam = th[3], ts = th[4], tb = th[5], s = th[6];
+  h.ng = gauss_norm(mu, sig);
+  h.ne = exp_norm(lam);
+  MassTimeConst& k = h.k;
+  k.cS = f / h.ng.N;
+  k.cB = (1.0 - f) / h.ne.N;
+  k.mu = mu;
+  k.q = 1.0 / (2.0 * sig * sig);
+  k.lam = lam;
+  k.s = s;
+  k.gs = 1.0 / ts;
+  k.gb = 1.0 / tb;
+  k.hs2 = 0.5 * k.gs * k.gs;
+  k.hb2 = 0.5 * k.gb * k.gb;
+  k.gmax = k.gs > k.gb ? k.gs : k.gb;
+  k.eAs = std::exp(-k.gs * kTLo);
+  k.eBs = std::exp(-k.gs * kTHi);
+  k.eAb = std::exp(-k.gb * kTLo);
+  k.eBb = std::exp(-k.gb * kTHi);
+  k.inv_gs = ts;
+  k.inv_gb = tb;
+  return h;
+}
+inline void grad_masstime(const MassTimeHoist& h, const double* th, const double* a, double* g) {
+  const double f = th[0], sig = th[2], ts = th[4], tb = th[5];
+  const double NG = h.ng.N, NE = h.ne.N;
+  g[0] = -(a[1] / NG - a[2] / NE);
+  g[1] = -(a[3] - a[1] * f / (NG * NG) * h.ng.dmu);
+  g[2] = -(a[4] * (-1.0 / (sig * sig * sig)) - a[1] * f / (NG * NG) * h.ng.dsig);
+  g[3] = -(a[5] - a[2] * (1.0 - f) / (NE * NE) * h.ne.dlam);
+  g[4] = -(a[6] * (-1.0 / (ts * ts)));
+  g[5] = -(a[7] * (-1.0 / (tb * tb)));
+  g[6] = -a[8];
+}
+
+// ---------------------------------------------------------------------------
+// Model 3
+// ---------------------------------------------------------------------------
+// Integrals of the ten angular functions over the full angular range.
+constexpr double kXi[10] = {32.0 * M_PI / 9.0, 32.0 * M_PI / 9.0, 32.0 * M_PI / 9.0, 0.0, 0.0, 0.0,
+                            32.0 * M_PI / 9.0, 0.0, 0.0, 0.0};
+
+using HD7 = HD<7>;  // directions: fL, fperp, Fs, dpa, dpe, dS, phis
+
+// C[k][j] = N_k (a_k, b_k, c_k, d_k), |lambda| = 1, C_SP = 1, delta_0 = 0.
+inline void angular_coefficients(const double* th, HD7 C[10][4]) {
+  const HD7 fL = HD7::var(th[0], 0), fpe = HD7::var(th[1], 1), Fs = HD7::var(th[2], 2);
+  const HD7 dpa = HD7::var(th[3], 3), dpe = HD7::var(th[4], 4), dS = HD7::var(th[5], 5);
+  const HD7 phis = HD7::var(th[9], 6);
+  const HD7 one(1.0), zero(0.0);
+  const HD7 Cc = zero;            // (1 - |lambda|^2)/(1 + |lambda|^2)
+  const HD7 S = -hsin(phis);      // -2|lambda| sin(phis)/(1 + |lambda|^2)
+  const HD7 Dd = -hcos(phis);     // -2|lambda| cos(phis)/(1 + |lambda|^2)
+  const HD7 a0 = (one - Fs) * fL, ape = (one - Fs) * fpe, apa = (one - Fs) * (one - fL - fpe), aS = Fs;
+  const HD7 r0 = hsqrt(a0), rpe = hsqrt(ape), rpa = hsqrt(apa), rS = hsqrt(aS);
+  const HD7 d0 = zero;
+  const HD7 spp = hsin(dpe - dpa), cpp = hcos(dpe - dpa);
+  const HD7 cp0 = hcos(dpa - d0);
+  const HD7 se0 = hsin(dpe - d0), ce0 = hcos(dpe - d0);
+  const HD7 cpS = hcos(dpa - dS), spS = hsin(dpa - dS);
+  const HD7 seS = hsin(dpe - dS);
+  const HD7 c0S = hcos(d0 - dS), s0S = hsin(d0 - dS);
+  const HD7 N[10] = {a0, apa, ape, rpa * rpe, r0 * rpa, r0 * rpe, aS, rS * rpa, rS * rpe, rS * r0};
+  const HD7 abcd[10][4] = {
+      {one, Dd, Cc, -S},
+      {one, Dd, Cc, -S},
+      {one, -Dd, Cc, S},
+      {Cc * spp, S * cpp, spp, Dd * cpp},
+      {cp0, Dd * cp0, Cc * cp0, -(S * cp0)},
+      {Cc * se0, S * ce0, se0, Dd * ce0},
+      {one, -Dd, Cc, S},
+      {Cc * cpS, S * spS, cpS, Dd * spS},
+      {seS, -(Dd * seS), Cc * seS, S * seS},
+      {Cc * c0S, S * s0S, c0S, Dd * s0S},
+  };
+  for (int k = 0; k < 10; ++k)
+    for (int j = 0; j < 4; ++j) C[k][j] = N[k] * abcd[k][j];
+}
+
+struct AngTimeHoist {
+  AngTimeConst k;
+  HD7 C[10][4];
+  GaussNorm ng;
+};
+inline AngTimeHoist hoist_angtime(const double* th) {
+  AngTimeHoist h;
+  angular_coefficients(th, h.C);
+  AngTimeConst& k = h.k;
+  for (int j = 0; j < 4; ++j) {
+    double s = 0.0;
+    for (int kk = 0; kk < 10; ++kk) {
+      k.C[kk][j] = h.C[kk][j].v;
+      s += kXi[kk] * h.C[kk][j].v;
+    }
+    k.D[j] = s;
+  }
+  const double G = th[6], DG = th[7], DM = th[8];
+  k.gH = G - DG / 2.0;
+  k.gL = G + DG / 2.0;
+  k.g = G;
+  k.dm = DM;
+  k.gmax = std::fmax(std::fmax(k.gH, k.gL), G);
+  k.hH2 = 0.5 * k.gH * k.gH;
+  k.hL2 = 0.5 * k.gL * k.gL;
+  k.hc2 = 0.5 * (G * G - DM * DM);
+  k.gdm = G * DM;
+  k.eAH = std::exp(-k.gH * kTLo); k.eBH = std::exp(-k.gH * kTHi);
+  k.eAL = std::exp(-k.gL * kTLo); k.eBL = std::exp(-k.gL * kTHi);
+  k.eAG = std::exp(-G * kTLo);    k.eBG = std::exp(-G * kTHi);
+  k.cA = std::cos(DM * kTLo); k.sA = std::sin(DM * kTLo);
+  k.cB = std::cos(DM * kTHi); k.sB = std::sin(DM * kTHi);
+  k.inv_gH = 1.0 / k.gH;
+  k.inv_gL = 1.0 / k.gL;
+  const double den = G * G + DM * DM;  // 1/(G - i DM) = (G + i DM)/(G^2 + DM^2)
+  k.izr = G / den;
+  k.izi = DM / den;
+  const double mu = th[10], sig = th[11];
+  h.ng = gauss_norm(mu, sig);
+  k.mu = mu;
+  k.q = 1.0 / (2.0 * sig * sig);
+  k.lnNG = std::log(h.ng.N);
+  return h;
+}
+inline void grad_angtime(const AngTimeHoist& h, const double* th, const double* a, double* g) {
+  // total adjoint of C_kj: direct plus through D_j = sum_k xi_k C_kj
+  double phys[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int kk = 0; kk < 10; ++kk)
+    for (int j = 0; j < 4; ++j) {
+      const double adj = a[1 + 4 * kk + j] + kXi[kk] * a[41 + j];
+      for (int p = 0; p < 7; ++p) phys[p] += adj * h.C[kk][j].d[p];
+    }
+  const double dG = a[45] + a[46] + a[47];
+  const double dDG = -0.5 * a[45] + 0.5 * a[46];
+  const double dDM = a[48];
+  const double sig = th[11];
+  const double NG = h.ng.N;
+  const double dmu = a[49] - a[51] * h.ng.dmu / NG;
+  const double dsig = a[50] * (-1.0 / (sig * sig * sig)) - a[51] * h.ng.dsig / NG;
+  const double dl[12] = {phys[0], phys[1], phys[2], phys[3], phys[4], phys[5], dG, dDG, dDM, phys[6], dmu, dsig};
+  for (int i = 0; i < 12; ++i) g[i] = -dl[i];
+}
+
+}  // namespace ipx

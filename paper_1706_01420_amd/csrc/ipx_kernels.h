@@ -1,0 +1,382 @@
+// Per-event likelihood kernels and the deterministic two-level FP64 reduction.
+//
+// One lane evaluates kEventsPerLane events of a canonical tile (event index
+// tile*kTile + e*256 + lane, so each load instruction of a wave reads 64
+// consecutive doubles of a column), keeping the running sums of ln P and, for
+// the gradient kernels, of the adjoints in registers.  At the end of a tile
+// the sums are reduced across the wave by an xor butterfly (every lane ends
+// with the same, order-fixed total), across the four waves through LDS in wave
+// order, and written as one partial per tile (component-major).  A second
+// kernel sums the tile partials of each component in index order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "ipx_math.h"
+#include "ipx_models.h"
+
+namespace ipx {
+
+// ---------------------------------------------------------------------------
+// Reduction
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <int NACC>
+__device__ __forceinline__ void tile_store(const double (&acc)[NACC], double* __restrict__ partials,
+                                           int64_t tile, int64_t n_tiles) {
+  __shared__ double lds[kThreads / 64][NACC];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < NACC; ++c) {
+    const double v = wave_sum(acc[c]);
+    if (lane == 0) lds[wave][c] = v;
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < NACC; c += kThreads)
+    partials[(int64_t)c * n_tiles + tile] = (lds[0][c] + lds[1][c]) + (lds[2][c] + lds[3][c]);
+  __syncthreads();
+}
+
+// out[c] = sum over tiles of partials[c][tile], one workgroup per component.
+__global__ __launch_bounds__(kThreads) void k_reduce_tiles(const double* __restrict__ partials,
+                                                           int64_t n_tiles, double* __restrict__ out) {
+  const int c = blockIdx.x;
+  const double* p = partials + (int64_t)c * n_tiles;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n_tiles; i += kThreads) s += p[i];
+  __shared__ double lds[kThreads / 64];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[c] = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+}
+
+// ---------------------------------------------------------------------------
+// Model 1: mass
+// ---------------------------------------------------------------------------
+template <bool GRAD>
+__device__ __forceinline__ void event_mass(const MassConst& k, double m, double w, double* acc) {
+  const double d = m - k.mu;
+  const double G = exp(-d * d * k.q);
+  const double E = exp(-k.lam * (m - kMLo));
+  const double P = k.cS * G + k.cB * E;
+  acc[0] += w * log(P);
+  if constexpr (GRAD) {
+    const double iw = w / P;
+    const double ps = k.cS * G * iw;
+    acc[1] += G * iw;
+    acc[2] += E * iw;
+    acc[3] += ps * 2.0 * k.q * d;
+    acc[4] -= ps * d * d;
+    acc[5] -= k.cB * E * iw * (m - kMLo);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Resolution-convolved exponentials
+//   F(tau; z, s) = exp(z^2 s^2/2 - z tau) - 1/2 g w(-u)   (Im u < 0)
+//               = 1/2 g w(u)                              (Im u >= 0)
+//   u = i (z s^2 - tau)/(sqrt2 s),  g = exp(-tau^2/(2 s^2)).
+// For a real rate, w on the imaginary axis is erfcx.
+// ---------------------------------------------------------------------------
+struct TimePoint {
+  double g;     // exp(-tau^2 / (2 s^2)), 0 when the correction is negligible
+  bool need;    // correction evaluated
+};
+
+__device__ __forceinline__ TimePoint time_point(double tau, double gmax, double s2, double inv_r2s,
+                                                double re_u2) {
+  TimePoint p;
+  const double x = (tau - gmax * s2) * inv_r2s;  // smallest |Im u| over the rates
+  p.need = !(x > 0.0 && x * x - re_u2 > kCorrSkip);
+  const double a = tau * inv_r2s;
+  p.g = p.need ? exp(-a * a) : 0.0;
+  return p;
+}
+
+__device__ __forceinline__ double conv_real(double tau, double rate, double main, const TimePoint& p,
+                                            double s2, double inv_r2s) {
+  if (!p.need) return main;
+  const double y = (tau - rate * s2) * inv_r2s;  // -Im u
+  const double hg = 0.5 * p.g;
+  return y >= 0.0 ? main - hg * erfcx_pos(y) : hg * erfcx_pos(-y);
+}
+
+// complex rate Gamma - i dm; dmr = dm s / sqrt2 = Re u
+__device__ __forceinline__ cplx conv_cplx(double tau, double rate, double dmr, cplx main, const TimePoint& p,
+                                          double s2, double inv_r2s) {
+  if (!p.need) return main;
+  const double y = (tau - rate * s2) * inv_r2s;
+  const double hg = 0.5 * p.g;
+  if (y >= 0.0) return csub(main, cscale(faddeeva_upper(cplx{-dmr, y}), hg));
+  return cscale(faddeeva_upper(cplx{dmr, -y}), hg);
+}
+
+// ---------------------------------------------------------------------------
+// Model 2: mass x decay time, two real rates, per-event width s sigma_t
+// ---------------------------------------------------------------------------
+struct RateTerms {
+  double F, I;      // F(t), integral over [T_LO, T_HI]
+  double dlz, dls;  // d ln(F/I) / d rate, d ln(F/I) / d sigma
+};
+
+template <bool GRAD>
+__device__ __forceinline__ RateTerms rate_terms(double t, double rate, double h2, double eA, double eB,
+                                                double inv_rate, double sig, double s2, double inv_r2s,
+                                                const TimePoint& pt, const TimePoint& pa,
+                                                const TimePoint& pb, double dphi) {
+  RateTerms r;
+  const double e2 = exp(h2 * s2);
+  const double Ft = conv_real(t, rate, e2 * exp(-rate * t), pt, s2, inv_r2s);
+  const double Fa = conv_real(kTLo, rate, e2 * eA, pa, s2, inv_r2s);
+  const double Fb = conv_real(kTHi, rate, e2 * eB, pb, s2, inv_r2s);
+  r.F = Ft;
+  r.I = (dphi + Fa - Fb) * inv_rate;
+  if constexpr (GRAD) {
+    const double inv_sig = 1.0 / sig;
+    const double Gt = pt.g * kInvSqrt2Pi * inv_sig;
+    const double Ga = pa.g * kInvSqrt2Pi * inv_sig;
+    const double Gb = pb.g * kInvSqrt2Pi * inv_sig;
+    const double dzt = (s2 * rate - t) * Ft - s2 * Gt;
+    const double dza = (s2 * rate - kTLo) * Fa - s2 * Ga;
+    const double dzb = (s2 * rate - kTHi) * Fb - s2 * Gb;
+    const double sr = sig * rate;
+    const double dst = sr * rate * Ft - (sr + t * inv_sig) * Gt;
+    const double dsa = sr * rate * Fa - (sr + kTLo * inv_sig) * Ga;
+    const double dsb = sr * rate * Fb - (sr + kTHi * inv_sig) * Gb;
+    // d Phi(x)/d sigma = -(x / sigma) G_t(x)
+    const double dphis = -(kTHi * inv_sig) * Gb + (kTLo * inv_sig) * Ga;
+    const double dIz = (-r.I + dza - dzb) * inv_rate;
+    const double dIs = (dphis - dsb + dsa) * inv_rate;
+    const double iF = 1.0 / Ft, iI = 1.0 / r.I;
+    r.dlz = dzt * iF - dIz * iI;
+    r.dls = dst * iF - dIs * iI;
+  }
+  return r;
+}
+
+template <bool GRAD>
+__device__ __forceinline__ void event_masstime(const MassTimeConst& k, double m, double t, double sigt,
+                                               double w, double* acc) {
+  const double sig = k.s * sigt;
+  const double s2 = sig * sig;
+  const double inv_r2s = kInvSqrt2 / sig;
+  const TimePoint pt = time_point(t, k.gmax, s2, inv_r2s, 0.0);
+  const TimePoint pa = time_point(kTLo, k.gmax, s2, inv_r2s, 0.0);
+  const TimePoint pb = time_point(kTHi, k.gmax, s2, inv_r2s, 0.0);
+  // Phi(T_HI) - Phi(T_LO) = 1/2 [g_a erfcx(T_LO/(sqrt2 s)) - g_b erfcx(T_HI/(sqrt2 s))]
+  double dphi = 0.0;
+  if (pa.need) dphi += 0.5 * pa.g * erfcx_pos(kTLo * inv_r2s);
+  if (pb.need) dphi -= 0.5 * pb.g * erfcx_pos(kTHi * inv_r2s);
+  const RateTerms rs = rate_terms<GRAD>(t, k.gs, k.hs2, k.eAs, k.eBs, k.inv_gs, sig, s2, inv_r2s, pt, pa, pb, dphi);
+  const RateTerms rb = rate_terms<GRAD>(t, k.gb, k.hb2, k.eAb, k.eBb, k.inv_gb, sig, s2, inv_r2s, pt, pa, pb, dphi);
+  const double d = m - k.mu;
+  const double G = exp(-d * d * k.q);
+  const double E = exp(-k.lam * (m - kMLo));
+  const double hs = rs.F / rs.I, hb = rb.F / rb.I;
+  const double P = k.cS * G * hs + k.cB * E * hb;
+  acc[0] += w * log(P);
+  if constexpr (GRAD) {
+    const double iw = w / P;
+    const double ps = k.cS * G * hs * iw;  // w x signal posterior
+    const double pbk = k.cB * E * hb * iw;
+    acc[1] += G * hs * iw;
+    acc[2] += E * hb * iw;
+    acc[3] += ps * 2.0 * k.q * d;
+    acc[4] -= ps * d * d;
+    acc[5] -= pbk * (m - kMLo);
+    acc[6] += ps * rs.dlz;
+    acc[7] += pbk * rb.dlz;
+    acc[8] += sigt * (ps * rs.dls + pbk * rb.dls);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Model 3: angular x decay time x signal mass
+// ---------------------------------------------------------------------------
+struct Conv3 {
+  double FH, FL;
+  cplx Fc;
+  double g;
+};
+
+__device__ __forceinline__ Conv3 conv3(double tau, double mainH, double mainL, cplx mainC,
+                                       const AngTimeConst& k, double s2, double inv_r2s, double dmr) {
+  const TimePoint p = time_point(tau, k.gmax, s2, inv_r2s, dmr * dmr);
+  Conv3 r;
+  r.FH = conv_real(tau, k.gH, mainH, p, s2, inv_r2s);
+  r.FL = conv_real(tau, k.gL, mainL, p, s2, inv_r2s);
+  r.Fc = conv_cplx(tau, k.g, dmr, mainC, p, s2, inv_r2s);
+  r.g = p.g;
+  return r;
+}
+
+// d F / d z = (s^2 z - tau) F - s^2 G_t(tau)
+__device__ __forceinline__ double dconv_real(double tau, double rate, double F, double s2, double Gt) {
+  return (s2 * rate - tau) * F - s2 * Gt;
+}
+__device__ __forceinline__ cplx dconv_cplx(double tau, const AngTimeConst& k, cplx F, double s2, double Gt) {
+  const cplx a{s2 * k.g - tau, -s2 * k.dm};
+  const cplx r = cmul(a, F);
+  return cplx{r.re - s2 * Gt, r.im};
+}
+
+template <bool GRAD>
+__device__ __forceinline__ void event_angtime(const AngTimeConst& k, double ck, double cl, double ph,
+                                              double t, double sig, double m, double w, double* acc) {
+  // angular functions f_k(Omega)
+  const double sk2 = 1.0 - ck * ck, sl2 = 1.0 - cl * cl;
+  const double sk = sqrt(sk2), sl = sqrt(sl2);
+  double sph, cph;
+  sincos(ph, &sph, &cph);
+  const double s2k = 2.0 * sk * ck, s2l = 2.0 * sl * cl;
+  constexpr double c5 = 0.70710678118654752440;   // sqrt2/2
+  constexpr double c8 = 0.81649658092772603273;   // sqrt6/3
+  constexpr double c10 = 2.3094010767585030580;   // 4 sqrt3/3
+  double f[10];
+  f[0] = 2.0 * ck * ck * sl2;
+  f[1] = sk2 * (1.0 - sl2 * cph * cph);
+  f[2] = sk2 * (1.0 - sl2 * sph * sph);
+  f[3] = sk2 * sl2 * (2.0 * sph * cph);
+  f[4] = -c5 * s2k * s2l * cph;
+  f[5] = c5 * s2k * s2l * sph;
+  f[6] = (2.0 / 3.0) * sl2;
+  f[7] = -c8 * sk * s2l * cph;
+  f[8] = c8 * sk * s2l * sph;
+  f[9] = c10 * ck * sl2;
+
+  // time: per-event factors shared by t, T_LO and T_HI
+  const double s2 = sig * sig;
+  const double inv_r2s = kInvSqrt2 / sig;
+  const double dmr = k.dm * sig * kInvSqrt2;
+  const double eH2 = exp(k.hH2 * s2), eL2 = exp(k.hL2 * s2), ec2 = exp(k.hc2 * s2);
+  double sc, cc;
+  sincos(k.gdm * s2, &sc, &cc);
+  double st, ct;
+  sincos(k.dm * t, &st, &ct);
+  // exp(z^2 s^2/2 - z tau) for z = Gamma - i dm has phase dm (tau - Gamma s^2)
+  const double mt = ec2 * exp(-k.g * t);
+  const Conv3 Xt = conv3(t, eH2 * exp(-k.gH * t), eL2 * exp(-k.gL * t),
+                         cplx{mt * (ct * cc + st * sc), mt * (st * cc - ct * sc)}, k, s2, inv_r2s, dmr);
+  const double ma = ec2 * k.eAG, mb = ec2 * k.eBG;
+  const Conv3 Xa = conv3(kTLo, eH2 * k.eAH, eL2 * k.eAL,
+                         cplx{ma * (k.cA * cc + k.sA * sc), ma * (k.sA * cc - k.cA * sc)}, k, s2, inv_r2s, dmr);
+  const Conv3 Xb = conv3(kTHi, eH2 * k.eBH, eL2 * k.eBL,
+                         cplx{mb * (k.cB * cc + k.sB * sc), mb * (k.sB * cc - k.cB * sc)}, k, s2, inv_r2s, dmr);
+  double dphi = 0.0;
+  if (Xa.g != 0.0) dphi += 0.5 * Xa.g * erfcx_pos(kTLo * inv_r2s);
+  if (Xb.g != 0.0) dphi -= 0.5 * Xb.g * erfcx_pos(kTHi * inv_r2s);
+  const double IH = (dphi + Xa.FH - Xb.FH) * k.inv_gH;
+  const double IL = (dphi + Xa.FL - Xb.FL) * k.inv_gL;
+  const cplx Ic = cmul(cplx{dphi + Xa.Fc.re - Xb.Fc.re, Xa.Fc.im - Xb.Fc.im}, cplx{k.izr, k.izi});
+
+  const double T[4] = {0.5 * (Xt.FH + Xt.FL), 0.5 * (Xt.FH - Xt.FL), Xt.Fc.re, Xt.Fc.im};
+  const double I[4] = {0.5 * (IH + IL), 0.5 * (IH - IL), Ic.re, Ic.im};
+  double A[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    double s = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < 10; ++kk) s += f[kk] * k.C[kk][j];
+    A[j] = s;
+  }
+  const double num = A[0] * T[0] + A[1] * T[1] + A[2] * T[2] + A[3] * T[3];
+  const double den = k.D[0] * I[0] + k.D[1] * I[1] + k.D[2] * I[2] + k.D[3] * I[3];
+  const double d = m - k.mu;
+  acc[0] += w * (log(num / den) - d * d * k.q - k.lnNG);
+
+  if constexpr (GRAD) {
+    const double inum = w / num, iden = w / den;
+    double tau[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) tau[j] = T[j] * inum;
+#pragma unroll
+    for (int kk = 0; kk < 10; ++kk)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[1 + 4 * kk + j] += f[kk] * tau[j];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[41 + j] -= I[j] * iden;
+
+    const double inv_sig = 1.0 / sig;
+    const double Gt = Xt.g * kInvSqrt2Pi * inv_sig;
+    const double Ga = Xa.g * kInvSqrt2Pi * inv_sig;
+    const double Gb = Xb.g * kInvSqrt2Pi * inv_sig;
+    const double dFHt = dconv_real(t, k.gH, Xt.FH, s2, Gt);
+    const double dFLt = dconv_real(t, k.gL, Xt.FL, s2, Gt);
+    const cplx dFct = dconv_cplx(t, k, Xt.Fc, s2, Gt);
+    const double dIH = (-IH + dconv_real(kTLo, k.gH, Xa.FH, s2, Ga) - dconv_real(kTHi, k.gH, Xb.FH, s2, Gb)) * k.inv_gH;
+    const double dIL = (-IL + dconv_real(kTLo, k.gL, Xa.FL, s2, Ga) - dconv_real(kTHi, k.gL, Xb.FL, s2, Gb)) * k.inv_gL;
+    const cplx dFca = dconv_cplx(kTLo, k, Xa.Fc, s2, Ga);
+    const cplx dFcb = dconv_cplx(kTHi, k, Xb.Fc, s2, Gb);
+    const cplx dIc = cmul(cplx{-Ic.re + dFca.re - dFcb.re, -Ic.im + dFca.im - dFcb.im}, cplx{k.izr, k.izi});
+    acc[45] += 0.5 * (A[0] + A[1]) * dFHt * inum - 0.5 * (k.D[0] + k.D[1]) * dIH * iden;
+    acc[46] += 0.5 * (A[0] - A[1]) * dFLt * inum - 0.5 * (k.D[0] - k.D[1]) * dIL * iden;
+    acc[47] += (A[2] * dFct.re + A[3] * dFct.im) * inum - (k.D[2] * dIc.re + k.D[3] * dIc.im) * iden;
+    acc[48] += (A[2] * dFct.im - A[3] * dFct.re) * inum - (k.D[2] * dIc.im - k.D[3] * dIc.re) * iden;
+    acc[49] += w * 2.0 * k.q * d;
+    acc[50] -= w * d * d;
+    acc[51] += w;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Tile kernels
+// ---------------------------------------------------------------------------
+template <int MODEL>
+struct ModelTraits;
+template <>
+struct ModelTraits<1> {
+  using Const = MassConst;
+  static constexpr int kAcc = kAccMass;
+};
+template <>
+struct ModelTraits<2> {
+  using Const = MassTimeConst;
+  static constexpr int kAcc = kAccMassTime;
+};
+template <>
+struct ModelTraits<3> {
+  using Const = AngTimeConst;
+  static constexpr int kAcc = kAccAngTime;
+};
+
+template <int MODEL, bool GRAD>
+__device__ __forceinline__ void event(const typename ModelTraits<MODEL>::Const& k, const EventCols& cols,
+                                      int64_t i, double* acc) {
+  const double w = cols.w ? cols.w[i] : 1.0;
+  if constexpr (MODEL == 1) {
+    event_mass<GRAD>(k, cols.c[0][i], w, acc);
+  } else if constexpr (MODEL == 2) {
+    event_masstime<GRAD>(k, cols.c[0][i], cols.c[1][i], cols.c[2][i], w, acc);
+  } else {
+    event_angtime<GRAD>(k, cols.c[0][i], cols.c[1][i], cols.c[2][i], cols.c[3][i], cols.c[4][i],
+                        cols.c[5][i], w, acc);
+  }
+}
+
+// Grid-stride over canonical tiles; one partial (per component) per tile.
+template <int MODEL, bool GRAD>
+__global__ __launch_bounds__(kThreads) void k_nll_tiles(EventCols cols, typename ModelTraits<MODEL>::Const k,
+                                                        double* __restrict__ partials, int64_t n_tiles) {
+  constexpr int NACC = GRAD ? ModelTraits<MODEL>::kAcc : 1;
+  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    double acc[NACC];
+#pragma unroll
+    for (int c = 0; c < NACC; ++c) acc[c] = 0.0;
+    const int64_t base = tile * kTile + threadIdx.x;
+#pragma unroll
+    for (int e = 0; e < kEventsPerLane; ++e) {
+      const int64_t i = base + (int64_t)e * kThreads;
+      if (i < cols.n) event<MODEL, GRAD>(k, cols, i, acc);
+    }
+    tile_store<NACC>(acc, partials, tile, n_tiles);
+  }
+}
+
+}  // namespace ipx

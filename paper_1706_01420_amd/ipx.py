@@ -1,0 +1,220 @@
+"""Thin ctypes binding of libipx (include/ipx.h): argument marshalling only.
+
+Every function keeps the C name.  Device work happens in the library's HIP
+kernels; nothing here computes a likelihood.  Importing this module imports
+torch first, so that libipx binds to the HIP runtime torch has already mapped
+(one runtime per process; torch tensors and streams can then be passed in).
+If libipx.so is missing the import fails: there is no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch  # noqa: F401  (maps torch's HIP runtime before libipx is loaded)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libipx.so")
+
+IPX_OK = 0
+IPX_EINVAL = -1
+IPX_ENOMEM = -2
+IPX_EDEVICE = -3
+IPX_EBUSY = -4
+IPX_ENOTFOUND = -5
+IPX_ETIMEOUT = -6
+IPX_EDOMAIN = -7
+STATUS_NAMES = {0: "IPX_OK", -1: "IPX_EINVAL", -2: "IPX_ENOMEM", -3: "IPX_EDEVICE", -4: "IPX_EBUSY",
+                -5: "IPX_ENOTFOUND", -6: "IPX_ETIMEOUT", -7: "IPX_EDOMAIN"}
+
+IPX_MODEL_MASS = 1
+IPX_MODEL_MASSTIME = 2
+IPX_MODEL_ANGTIME = 3
+
+IPX_COPY_HOST = 0
+IPX_COPY_DEVICE = 1
+IPX_BORROW_DEVICE = 2
+
+_c_double_p = ctypes.POINTER(ctypes.c_double)
+_c_void_pp = ctypes.POINTER(ctypes.c_void_p)
+
+# (name, restype, argtypes) of every exported function
+_SIGNATURES = [
+    ("ipx_create", ctypes.c_int, [ctypes.c_int, _c_void_pp]),
+    ("ipx_destroy", None, [ctypes.c_void_p]),
+    ("ipx_last_error", ctypes.c_char_p, []),
+    ("ipx_model_nparams", ctypes.c_int, [ctypes.c_int]),
+    ("ipx_model_ncols", ctypes.c_int, [ctypes.c_int]),
+    ("ipx_dataset_create", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+      ctypes.c_void_p, ctypes.c_uint, _c_void_pp]),
+    ("ipx_dataset_destroy", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("ipx_dataset_bytes", ctypes.c_size_t, [ctypes.c_void_p]),
+    ("ipx_dataset_size", ctypes.c_int64, [ctypes.c_void_p]),
+    ("ipx_dataset_model", ctypes.c_int, [ctypes.c_void_p]),
+    ("ipx_dataset_column", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_void_pp]),
+    ("nll_eval", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_void_p, _c_double_p, ctypes.c_int, _c_double_p, ctypes.c_void_p]),
+    ("nll_grad", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_void_p, _c_double_p, ctypes.c_int, _c_double_p, _c_double_p, ctypes.c_void_p]),
+    ("ipx_timing_enable", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    ("ipx_timing_read", ctypes.c_int,
+     [ctypes.c_void_p, _c_double_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]),
+]
+EXPORTED = [s[0] for s in _SIGNATURES]
+
+
+class IpxError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), message))
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libipx.so is not built (python -m paper_1706_01420_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, res, args in _SIGNATURES:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def _check(status):
+    if status != IPX_OK:
+        raise IpxError(status, _lib.ipx_last_error().decode())
+    return status
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream  # torch.cuda.Stream
+
+
+def _dbl(a):
+    return a.ctypes.data_as(_c_double_p)
+
+
+# ---------------------------------------------------------------------------
+# C functions (same names)
+# ---------------------------------------------------------------------------
+def ipx_create(device=0):
+    h = ctypes.c_void_p()
+    _check(_lib.ipx_create(int(device), ctypes.byref(h)))
+    return h
+
+
+def ipx_destroy(ctx):
+    _lib.ipx_destroy(ctx)
+
+
+def ipx_last_error():
+    return _lib.ipx_last_error().decode()
+
+
+def ipx_model_nparams(model):
+    return _lib.ipx_model_nparams(int(model))
+
+
+def ipx_model_ncols(model):
+    return _lib.ipx_model_ncols(int(model))
+
+
+def ipx_dataset_create(ctx, model, cols, w=None, flags=IPX_COPY_HOST):
+    """cols: list of 1-D float64 arrays (host numpy arrays for IPX_COPY_HOST,
+    CUDA torch tensors for the device flags)."""
+    ncols = len(cols)
+    keep = []
+    ptrs = (ctypes.c_void_p * max(ncols, 1))()
+    n = None
+    for i, c in enumerate(cols):
+        if flags == IPX_COPY_HOST:
+            c = np.ascontiguousarray(c, dtype=np.float64)
+            keep.append(c)
+            ptrs[i] = c.ctypes.data
+            length = c.shape[0]
+        else:
+            if not (isinstance(c, torch.Tensor) and c.is_cuda and c.dtype == torch.float64 and c.is_contiguous()):
+                raise TypeError("device columns must be contiguous float64 CUDA tensors")
+            ptrs[i] = c.data_ptr()
+            length = c.shape[0]
+        if n is None:
+            n = length
+        elif n != length:
+            raise ValueError("columns differ in length")
+    wp = None
+    if w is not None:
+        if flags == IPX_COPY_HOST:
+            w = np.ascontiguousarray(w, dtype=np.float64)
+            keep.append(w)
+            wp = w.ctypes.data
+        else:
+            wp = w.data_ptr()
+        if w.shape[0] != n:
+            raise ValueError("weights differ in length")
+    h = ctypes.c_void_p()
+    _check(_lib.ipx_dataset_create(ctx, int(model), int(n or 0), ptrs, ncols, wp, int(flags), ctypes.byref(h)))
+    return h
+
+
+def ipx_dataset_destroy(ctx, ds):
+    _check(_lib.ipx_dataset_destroy(ctx, ds))
+
+
+def ipx_dataset_bytes(ds):
+    return _lib.ipx_dataset_bytes(ds)
+
+
+def ipx_dataset_size(ds):
+    return _lib.ipx_dataset_size(ds)
+
+
+def ipx_dataset_model(ds):
+    return _lib.ipx_dataset_model(ds)
+
+
+def ipx_dataset_column(ds, col):
+    p = ctypes.c_void_p()
+    _check(_lib.ipx_dataset_column(ds, int(col), ctypes.byref(p)))
+    return p.value
+
+
+def nll_eval(ctx, ds, theta, stream=None):
+    """-sum w ln P at theta; +inf for IPX_EDOMAIN (parameters outside the domain
+    or a non-finite likelihood), an exception for any other error."""
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    out = ctypes.c_double()
+    st = _lib.nll_eval(ctx, ds, _dbl(th), th.shape[0], ctypes.byref(out), _stream_ptr(stream))
+    if st == IPX_EDOMAIN:
+        return float("inf")
+    _check(st)
+    return out.value
+
+
+def nll_grad(ctx, ds, theta, stream=None):
+    """(NLL, dNLL/dtheta); (+inf, NaN) for IPX_EDOMAIN."""
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    out = ctypes.c_double()
+    g = np.empty(th.shape[0])
+    st = _lib.nll_grad(ctx, ds, _dbl(th), th.shape[0], ctypes.byref(out), _dbl(g), _stream_ptr(stream))
+    if st == IPX_EDOMAIN:
+        return float("inf"), np.full(th.shape[0], np.nan)
+    _check(st)
+    return out.value, g
+
+
+def ipx_timing_enable(ctx, enable=True):
+    _check(_lib.ipx_timing_enable(ctx, 1 if enable else 0))
+
+
+def ipx_timing_read(ctx, reset=False):
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(_lib.ipx_timing_read(ctx, ctypes.byref(ms), ctypes.byref(n), 1 if reset else 0))
+    return ms.value, n.value
