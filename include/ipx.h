@@ -86,6 +86,7 @@ typedef enum {
 #define IPX_COPY_HOST 0u     /* cols/w are host pointers; data are copied to the device */
 #define IPX_COPY_DEVICE 1u   /* cols/w are device pointers; data are copied device-to-device */
 #define IPX_BORROW_DEVICE 2u /* cols/w are device pointers used in place; the caller keeps them alive */
+#define IPX_KEEP_ORDER 4u    /* or-ed with a COPY flag: store events in the given order */
 
 typedef struct ipx_ctx ipx_ctx;
 typedef struct ipx_dataset ipx_dataset;
@@ -106,7 +107,10 @@ IPX_API int ipx_model_ncols(int model);
  *          model's column order (host or device memory per `flags`).
  *   w:     optional per-event weights (n doubles, same memory kind), NULL for 1.
  * With IPX_COPY_*, the library owns the device copy (one allocation, columns
- * padded to 256-byte boundaries).  The dataset also holds the scratch for its
+ * padded to 256-byte boundaries); the models with a decay time store it sorted
+ * by t (unless IPX_KEEP_ORDER), which keeps the waves that need the
+ * small-t/sigma resolution correction together.  The NLL is a sum over events,
+ * so the order changes only its rounding.  The dataset also holds the scratch for its
  * reduction partials, so calls on different datasets may run concurrently on
  * different streams; calls on one dataset must not overlap.
  */
@@ -120,6 +124,12 @@ IPX_API int ipx_dataset_model(const ipx_dataset *ds);
 /* Device pointer of column `col` (0..ncols-1) or of the weights (col = ncols,
  * NULL when unweighted). */
 IPX_API ipx_status ipx_dataset_column(const ipx_dataset *ds, int col, const double **dev_ptr);
+/* Copy events [offset, offset + count) of column `col` (or of the weights,
+ * col = ncols) to host memory `host` (count doubles, caller-owned).  Events
+ * are in storage order (sorted by t for the time models unless
+ * IPX_KEEP_ORDER).  Synchronous. */
+IPX_API ipx_status ipx_dataset_read(ipx_ctx *ctx, const ipx_dataset *ds, int col, int64_t offset, int64_t count,
+                                    double *host);
 
 /*
  * NLL of the dataset at theta (np = ipx_model_nparams(model) doubles).
@@ -141,6 +151,56 @@ IPX_API ipx_status nll_eval(ipx_ctx *ctx, const ipx_dataset *ds, const double *t
  */
 IPX_API ipx_status nll_grad(ipx_ctx *ctx, const ipx_dataset *ds, const double *theta, int np, double *nll,
                     double *grad, void *stream);
+
+/*
+ * Batched evaluation (many datasets of one model, each at its own theta, in
+ * one fused launch; the paper's pseudo-experiment studies fit hundreds of toys
+ * with the same likelihood).  A plan fixes the list of datasets (all of the
+ * same model, each appearing once) and owns the staging buffers; its first
+ * evaluation in each mode (NLL only / NLL + gradient) is captured into a HIP
+ * graph that later calls replay.  Each dataset keeps its canonical tiles and
+ * partial buffers, so its result is bitwise the same as nll_eval/nll_grad on
+ * the dataset alone, whatever else is in the batch.
+ *   theta:  nb x np doubles (row j for dataset j), host memory.
+ *   active: nb flags (nullable = all active); inactive entries are skipped and
+ *           their outputs left untouched.
+ *   nll:    nb doubles; grad: nb x np doubles or NULL for NLL only.
+ * Entries outside the domain or with a non-finite likelihood get +inf (and
+ * NaN gradients); the call then returns IPX_EDOMAIN after filling every other
+ * entry.  Plans must not be used concurrently with each other or with plain
+ * calls on the same datasets.
+ */
+typedef struct ipx_plan ipx_plan;
+IPX_API ipx_status ipx_plan_create(ipx_ctx *ctx, int nb, ipx_dataset *const *ds, ipx_plan **out);
+IPX_API void ipx_plan_destroy(ipx_plan *plan);
+IPX_API ipx_status nll_eval_batch(ipx_ctx *ctx, ipx_plan *plan, const double *theta, const unsigned char *active,
+                                  double *nll, double *grad, void *stream);
+
+/*
+ * Unbinned toy generation by accept-reject (Example 5 of the paper: toys
+ * generated on the device by accept-reject from a counter-based stream).
+ * Generates n events of `model` at theta_gen into a new dataset (*out, owned
+ * by the caller, destroyed with ipx_dataset_destroy).
+ *   Stream: Philox4x64-10, key (seed, toy_id), counter (c, b, model, 0) for
+ *   candidate c and block b (1, 2, 3 blocks per candidate for models 1, 2, 3);
+ *   uniforms ((word >> 12) + 0.5) 2^-52.  Candidate c is accepted on its own
+ *   words; the output holds the first n accepted candidates (increasing c),
+ *   sorted by decay time for models 2 and 3 unless flags has IPX_KEEP_ORDER.
+ *   Model 3 also draws weights 0.8 + 0.2 u (the workload's efficiency weights).
+ *   Each model's recipe (proposals, bounds, acceptance ratios) is documented
+ *   in the library source; conditional on sigma_t the accepted events follow
+ *   the model's PDF exactly.
+ * stats (nullable): n_candidates = index of the n-th accepted candidate + 1;
+ * n_violations = candidates whose acceptance ratio exceeded the bound (0 for
+ * an exact sample).
+ */
+typedef struct {
+  uint64_t n_candidates;
+  uint64_t n_violations;
+} ipx_toy_stats;
+IPX_API ipx_status toy_generate(ipx_ctx *ctx, int model, const double *theta_gen, int np, uint64_t seed,
+                                uint64_t toy_id, int64_t n, unsigned flags, ipx_dataset **out,
+                                ipx_toy_stats *stats);
 
 /*
  * Timing of the dominant kernel of nll_eval/nll_grad, measured with HIP events

@@ -1,0 +1,139 @@
+// Batched evaluation: one launch evaluates many datasets of one model, each at
+// its own parameter vector (the paper's Examples 4-5: hundreds of
+// pseudo-experiments generated and fitted; here their likelihood calls are
+// fused).  Every dataset keeps its own canonical tiles and partial buffers,
+// and each tile runs the same per-event code as the single-dataset kernels,
+// so a dataset's result does not depend on what else is in the batch.
+//
+// Work decomposition: a table of (segment, local tile) pairs covers the
+// active datasets; workgroups stride over it.  Per-segment constants live in
+// device memory (read with uniform addresses, i.e. scalar loads).
+#pragma once
+
+#include "ipx_kernels.h"
+
+namespace ipx {
+
+struct SegInfo {
+  EventCols cols;
+  double* partials;      // n_tiles x kAccMax, component-major
+  double* tau;           // angular gradient scratch (4 x tau_stride)
+  int64_t tau_stride;
+  int64_t n_tiles;
+  int64_t n_tiles_outer;
+};
+
+struct TileRef {
+  int seg;
+  int tile;
+};
+
+// Models 1 and 2.
+template <int MODEL, bool GRAD>
+__global__ __launch_bounds__(kThreads) void k_nll_batch(const SegInfo* __restrict__ segs,
+                                                        const TileRef* __restrict__ tiles, int64_t n_tiles,
+                                                        const typename ModelTraits<MODEL>::Const* __restrict__ consts,
+                                                        const unsigned char* __restrict__ active) {
+  constexpr int NACC = GRAD ? ModelTraits<MODEL>::kAcc : 1;
+  for (int64_t g = blockIdx.x; g < n_tiles; g += gridDim.x) {
+    const TileRef tr = tiles[g];
+    if (!active[tr.seg]) continue;
+    const SegInfo& S = segs[tr.seg];
+    const typename ModelTraits<MODEL>::Const k = consts[tr.seg];
+    double acc[NACC];
+#pragma unroll
+    for (int c = 0; c < NACC; ++c) acc[c] = 0.0;
+    const int64_t base = (int64_t)tr.tile * kTile + threadIdx.x;
+#pragma unroll 1
+    for (int e = 0; e < kEventsPerLane; ++e) {
+      const int64_t i = base + (int64_t)e * kThreads;
+      if (i < S.cols.n) event<MODEL, GRAD>(k, S.cols, i, acc);
+    }
+    tile_store<NACC>(acc, S.partials, tr.tile, S.n_tiles);
+  }
+}
+
+// Angular model: per-event kernel.
+template <bool GRAD>
+__global__ __launch_bounds__(kThreads) void k_angtime_batch(const SegInfo* __restrict__ segs,
+                                                            const TileRef* __restrict__ tiles, int64_t n_tiles,
+                                                            const AngTimeConst* __restrict__ consts,
+                                                            const unsigned char* __restrict__ active) {
+  __shared__ double sC[40];
+  constexpr int NACC = GRAD ? kAngInner : 1;
+  for (int64_t g = blockIdx.x; g < n_tiles; g += gridDim.x) {
+    const TileRef tr = tiles[g];
+    if (!active[tr.seg]) continue;
+    const SegInfo& S = segs[tr.seg];
+    const AngTimeConst& k = consts[tr.seg];
+    if (threadIdx.x < 40) sC[threadIdx.x] = (&k.C[0][0])[threadIdx.x];
+    __syncthreads();
+    double acc[NACC];
+#pragma unroll
+    for (int c = 0; c < NACC; ++c) acc[c] = 0.0;
+    const int64_t base = (int64_t)tr.tile * kTile + threadIdx.x;
+#pragma unroll 1
+    for (int e = 0; e < kEventsPerLane; ++e) {
+      const int64_t i = base + (int64_t)e * kThreads;
+      asm volatile("" ::: "memory");
+      if (i < S.cols.n) {
+        const EventCols& cl = S.cols;
+        const double w = cl.w ? cl.w[i] : 1.0;
+        event_angtime<GRAD>(k, sC, cl.c[0][i], cl.c[1][i], cl.c[2][i], cl.c[3][i], cl.c[4][i], cl.c[5][i], w, acc,
+                            S.tau, S.tau_stride, i);
+      }
+    }
+    tile_store<NACC>(acc, S.partials, tr.tile, S.n_tiles);
+  }
+}
+
+// Angular model: coefficient adjoints over the outer tiles of each segment.
+__global__ __launch_bounds__(kThreads) void k_angtime_outer_batch(const SegInfo* __restrict__ segs,
+                                                                  const TileRef* __restrict__ tiles,
+                                                                  int64_t n_tiles,
+                                                                  const unsigned char* __restrict__ active) {
+  for (int64_t g = blockIdx.x; g < n_tiles; g += gridDim.x) {
+    const TileRef tr = tiles[g];
+    if (!active[tr.seg]) continue;
+    const SegInfo& S = segs[tr.seg];
+    double acc[kAngOuter];
+#pragma unroll
+    for (int c = 0; c < kAngOuter; ++c) acc[c] = 0.0;
+    const int64_t base = (int64_t)tr.tile * kOuterTile + threadIdx.x;
+#pragma unroll 2
+    for (int e = 0; e < kOuterEventsPerLane; ++e) {
+      const int64_t i = base + (int64_t)e * kThreads;
+      if (i < S.cols.n) {
+        double f[10];
+        angular_functions(S.cols.c[0][i], S.cols.c[1][i], S.cols.c[2][i], f);
+        const double* tau = S.tau;
+        const int64_t ts = S.tau_stride;
+        const double t0 = tau[i], t1 = tau[ts + i], t2 = tau[2 * ts + i], t3 = tau[3 * ts + i];
+#pragma unroll
+        for (int kk = 0; kk < 10; ++kk) {
+          acc[4 * kk + 0] += f[kk] * t0;
+          acc[4 * kk + 1] += f[kk] * t1;
+          acc[4 * kk + 2] += f[kk] * t2;
+          acc[4 * kk + 3] += f[kk] * t3;
+        }
+      }
+    }
+    tile_store<kAngOuter>(acc, S.partials + kAngOuter0 * S.n_tiles, tr.tile, S.n_tiles);
+  }
+}
+
+// out[seg * kAccMax + c] = sum of the segment's tile partials of component c;
+// grid (nacc, n_segments).  Components >= split use the outer tile count.
+__global__ __launch_bounds__(kThreads) void k_reduce_batch(const SegInfo* __restrict__ segs,
+                                                           const unsigned char* __restrict__ active, int split,
+                                                           double* __restrict__ out) {
+  const int seg = blockIdx.y;
+  if (!active[seg]) return;
+  const int c = blockIdx.x;
+  const SegInfo& S = segs[seg];
+  const int64_t nt = c < split ? S.n_tiles : S.n_tiles_outer;
+  const double total = reduce_component(S.partials + (int64_t)c * S.n_tiles, nt);
+  if (threadIdx.x == 0) out[(int64_t)seg * kAccMax + c] = total;
+}
+
+}  // namespace ipx

@@ -250,19 +250,21 @@ inline AngTimeHoist hoist_angtime(const double* th) {
 }
 inline void grad_angtime(const AngTimeHoist& h, const double* th, const double* a, double* g) {
   // total adjoint of C_kj: direct plus through D_j = sum_k xi_k C_kj
+  // layout: a[0] l, a[1..4] dD_j, a[5..8] d(Gamma_H, Gamma_L, Re z, dm),
+  // a[9] dmu, a[10] dq, a[11] sum w, a[12 + 4k + j] dC_kj
   double phys[7] = {0, 0, 0, 0, 0, 0, 0};
   for (int kk = 0; kk < 10; ++kk)
     for (int j = 0; j < 4; ++j) {
-      const double adj = a[1 + 4 * kk + j] + kXi[kk] * a[41 + j];
+      const double adj = a[12 + 4 * kk + j] + kXi[kk] * a[1 + j];
       for (int p = 0; p < 7; ++p) phys[p] += adj * h.C[kk][j].d[p];
     }
-  const double dG = a[45] + a[46] + a[47];
-  const double dDG = -0.5 * a[45] + 0.5 * a[46];
-  const double dDM = a[48];
+  const double dG = a[5] + a[6] + a[7];
+  const double dDG = -0.5 * a[5] + 0.5 * a[6];
+  const double dDM = a[8];
   const double sig = th[11];
   const double NG = h.ng.N;
-  const double dmu = a[49] - a[51] * h.ng.dmu / NG;
-  const double dsig = a[50] * (-1.0 / (sig * sig * sig)) - a[51] * h.ng.dsig / NG;
+  const double dmu = a[9] - a[11] * h.ng.dmu / NG;
+  const double dsig = a[10] * (-1.0 / (sig * sig * sig)) - a[11] * h.ng.dsig / NG;
   const double dl[12] = {phys[0], phys[1], phys[2], phys[3], phys[4], phys[5], dG, dDG, dDM, phys[6], dmu, dsig};
   for (int i = 0; i < 12; ++i) g[i] = -dl[i];
 }

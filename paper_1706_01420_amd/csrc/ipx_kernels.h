@@ -43,18 +43,26 @@ __device__ __forceinline__ void tile_store(const double (&acc)[NACC], double* __
   __syncthreads();
 }
 
-// out[c] = sum over tiles of partials[c][tile], one workgroup per component.
-__global__ __launch_bounds__(kThreads) void k_reduce_tiles(const double* __restrict__ partials,
-                                                           int64_t n_tiles, double* __restrict__ out) {
-  const int c = blockIdx.x;
-  const double* p = partials + (int64_t)c * n_tiles;
+// Sum of nt tile partials in a fixed order: lane-sequential over a stride of
+// 256, wave butterfly, waves in order.  Used by every reduction of partials.
+__device__ __forceinline__ double reduce_component(const double* __restrict__ p, int64_t nt) {
   double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n_tiles; i += kThreads) s += p[i];
+  for (int64_t i = threadIdx.x; i < nt; i += kThreads) s += p[i];
   __shared__ double lds[kThreads / 64];
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) out[c] = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+  return (lds[0] + lds[1]) + (lds[2] + lds[3]);
+}
+
+// out[c] = sum over tiles of partials[c * stride + tile], one workgroup per
+// component; components below `split` have n_tiles tiles, the others n_tiles2.
+__global__ __launch_bounds__(kThreads) void k_reduce_tiles(const double* __restrict__ partials, int64_t stride,
+                                                           int64_t n_tiles, int split, int64_t n_tiles2,
+                                                           double* __restrict__ out) {
+  const int c = blockIdx.x;
+  const double total = reduce_component(partials + (int64_t)c * stride, c < split ? n_tiles : n_tiles2);
+  if (threadIdx.x == 0) out[c] = total;
 }
 
 // ---------------------------------------------------------------------------
@@ -104,8 +112,8 @@ __device__ __forceinline__ double conv_real(double tau, double rate, double main
                                             double s2, double inv_r2s) {
   if (!p.need) return main;
   const double y = (tau - rate * s2) * inv_r2s;  // -Im u
-  const double hg = 0.5 * p.g;
-  return y >= 0.0 ? main - hg * erfcx_pos(y) : hg * erfcx_pos(-y);
+  const double c = 0.5 * p.g * erfcx_pos(fabs(y));
+  return y >= 0.0 ? main - c : c;
 }
 
 // complex rate Gamma - i dm; dmr = dm s / sqrt2 = Re u
@@ -113,9 +121,10 @@ __device__ __forceinline__ cplx conv_cplx(double tau, double rate, double dmr, c
                                           double s2, double inv_r2s) {
   if (!p.need) return main;
   const double y = (tau - rate * s2) * inv_r2s;
-  const double hg = 0.5 * p.g;
-  if (y >= 0.0) return csub(main, cscale(faddeeva_upper(cplx{-dmr, y}), hg));
-  return cscale(faddeeva_upper(cplx{dmr, -y}), hg);
+  // w(-u) for y >= 0 (then F = main - g w(-u)/2), w(u) otherwise (F = g w(u)/2)
+  const bool lower = y >= 0.0;
+  const cplx c = cscale(faddeeva_upper(lower ? cplx{-dmr, y} : cplx{dmr, -y}), 0.5 * p.g);
+  return lower ? csub(main, c) : c;
 }
 
 // ---------------------------------------------------------------------------
@@ -139,7 +148,7 @@ __device__ __forceinline__ RateTerms rate_terms(double t, double rate, double h2
   r.F = Ft;
   r.I = (dphi + Fa - Fb) * inv_rate;
   if constexpr (GRAD) {
-    const double inv_sig = 1.0 / sig;
+    const double inv_sig = rcp(sig);
     const double Gt = pt.g * kInvSqrt2Pi * inv_sig;
     const double Ga = pa.g * kInvSqrt2Pi * inv_sig;
     const double Gb = pb.g * kInvSqrt2Pi * inv_sig;
@@ -154,7 +163,7 @@ __device__ __forceinline__ RateTerms rate_terms(double t, double rate, double h2
     const double dphis = -(kTHi * inv_sig) * Gb + (kTLo * inv_sig) * Ga;
     const double dIz = (-r.I + dza - dzb) * inv_rate;
     const double dIs = (dphis - dsb + dsa) * inv_rate;
-    const double iF = 1.0 / Ft, iI = 1.0 / r.I;
+    const double iF = rcp(Ft), iI = rcp(r.I);
     r.dlz = dzt * iF - dIz * iI;
     r.dls = dst * iF - dIs * iI;
   }
@@ -166,7 +175,7 @@ __device__ __forceinline__ void event_masstime(const MassTimeConst& k, double m,
                                                double w, double* acc) {
   const double sig = k.s * sigt;
   const double s2 = sig * sig;
-  const double inv_r2s = kInvSqrt2 / sig;
+  const double inv_r2s = kInvSqrt2 * rcp(sig);
   const TimePoint pt = time_point(t, k.gmax, s2, inv_r2s, 0.0);
   const TimePoint pa = time_point(kTLo, k.gmax, s2, inv_r2s, 0.0);
   const TimePoint pb = time_point(kTHi, k.gmax, s2, inv_r2s, 0.0);
@@ -179,11 +188,11 @@ __device__ __forceinline__ void event_masstime(const MassTimeConst& k, double m,
   const double d = m - k.mu;
   const double G = exp(-d * d * k.q);
   const double E = exp(-k.lam * (m - kMLo));
-  const double hs = rs.F / rs.I, hb = rb.F / rb.I;
+  const double hs = rs.F * rcp(rs.I), hb = rb.F * rcp(rb.I);
   const double P = k.cS * G * hs + k.cB * E * hb;
   acc[0] += w * log(P);
   if constexpr (GRAD) {
-    const double iw = w / P;
+    const double iw = w * rcp(P);
     const double ps = k.cS * G * hs * iw;  // w x signal posterior
     const double pbk = k.cB * E * hb * iw;
     acc[1] += G * hs * iw;
@@ -227,10 +236,8 @@ __device__ __forceinline__ cplx dconv_cplx(double tau, const AngTimeConst& k, cp
   return cplx{r.re - s2 * Gt, r.im};
 }
 
-template <bool GRAD>
-__device__ __forceinline__ void event_angtime(const AngTimeConst& k, double ck, double cl, double ph,
-                                              double t, double sig, double m, double w, double* acc) {
-  // angular functions f_k(Omega)
+// The ten angular functions f_k(Omega).
+__device__ __forceinline__ void angular_functions(double ck, double cl, double ph, double* f) {
   const double sk2 = 1.0 - ck * ck, sl2 = 1.0 - cl * cl;
   const double sk = sqrt(sk2), sl = sqrt(sl2);
   double sph, cph;
@@ -239,7 +246,6 @@ __device__ __forceinline__ void event_angtime(const AngTimeConst& k, double ck, 
   constexpr double c5 = 0.70710678118654752440;   // sqrt2/2
   constexpr double c8 = 0.81649658092772603273;   // sqrt6/3
   constexpr double c10 = 2.3094010767585030580;   // 4 sqrt3/3
-  double f[10];
   f[0] = 2.0 * ck * ck * sl2;
   f[1] = sk2 * (1.0 - sl2 * cph * cph);
   f[2] = sk2 * (1.0 - sl2 * sph * sph);
@@ -250,10 +256,27 @@ __device__ __forceinline__ void event_angtime(const AngTimeConst& k, double ck, 
   f[7] = -c8 * sk * s2l * cph;
   f[8] = c8 * sk * s2l * sph;
   f[9] = c10 * ck * sl2;
+}
 
+// Accumulator layout of the angular adjoint kernel (the 40 coefficient
+// adjoints come from k_angtime_outer at components kAngOuter0 + 4k + j).
+constexpr int kAngInner = 12;   // l, dD[4], dgH, dgL, dzr, ddm, dmu, dq, sum_w
+constexpr int kAngOuter0 = 12;
+constexpr int kAngOuter = 40;
+constexpr int kOuterEventsPerLane = 16;
+constexpr int kOuterTile = kThreads * kOuterEventsPerLane;
+
+// One event.  C is the coefficient table in LDS (row-major 10 x 4).  For the
+// gradient, writes tau_j = w T_j / num to tau[j * tau_stride + i].
+template <bool GRAD>
+__device__ __forceinline__ void event_angtime(const AngTimeConst& k, const double* __restrict__ C,
+                                              double ck, double cl, double ph, double t, double sig,
+                                              double m, double w, double* acc, double* __restrict__ tau,
+                                              int64_t tau_stride, int64_t i) {
   // time: per-event factors shared by t, T_LO and T_HI
   const double s2 = sig * sig;
-  const double inv_r2s = kInvSqrt2 / sig;
+  const double inv_sig = rcp(sig);
+  const double inv_r2s = kInvSqrt2 * inv_sig;
   const double dmr = k.dm * sig * kInvSqrt2;
   const double eH2 = exp(k.hH2 * s2), eL2 = exp(k.hL2 * s2), ec2 = exp(k.hc2 * s2);
   double sc, cc;
@@ -275,35 +298,28 @@ __device__ __forceinline__ void event_angtime(const AngTimeConst& k, double ck, 
   const double IH = (dphi + Xa.FH - Xb.FH) * k.inv_gH;
   const double IL = (dphi + Xa.FL - Xb.FL) * k.inv_gL;
   const cplx Ic = cmul(cplx{dphi + Xa.Fc.re - Xb.Fc.re, Xa.Fc.im - Xb.Fc.im}, cplx{k.izr, k.izi});
-
   const double T[4] = {0.5 * (Xt.FH + Xt.FL), 0.5 * (Xt.FH - Xt.FL), Xt.Fc.re, Xt.Fc.im};
   const double I[4] = {0.5 * (IH + IL), 0.5 * (IH - IL), Ic.re, Ic.im};
-  double A[4];
+
+  // angular part: A_j = sum_k f_k C_kj
+  double f[10];
+  angular_functions(ck, cl, ph, f);
+  double A[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    double s = 0.0;
+  for (int kk = 0; kk < 10; ++kk)
 #pragma unroll
-    for (int kk = 0; kk < 10; ++kk) s += f[kk] * k.C[kk][j];
-    A[j] = s;
-  }
+    for (int j = 0; j < 4; ++j) A[j] += f[kk] * C[4 * kk + j];
   const double num = A[0] * T[0] + A[1] * T[1] + A[2] * T[2] + A[3] * T[3];
   const double den = k.D[0] * I[0] + k.D[1] * I[1] + k.D[2] * I[2] + k.D[3] * I[3];
   const double d = m - k.mu;
-  acc[0] += w * (log(num / den) - d * d * k.q - k.lnNG);
+  acc[0] += w * (log(num * rcp(den)) - d * d * k.q - k.lnNG);
 
   if constexpr (GRAD) {
-    const double inum = w / num, iden = w / den;
-    double tau[4];
+    const double inum = w * rcp(num), iden = w * rcp(den);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) tau[j] = T[j] * inum;
+    for (int j = 0; j < 4; ++j) tau[j * tau_stride + i] = T[j] * inum;
 #pragma unroll
-    for (int kk = 0; kk < 10; ++kk)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[1 + 4 * kk + j] += f[kk] * tau[j];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[41 + j] -= I[j] * iden;
-
-    const double inv_sig = 1.0 / sig;
+    for (int j = 0; j < 4; ++j) acc[1 + j] -= I[j] * iden;
     const double Gt = Xt.g * kInvSqrt2Pi * inv_sig;
     const double Ga = Xa.g * kInvSqrt2Pi * inv_sig;
     const double Gb = Xb.g * kInvSqrt2Pi * inv_sig;
@@ -315,13 +331,75 @@ __device__ __forceinline__ void event_angtime(const AngTimeConst& k, double ck, 
     const cplx dFca = dconv_cplx(kTLo, k, Xa.Fc, s2, Ga);
     const cplx dFcb = dconv_cplx(kTHi, k, Xb.Fc, s2, Gb);
     const cplx dIc = cmul(cplx{-Ic.re + dFca.re - dFcb.re, -Ic.im + dFca.im - dFcb.im}, cplx{k.izr, k.izi});
-    acc[45] += 0.5 * (A[0] + A[1]) * dFHt * inum - 0.5 * (k.D[0] + k.D[1]) * dIH * iden;
-    acc[46] += 0.5 * (A[0] - A[1]) * dFLt * inum - 0.5 * (k.D[0] - k.D[1]) * dIL * iden;
-    acc[47] += (A[2] * dFct.re + A[3] * dFct.im) * inum - (k.D[2] * dIc.re + k.D[3] * dIc.im) * iden;
-    acc[48] += (A[2] * dFct.im - A[3] * dFct.re) * inum - (k.D[2] * dIc.im - k.D[3] * dIc.re) * iden;
-    acc[49] += w * 2.0 * k.q * d;
-    acc[50] -= w * d * d;
-    acc[51] += w;
+    acc[5] += 0.5 * (A[0] + A[1]) * dFHt * inum - 0.5 * (k.D[0] + k.D[1]) * dIH * iden;
+    acc[6] += 0.5 * (A[0] - A[1]) * dFLt * inum - 0.5 * (k.D[0] - k.D[1]) * dIL * iden;
+    acc[7] += (A[2] * dFct.re + A[3] * dFct.im) * inum - (k.D[2] * dIc.re + k.D[3] * dIc.im) * iden;
+    acc[8] += (A[2] * dFct.im - A[3] * dFct.re) * inum - (k.D[2] * dIc.im - k.D[3] * dIc.re) * iden;
+    acc[9] += w * 2.0 * k.q * d;
+    acc[10] -= w * d * d;
+    acc[11] += w;
+  }
+}
+
+// Per-event kernel of the angular model (NLL, and for GRAD the 11 small
+// adjoint sums plus tau_j per event).
+template <bool GRAD>
+__global__ __launch_bounds__(kThreads) void k_angtime(EventCols cols, AngTimeConst k,
+                                                      double* __restrict__ partials, int64_t n_tiles,
+                                                      double* __restrict__ tau, int64_t tau_stride) {
+  __shared__ double sC[40];
+  if (threadIdx.x < 40) sC[threadIdx.x] = (&k.C[0][0])[threadIdx.x];
+  __syncthreads();
+  constexpr int NACC = GRAD ? kAngInner : 1;
+  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    double acc[NACC];
+#pragma unroll
+    for (int c = 0; c < NACC; ++c) acc[c] = 0.0;
+    const int64_t base = tile * kTile + threadIdx.x;
+#pragma unroll 1
+    for (int e = 0; e < kEventsPerLane; ++e) {
+      const int64_t i = base + (int64_t)e * kThreads;
+      // keeps the LDS table reads inside the loop (re-read per event rather
+      // than pinned in 80 registers)
+      asm volatile("" ::: "memory");
+      if (i < cols.n) {
+        const double w = cols.w ? cols.w[i] : 1.0;
+        event_angtime<GRAD>(k, sC, cols.c[0][i], cols.c[1][i], cols.c[2][i], cols.c[3][i], cols.c[4][i],
+                            cols.c[5][i], w, acc, tau, tau_stride, i);
+      }
+    }
+    tile_store<NACC>(acc, partials, tile, n_tiles);
+  }
+}
+
+// Coefficient adjoints sum_i f_k(Omega_i) tau_j,i over canonical tiles of
+// kOuterTile events; partials at components kAngOuter0 + 4k + j.
+__global__ __launch_bounds__(kThreads) void k_angtime_outer(EventCols cols, const double* __restrict__ tau,
+                                                            int64_t tau_stride, double* __restrict__ partials,
+                                                            int64_t n_tiles_outer, int64_t stride) {
+  for (int64_t tile = blockIdx.x; tile < n_tiles_outer; tile += gridDim.x) {
+    double acc[kAngOuter];
+#pragma unroll
+    for (int c = 0; c < kAngOuter; ++c) acc[c] = 0.0;
+    const int64_t base = tile * kOuterTile + threadIdx.x;
+#pragma unroll 2
+    for (int e = 0; e < kOuterEventsPerLane; ++e) {
+      const int64_t i = base + (int64_t)e * kThreads;
+      if (i < cols.n) {
+        double f[10];
+        angular_functions(cols.c[0][i], cols.c[1][i], cols.c[2][i], f);
+        const double t0 = tau[i], t1 = tau[tau_stride + i], t2 = tau[2 * tau_stride + i],
+                     t3 = tau[3 * tau_stride + i];
+#pragma unroll
+        for (int kk = 0; kk < 10; ++kk) {
+          acc[4 * kk + 0] += f[kk] * t0;
+          acc[4 * kk + 1] += f[kk] * t1;
+          acc[4 * kk + 2] += f[kk] * t2;
+          acc[4 * kk + 3] += f[kk] * t3;
+        }
+      }
+    }
+    tile_store<kAngOuter>(acc, partials + kAngOuter0 * stride, tile, stride);
   }
 }
 
@@ -340,11 +418,6 @@ struct ModelTraits<2> {
   using Const = MassTimeConst;
   static constexpr int kAcc = kAccMassTime;
 };
-template <>
-struct ModelTraits<3> {
-  using Const = AngTimeConst;
-  static constexpr int kAcc = kAccAngTime;
-};
 
 template <int MODEL, bool GRAD>
 __device__ __forceinline__ void event(const typename ModelTraits<MODEL>::Const& k, const EventCols& cols,
@@ -352,11 +425,8 @@ __device__ __forceinline__ void event(const typename ModelTraits<MODEL>::Const& 
   const double w = cols.w ? cols.w[i] : 1.0;
   if constexpr (MODEL == 1) {
     event_mass<GRAD>(k, cols.c[0][i], w, acc);
-  } else if constexpr (MODEL == 2) {
-    event_masstime<GRAD>(k, cols.c[0][i], cols.c[1][i], cols.c[2][i], w, acc);
   } else {
-    event_angtime<GRAD>(k, cols.c[0][i], cols.c[1][i], cols.c[2][i], cols.c[3][i], cols.c[4][i],
-                        cols.c[5][i], w, acc);
+    event_masstime<GRAD>(k, cols.c[0][i], cols.c[1][i], cols.c[2][i], w, acc);
   }
 }
 
@@ -370,7 +440,7 @@ __global__ __launch_bounds__(kThreads) void k_nll_tiles(EventCols cols, typename
 #pragma unroll
     for (int c = 0; c < NACC; ++c) acc[c] = 0.0;
     const int64_t base = tile * kTile + threadIdx.x;
-#pragma unroll
+#pragma unroll 1
     for (int e = 0; e < kEventsPerLane; ++e) {
       const int64_t i = base + (int64_t)e * kThreads;
       if (i < cols.n) event<MODEL, GRAD>(k, cols, i, acc);

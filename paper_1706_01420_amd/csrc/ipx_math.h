@@ -30,6 +30,17 @@ struct cplx {
   double re, im;
 };
 
+// 1/x from the hardware reciprocal estimate and two Newton steps (relative
+// error near 1 ulp, not correctly rounded; used where the exact IEEE quotient
+// is not needed).  x must be finite and non-zero.
+__device__ __forceinline__ double rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(e, r, r);
+  e = fma(-x, r, 1.0);
+  return fma(e, r, r);
+}
+
 __device__ __forceinline__ cplx cx(double re, double im) { return cplx{re, im}; }
 __device__ __forceinline__ cplx cadd(cplx a, cplx b) { return cplx{a.re + b.re, a.im + b.im}; }
 __device__ __forceinline__ cplx csub(cplx a, cplx b) { return cplx{a.re - b.re, a.im - b.im}; }
@@ -40,12 +51,12 @@ __device__ __forceinline__ cplx cmul(cplx a, cplx b) {
 // Smith's scaled division (no overflow for |b| near the double range limits).
 __device__ __forceinline__ cplx cdiv(cplx a, cplx b) {
   if (fabs(b.re) >= fabs(b.im)) {
-    const double r = b.im / b.re;
-    const double inv = 1.0 / (b.re + b.im * r);
+    const double r = b.im * rcp(b.re);
+    const double inv = rcp(b.re + b.im * r);
     return cplx{(a.re + a.im * r) * inv, (a.im - a.re * r) * inv};
   }
-  const double r = b.re / b.im;
-  const double inv = 1.0 / (b.re * r + b.im);
+  const double r = b.re * rcp(b.im);
+  const double inv = rcp(b.re * r + b.im);
   return cplx{(a.re * r + a.im) * inv, (a.im * r - a.re) * inv};
 }
 
@@ -112,7 +123,7 @@ __device__ __forceinline__ double erfcx_pos(double y) {
     const double qn = d * q - c * qm;
     pm = p; qm = q; p = pn; q = qn;
   }
-  return -y * q * kInvSqrtPi / p;
+  return -y * q * kInvSqrtPi * rcp(p);
 }
 
 }  // namespace ipx

@@ -33,6 +33,7 @@ IPX_MODEL_ANGTIME = 3
 IPX_COPY_HOST = 0
 IPX_COPY_DEVICE = 1
 IPX_BORROW_DEVICE = 2
+IPX_KEEP_ORDER = 4
 
 _c_double_p = ctypes.POINTER(ctypes.c_double)
 _c_void_pp = ctypes.POINTER(ctypes.c_void_p)
@@ -52,10 +53,20 @@ _SIGNATURES = [
     ("ipx_dataset_size", ctypes.c_int64, [ctypes.c_void_p]),
     ("ipx_dataset_model", ctypes.c_int, [ctypes.c_void_p]),
     ("ipx_dataset_column", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_void_pp]),
+    ("ipx_dataset_read", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_int64, _c_double_p]),
     ("nll_eval", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_void_p, _c_double_p, ctypes.c_int, _c_double_p, ctypes.c_void_p]),
     ("nll_grad", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_void_p, _c_double_p, ctypes.c_int, _c_double_p, _c_double_p, ctypes.c_void_p]),
+    ("ipx_plan_create", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p), _c_void_pp]),
+    ("ipx_plan_destroy", None, [ctypes.c_void_p]),
+    ("nll_eval_batch", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_void_p, _c_double_p, ctypes.c_void_p, _c_double_p, ctypes.c_void_p,
+      ctypes.c_void_p]),
+    ("toy_generate", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_int, _c_double_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64,
+      ctypes.c_uint, _c_void_pp, ctypes.c_void_p]),
     ("ipx_timing_enable", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     ("ipx_timing_read", ctypes.c_int,
      [ctypes.c_void_p, _c_double_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]),
@@ -133,8 +144,9 @@ def ipx_dataset_create(ctx, model, cols, w=None, flags=IPX_COPY_HOST):
     keep = []
     ptrs = (ctypes.c_void_p * max(ncols, 1))()
     n = None
+    kind = flags & 3
     for i, c in enumerate(cols):
-        if flags == IPX_COPY_HOST:
+        if kind == IPX_COPY_HOST:
             c = np.ascontiguousarray(c, dtype=np.float64)
             keep.append(c)
             ptrs[i] = c.ctypes.data
@@ -150,7 +162,7 @@ def ipx_dataset_create(ctx, model, cols, w=None, flags=IPX_COPY_HOST):
             raise ValueError("columns differ in length")
     wp = None
     if w is not None:
-        if flags == IPX_COPY_HOST:
+        if kind == IPX_COPY_HOST:
             w = np.ascontiguousarray(w, dtype=np.float64)
             keep.append(w)
             wp = w.ctypes.data
@@ -185,6 +197,15 @@ def ipx_dataset_column(ds, col):
     return p.value
 
 
+def ipx_dataset_read(ctx, ds, col, offset=0, count=None):
+    """Host copy (numpy) of column `col` of a dataset, in storage order."""
+    n = ipx_dataset_size(ds)
+    count = n - offset if count is None else count
+    out = np.empty(count)
+    _check(_lib.ipx_dataset_read(ctx, ds, int(col), int(offset), int(count), _dbl(out)))
+    return out
+
+
 def nll_eval(ctx, ds, theta, stream=None):
     """-sum w ln P at theta; +inf for IPX_EDOMAIN (parameters outside the domain
     or a non-finite likelihood), an exception for any other error."""
@@ -207,6 +228,48 @@ def nll_grad(ctx, ds, theta, stream=None):
         return float("inf"), np.full(th.shape[0], np.nan)
     _check(st)
     return out.value, g
+
+
+def ipx_plan_create(ctx, datasets):
+    arr = (ctypes.c_void_p * len(datasets))(*[d.value for d in datasets])
+    h = ctypes.c_void_p()
+    _check(_lib.ipx_plan_create(ctx, len(datasets), arr, ctypes.byref(h)))
+    return h
+
+
+def ipx_plan_destroy(plan):
+    _lib.ipx_plan_destroy(plan)
+
+
+def nll_eval_batch(ctx, plan, theta, active=None, grad=False, stream=None):
+    """theta: (nb, np).  Returns nll (nb,) and, with grad=True, (nll, grad (nb, np)).
+    Entries outside the domain / non-finite come back as +inf (NaN gradient)."""
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    nb, np_ = th.shape
+    nll = np.full(nb, np.nan)
+    g = np.full((nb, np_), np.nan) if grad else None
+    act = None
+    if active is not None:
+        act = np.ascontiguousarray(active, dtype=np.uint8)
+    st = _lib.nll_eval_batch(ctx, plan, _dbl(th), None if act is None else act.ctypes.data, _dbl(nll),
+                             None if g is None else g.ctypes.data, _stream_ptr(stream))
+    if st not in (IPX_OK, IPX_EDOMAIN):
+        _check(st)
+    return (nll, g) if grad else nll
+
+
+class _ToyStats(ctypes.Structure):
+    _fields_ = [("n_candidates", ctypes.c_uint64), ("n_violations", ctypes.c_uint64)]
+
+
+def toy_generate(ctx, model, theta_gen, seed, toy_id, n, flags=0):
+    """Generate n events; returns (dataset handle, {"n_candidates", "n_violations"})."""
+    th = np.ascontiguousarray(theta_gen, dtype=np.float64)
+    h = ctypes.c_void_p()
+    st = _ToyStats()
+    _check(_lib.toy_generate(ctx, int(model), _dbl(th), th.shape[0], ctypes.c_uint64(seed), ctypes.c_uint64(toy_id),
+                             int(n), int(flags), ctypes.byref(h), ctypes.byref(st)))
+    return h, {"n_candidates": st.n_candidates, "n_violations": st.n_violations}
 
 
 def ipx_timing_enable(ctx, enable=True):

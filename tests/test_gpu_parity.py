@@ -189,9 +189,9 @@ def test_borrowed_device_columns_and_torch_stream(lib, ctx, model):
     cols, w = small_data(model, n=5000, seed=5)
     dev = [torch.from_numpy(c).cuda() for c in cols]
     wd = None if w is None else torch.from_numpy(w).cuda()
-    ds_copy = lib.ipx_dataset_create(ctx, model, cols, w)
+    ds_copy = lib.ipx_dataset_create(ctx, model, cols, w, flags=lib.IPX_COPY_HOST | lib.IPX_KEEP_ORDER)
     ds_borrow = lib.ipx_dataset_create(ctx, model, dev, wd, flags=lib.IPX_BORROW_DEVICE)
-    ds_dcopy = lib.ipx_dataset_create(ctx, model, dev, wd, flags=lib.IPX_COPY_DEVICE)
+    ds_dcopy = lib.ipx_dataset_create(ctx, model, dev, wd, flags=lib.IPX_COPY_DEVICE | lib.IPX_KEEP_ORDER)
     try:
         th = thetas(model, 2)[1]
         say("borrow/stream model", model)
@@ -203,6 +203,32 @@ def test_borrowed_device_columns_and_torch_stream(lib, ctx, model):
     finally:
         for d in (ds_copy, ds_borrow, ds_dcopy):
             lib.ipx_dataset_destroy(ctx, d)
+
+
+@pytest.mark.parametrize("model", [2, 3])
+def test_time_sorted_store_is_a_sorted_permutation(lib, ctx, model):
+    cols, w = small_data(model, n=6000, seed=12)
+    ds = lib.ipx_dataset_create(ctx, model, cols, w)                      # sorted by t
+    dk = lib.ipx_dataset_create(ctx, model, cols, w, flags=lib.IPX_COPY_HOST | lib.IPX_KEEP_ORDER)
+    try:
+        say("sorted store model", model)
+        tcol = 1 if model == 2 else 3
+        got = [lib.ipx_dataset_read(ctx, ds, c) for c in range(len(cols))]
+        t = got[tcol]
+        assert np.all(np.diff(t) >= 0)
+        order = np.argsort(cols[tcol], kind="stable")
+        for c in range(len(cols)):
+            assert np.array_equal(np.sort(got[c]), np.sort(cols[c]))
+            assert np.array_equal(got[c], cols[c][order])
+        th = thetas(model, 2)[1]
+        a, b = lib.nll_eval(ctx, ds, th), lib.nll_eval(ctx, dk, th)
+        assert abs(a - b) <= 1e-13 * abs(b)
+        fa, ga = lib.nll_grad(ctx, ds, th)
+        fb, gb = lib.nll_grad(ctx, dk, th)
+        assert np.allclose(ga, gb, rtol=1e-10, atol=1e-10 * np.abs(gb).max())
+    finally:
+        lib.ipx_dataset_destroy(ctx, ds)
+        lib.ipx_dataset_destroy(ctx, dk)
 
 
 def test_timing_counters(lib, ctx):
