@@ -87,6 +87,7 @@ typedef enum {
 #define IPX_COPY_DEVICE 1u   /* cols/w are device pointers; data are copied device-to-device */
 #define IPX_BORROW_DEVICE 2u /* cols/w are device pointers used in place; the caller keeps them alive */
 #define IPX_KEEP_ORDER 4u    /* or-ed with a COPY flag: store events in the given order */
+#define IPX_NO_WEIGHTS 8u    /* toy_generate: no weight column (unit weights) */
 
 typedef struct ipx_ctx ipx_ctx;
 typedef struct ipx_dataset ipx_dataset;
@@ -168,13 +169,59 @@ IPX_API ipx_status nll_grad(ipx_ctx *ctx, const ipx_dataset *ds, const double *t
  * Entries outside the domain or with a non-finite likelihood get +inf (and
  * NaN gradients); the call then returns IPX_EDOMAIN after filling every other
  * entry.  Plans must not be used concurrently with each other or with plain
- * calls on the same datasets.
+ * calls on the same datasets.  A dataset referenced by a plan cannot be
+ * destroyed (IPX_EBUSY) until the plan is.
  */
 typedef struct ipx_plan ipx_plan;
 IPX_API ipx_status ipx_plan_create(ipx_ctx *ctx, int nb, ipx_dataset *const *ds, ipx_plan **out);
 IPX_API void ipx_plan_destroy(ipx_plan *plan);
 IPX_API ipx_status nll_eval_batch(ipx_ctx *ctx, ipx_plan *plan, const double *theta, const unsigned char *active,
                                   double *nll, double *grad, void *stream);
+
+/*
+ * Served likelihood: a persistent device loop that evaluates requests from
+ * many concurrent clients (minimizers, MCMC chains) over resident datasets
+ * (the paper's samplers and fitters each call the likelihood once per
+ * parameter vector).  Requests are admitted into device slots as slots and
+ * scratch memory (the request's tile partials, and the per-event scratch of
+ * the angular gradient) free up, so requests arriving while others run join
+ * the same launch; each request's result is bitwise the same as nll_eval /
+ * nll_grad on its dataset alone.  The device loop ends by itself after an
+ * idle period and is relaunched when work arrives.
+ *   ipx_submit is thread safe and non-blocking (IPX_EBUSY if max_pending
+ *   requests are already waiting; IPX_ENOMEM if the request alone exceeds the
+ *   scratch budget).  Results are taken once, with ipx_poll (IPX_EBUSY while
+ *   running) or ipx_wait (IPX_ETIMEOUT after timeout_ns; < 0 waits forever).
+ *   ipx_server_stop drains pending and in-flight requests, stops the device
+ *   loop and frees the server.  Datasets must outlive the requests on them.
+ */
+typedef struct ipx_server ipx_server;
+typedef struct {
+  int slots;               /* concurrent requests on the device (<= 64; 0 = 32) */
+  size_t scratch_bytes;    /* scratch budget for admitted requests (0 = 2 GiB) */
+  int workgroups;          /* persistent workgroups (0 = 2 per compute unit) */
+  int idle_iterations;     /* empty scans before the device loop exits (0 = 20000) */
+  int spin_limit;          /* cap on a wait for a request's first phase (0 = 2^24) */
+  int max_pending;         /* waiting requests accepted (0 = unlimited) */
+} ipx_server_cfg;
+typedef struct {
+  const ipx_dataset *ds;
+  const double *theta;     /* np doubles, copied at submission */
+  int np;
+  int want_grad;
+} ipx_request;
+typedef struct {
+  int status;              /* IPX_OK, IPX_EDOMAIN, ... */
+  int np;
+  double nll;
+  double grad[12];         /* np entries when the gradient was requested */
+  double latency_us;       /* submission to completion */
+} ipx_result;
+IPX_API ipx_status ipx_server_start(ipx_ctx *ctx, const ipx_server_cfg *cfg, ipx_server **out);
+IPX_API ipx_status ipx_submit(ipx_server *srv, const ipx_request *req, uint64_t *ticket);
+IPX_API ipx_status ipx_poll(ipx_server *srv, uint64_t ticket, ipx_result *out);
+IPX_API ipx_status ipx_wait(ipx_server *srv, uint64_t ticket, int64_t timeout_ns, ipx_result *out);
+IPX_API ipx_status ipx_server_stop(ipx_server *srv);
 
 /*
  * Unbinned toy generation by accept-reject (Example 5 of the paper: toys
@@ -186,7 +233,8 @@ IPX_API ipx_status nll_eval_batch(ipx_ctx *ctx, ipx_plan *plan, const double *th
  *   uniforms ((word >> 12) + 0.5) 2^-52.  Candidate c is accepted on its own
  *   words; the output holds the first n accepted candidates (increasing c),
  *   sorted by decay time for models 2 and 3 unless flags has IPX_KEEP_ORDER.
- *   Model 3 also draws weights 0.8 + 0.2 u (the workload's efficiency weights).
+ *   Model 3 also draws weights 0.8 + 0.2 u (the workload's efficiency weights)
+ *   unless flags has IPX_NO_WEIGHTS.
  *   Each model's recipe (proposals, bounds, acceptance ratios) is documented
  *   in the library source; conditional on sigma_t the accepted events follow
  *   the model's PDF exactly.

@@ -19,6 +19,12 @@
 #include <limits>
 #include <string>
 #include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
 #include <vector>
 
 #include "../../include/ipx.h"
@@ -26,6 +32,7 @@
 #include "ipx_kernels.h"
 #include "ipx_toys.h"
 #include "ipx_batch.h"
+#include "ipx_serve.h"
 
 using namespace ipx;
 
@@ -82,6 +89,8 @@ struct ipx_dataset {
   double* out_dev = nullptr;       // kAccMax
   double* out_host = nullptr;      // kAccMax, pinned
   size_t bytes = 0;
+  struct ipx_plan* self = nullptr; // one-dataset plan used by nll_eval / nll_grad
+  int plan_refs = 0;               // user plans that reference this dataset
 };
 
 static const int kNParams[4] = {-1, 4, 7, 12};
@@ -193,7 +202,9 @@ void ipx_destroy(ipx_ctx* c) {
   delete c;
 }
 
+static void free_plan(struct ipx_plan* p);
 static void free_dataset(ipx_dataset* d) {
+  if (d->self) free_plan(d->self);
   if (d->base) (void)hipFree(d->base);
   if (d->tau) (void)hipFree(d->tau);
   if (d->partials) (void)hipFree(d->partials);
@@ -273,6 +284,8 @@ ipx_status ipx_dataset_create(ipx_ctx* ctx, int model, int64_t n, const double* 
 
 ipx_status ipx_dataset_destroy(ipx_ctx* ctx, ipx_dataset* d) {
   if (!ctx || !d) return fail(IPX_EINVAL, "ipx_dataset_destroy: NULL argument");
+  if (d->plan_refs > 0)
+    return fail(IPX_EBUSY, "ipx_dataset_destroy: dataset is used by %d plan(s); destroy them first", d->plan_refs);
   HIP_TRY(hipSetDevice(ctx->device));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   free_dataset(d);
@@ -348,83 +361,6 @@ static EventCols cols_of(const ipx_dataset* d) {
   c.w = d->w;
   c.n = d->n;
   return c;
-}
-
-template <int MODEL, bool GRAD>
-static ipx_status launch_model(ipx_ctx* ctx, const ipx_dataset* d, const typename ModelTraits<MODEL>::Const& k,
-                               hipStream_t s) {
-  constexpr int nacc = GRAD ? ModelTraits<MODEL>::kAcc : 1;
-  if (d->n_tiles == 0) {
-    // empty dataset: the reduction of zero tiles writes zeros (no memset, so
-    // the call stays capturable in a graph)
-    hipLaunchKernelGGL(k_reduce_tiles, dim3(nacc), dim3(kThreads), 0, s, d->partials, (int64_t)0, (int64_t)0, nacc,
-                       (int64_t)0, d->out_dev);
-    HIP_TRY(hipGetLastError());
-    return IPX_OK;
-  }
-  const int64_t grid = d->n_tiles;  // one workgroup per canonical tile
-  const bool timed = ctx->timing;
-  if (timed) {
-    if (ctx->ev_used == 64) {
-      ipx_status st = timing_drain(ctx);
-      if (st != IPX_OK) return st;
-    }
-    HIP_TRY(hipEventRecord(ctx->ev_pool[0][ctx->ev_used], s));
-  }
-  hipLaunchKernelGGL((k_nll_tiles<MODEL, GRAD>), dim3((unsigned)grid), dim3(kThreads), 0, s, cols_of(d), k,
-                     d->partials, d->n_tiles);
-  HIP_TRY(hipGetLastError());
-  if (timed) {
-    HIP_TRY(hipEventRecord(ctx->ev_pool[1][ctx->ev_used], s));
-    ctx->ev_used++;
-  }
-  hipLaunchKernelGGL(k_reduce_tiles, dim3(nacc), dim3(kThreads), 0, s, d->partials, d->n_tiles, d->n_tiles, nacc,
-                     (int64_t)0, d->out_dev);
-  HIP_TRY(hipGetLastError());
-  return IPX_OK;
-}
-
-template <bool GRAD>
-static ipx_status launch_angtime(ipx_ctx* ctx, ipx_dataset* d, const AngTimeConst& k, hipStream_t s) {
-  constexpr int nacc = GRAD ? kAccAngTime : 1;
-  if (d->n_tiles == 0) {
-    hipLaunchKernelGGL(k_reduce_tiles, dim3(nacc), dim3(kThreads), 0, s, d->partials, (int64_t)0, (int64_t)0, nacc,
-                       (int64_t)0, d->out_dev);
-    HIP_TRY(hipGetLastError());
-    return IPX_OK;
-  }
-  if (GRAD && !d->tau) {
-    hipError_t e = hipMalloc(&d->tau, 4 * (size_t)d->n_pad * sizeof(double));
-    if (e != hipSuccess) {
-      d->tau = nullptr;
-      return fail(IPX_ENOMEM, "nll_grad: per-event scratch allocation failed: %s", hipGetErrorString(e));
-    }
-    d->bytes += 4 * (size_t)d->n_pad * sizeof(double);
-  }
-  const bool timed = ctx->timing;
-  if (timed) {
-    if (ctx->ev_used == 64) {
-      ipx_status st = timing_drain(ctx);
-      if (st != IPX_OK) return st;
-    }
-    HIP_TRY(hipEventRecord(ctx->ev_pool[0][ctx->ev_used], s));
-  }
-  hipLaunchKernelGGL((k_angtime<GRAD>), dim3((unsigned)d->n_tiles), dim3(kThreads), 0, s, cols_of(d), k,
-                     d->partials, d->n_tiles, d->tau, d->n_pad);
-  HIP_TRY(hipGetLastError());
-  if (timed) {
-    HIP_TRY(hipEventRecord(ctx->ev_pool[1][ctx->ev_used], s));
-    ctx->ev_used++;
-  }
-  if (GRAD) {
-    hipLaunchKernelGGL(k_angtime_outer, dim3((unsigned)d->n_tiles_outer), dim3(kThreads), 0, s, cols_of(d),
-                       (const double*)d->tau, d->n_pad, d->partials, d->n_tiles_outer, d->n_tiles);
-    HIP_TRY(hipGetLastError());
-  }
-  hipLaunchKernelGGL(k_reduce_tiles, dim3(nacc), dim3(kThreads), 0, s, d->partials, d->n_tiles, d->n_tiles,
-                     kAngInner, d->n_tiles_outer, d->out_dev);
-  HIP_TRY(hipGetLastError());
-  return IPX_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -540,7 +476,7 @@ extern "C" ipx_status toy_generate(ipx_ctx* ctx, int model, const double* theta,
   if (model < 1 || model > 3) return fail(IPX_EINVAL, "toy_generate: unknown model %d", model);
   if (np != kNParams[model]) return fail(IPX_EINVAL, "toy_generate: model %d takes %d parameters", model, kNParams[model]);
   if (n < 0 || n > 0x7fffffff) return fail(IPX_EINVAL, "toy_generate: n = %lld out of range", (long long)n);
-  if (flags & ~IPX_KEEP_ORDER) return fail(IPX_EINVAL, "toy_generate: bad flags %u", flags);
+  if (flags & ~(IPX_KEEP_ORDER | IPX_NO_WEIGHTS)) return fail(IPX_EINVAL, "toy_generate: bad flags %u", flags);
   if (!theta_valid(model, theta)) return fail(IPX_EDOMAIN, "toy_generate: parameters outside the domain");
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
@@ -558,7 +494,8 @@ extern "C" ipx_status toy_generate(ipx_ctx* ctx, int model, const double* theta,
   d->n_pad = (n + 31) / 32 * 32;
   d->n_tiles = (n + kTile - 1) / kTile;
   d->n_tiles_outer = (n + kOuterTile - 1) / kOuterTile;
-  const int nstore = ncols + (model == 3 ? 1 : 0);
+  const bool weighted = model == 3 && !(flags & IPX_NO_WEIGHTS);
+  const int nstore = ncols + (weighted ? 1 : 0);
   const size_t bytes = (size_t)nstore * (size_t)(d->n_pad > 0 ? d->n_pad : 32) * sizeof(double);
   hipError_t e = hipMalloc(&d->base, bytes);
   const int64_t tiles_alloc = d->n_tiles > 0 ? d->n_tiles : 1;
@@ -576,7 +513,7 @@ extern "C" ipx_status toy_generate(ipx_ctx* ctx, int model, const double* theta,
     d->cols[c] = colp_host[c];
   }
   double* wout = nullptr;
-  if (model == 3) {
+  if (weighted) {
     wout = d->base + (size_t)ncols * d->n_pad;
     d->w = wout;
   }
@@ -669,10 +606,13 @@ struct ipx_plan {
   unsigned char* h_active = nullptr;
   double* h_out = nullptr;
   hipGraphExec_t exec[2] = {nullptr, nullptr};  // [eval, grad]
+  bool counted = false;            // holds a reference on each dataset
   hipStream_t exec_stream[2] = {nullptr, nullptr};
 };
 
-static void free_plan(ipx_plan* p) {
+static void free_plan(struct ipx_plan* p) {
+  if (p->counted)
+    for (ipx_dataset* d : p->ds) d->plan_refs--;
   for (int i = 0; i < 2; ++i)
     if (p->exec[i]) (void)hipGraphExecDestroy(p->exec[i]);
   (void)hipFree(p->d_segs); (void)hipFree(p->d_tiles); (void)hipFree(p->d_tiles_outer);
@@ -687,7 +627,11 @@ static size_t const_size_of(int model) {
   return model == 1 ? sizeof(MassConst) : model == 2 ? sizeof(MassTimeConst) : sizeof(AngTimeConst);
 }
 
+static ipx_status plan_create(ipx_ctx* ctx, int nb, ipx_dataset* const* ds, ipx_plan** out, bool counted);
 extern "C" ipx_status ipx_plan_create(ipx_ctx* ctx, int nb, ipx_dataset* const* ds, ipx_plan** out) {
+  return plan_create(ctx, nb, ds, out, true);
+}
+static ipx_status plan_create(ipx_ctx* ctx, int nb, ipx_dataset* const* ds, ipx_plan** out, bool counted) {
   if (!ctx || !out || (nb > 0 && !ds)) return fail(IPX_EINVAL, "ipx_plan_create: NULL argument");
   *out = nullptr;
   if (nb <= 0) return fail(IPX_EINVAL, "ipx_plan_create: empty batch");
@@ -746,6 +690,10 @@ extern "C" ipx_status ipx_plan_create(ipx_ctx* ctx, int nb, ipx_dataset* const* 
     free_plan(p);
     return fail(IPX_ENOMEM, "ipx_plan_create: allocation failed: %s", hipGetErrorString(e));
   }
+  if (counted) {
+    for (ipx_dataset* d : p->ds) d->plan_refs++;
+    p->counted = true;
+  }
   *out = p;
   return IPX_OK;
 }
@@ -759,12 +707,36 @@ extern "C" void ipx_plan_destroy(ipx_plan* p) {
 
 // The body of one batched evaluation, as stream operations (captured once
 // into a graph per plan and mode).
-static ipx_status enqueue_batch(ipx_plan* p, bool grad, hipStream_t s) {
+static ipx_status timing_begin(ipx_ctx* ctx, hipStream_t s) {
+  if (!ctx || !ctx->timing) return IPX_OK;
+  if (ctx->ev_used == 64) {
+    ipx_status st = timing_drain(ctx);
+    if (st != IPX_OK) return st;
+  }
+  HIP_TRY(hipEventRecord(ctx->ev_pool[0][ctx->ev_used], s));
+  return IPX_OK;
+}
+static ipx_status timing_end(ipx_ctx* ctx, hipStream_t s) {
+  if (!ctx || !ctx->timing) return IPX_OK;
+  HIP_TRY(hipEventRecord(ctx->ev_pool[1][ctx->ev_used], s));
+  ctx->ev_used++;
+  return IPX_OK;
+}
+
+// Stream operations of one (batched) evaluation: constants and active flags
+// to the device, the per-event kernel (timed through `timer` when given), for
+// the angular gradient the coefficient-adjoint kernel, the per-segment
+// reductions, results back to pinned host memory.
+static ipx_status enqueue_batch(ipx_plan* p, bool grad, hipStream_t s, ipx_ctx* timer) {
   const int nb = p->nb;
   HIP_TRY(hipMemcpyAsync(p->d_consts, p->h_consts, nb * p->const_size, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(p->d_active, p->h_active, nb, hipMemcpyHostToDevice, s));
   const unsigned grid = (unsigned)std::max<int64_t>(1, p->n_tiles);
   int nacc = 1, split = 1;
+  {
+    ipx_status st = timing_begin(timer, s);
+    if (st != IPX_OK) return st;
+  }
   if (p->model == 1) {
     nacc = grad ? kAccMass : 1;
     split = nacc;
@@ -781,6 +753,10 @@ static ipx_status enqueue_batch(ipx_plan* p, bool grad, hipStream_t s) {
     if (grad) hipLaunchKernelGGL((k_angtime_batch<true>), dim3(grid), dim3(kThreads), 0, s, p->d_segs, p->d_tiles, p->n_tiles, (const AngTimeConst*)p->d_consts, p->d_active);
     else hipLaunchKernelGGL((k_angtime_batch<false>), dim3(grid), dim3(kThreads), 0, s, p->d_segs, p->d_tiles, p->n_tiles, (const AngTimeConst*)p->d_consts, p->d_active);
     HIP_TRY(hipGetLastError());
+    {
+      ipx_status st = timing_end(timer, s);
+      if (st != IPX_OK) return st;
+    }
     if (grad) {
       const unsigned go = (unsigned)std::max<int64_t>(1, p->n_tiles_outer);
       hipLaunchKernelGGL(k_angtime_outer_batch, dim3(go), dim3(kThreads), 0, s, p->d_segs, p->d_tiles_outer,
@@ -788,6 +764,10 @@ static ipx_status enqueue_batch(ipx_plan* p, bool grad, hipStream_t s) {
     }
   }
   HIP_TRY(hipGetLastError());
+  if (p->model != 3) {
+    ipx_status st = timing_end(timer, s);
+    if (st != IPX_OK) return st;
+  }
   hipLaunchKernelGGL(k_reduce_batch, dim3(nacc, nb), dim3(kThreads), 0, s, p->d_segs, p->d_active, split, p->d_out);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(p->h_out, p->d_out, (size_t)nb * kAccMax * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -830,7 +810,7 @@ extern "C" ipx_status nll_eval_batch(ipx_ctx* ctx, ipx_plan* p, const double* th
     if (!p->exec[mode]) {
       hipGraph_t g = nullptr;
       HIP_TRY(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-      ipx_status st = enqueue_batch(p, grad != nullptr, ctx->stream);
+      ipx_status st = enqueue_batch(p, grad != nullptr, ctx->stream, nullptr);
       hipError_t e = hipStreamEndCapture(ctx->stream, &g);
       if (st != IPX_OK) {
         if (g) (void)hipGraphDestroy(g);
@@ -875,10 +855,394 @@ extern "C" ipx_status nll_eval_batch(ipx_ctx* ctx, ipx_plan* p, const double* th
   return IPX_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Served likelihood (persistent kernel + host-visible mailbox)
+// ---------------------------------------------------------------------------
+struct ServeReq {
+  uint64_t ticket = 0;
+  ipx_dataset* ds = nullptr;
+  int model = 0, grad = 0, np = 0;
+  double theta[12];
+  MassHoist h1;
+  MassTimeHoist h2;
+  AngTimeHoist h3;
+  int slot = -1;
+  uint64_t seq = 0;
+  size_t off = 0, bytes = 0;
+  std::chrono::steady_clock::time_point t_submit, t_done;
+  bool done = false;
+  ipx_result res;
+};
+
+struct ipx_server {
+  ipx_ctx* ctx = nullptr;
+  ipx_server_cfg cfg;
+  hipStream_t stream = nullptr;
+  hipEvent_t kernel_done = nullptr;
+  bool kernel_launched = false;
+  ServeShared* hs = nullptr;     // fine-grained host memory
+  ServeShared* hs_dev = nullptr; // its device-side address
+  ServeCtl* ctl = nullptr;
+  ServeDesc* dd = nullptr;
+  ServeSlot* st = nullptr;
+  char* pool = nullptr;
+  std::map<size_t, size_t> free_list;  // offset -> size
+  std::mutex mu;
+  std::condition_variable cv;
+  std::thread worker;
+  bool stopping = false;
+  std::string worker_error;
+  uint64_t next_ticket = 1;
+  std::vector<uint64_t> slot_seq;      // last sequence number per slot
+  std::vector<ServeReq*> slot_req;     // request in the slot (nullptr = free)
+  std::deque<ServeReq*> pending;
+  std::map<uint64_t, ServeReq*> reqs;
+};
+
+static bool pool_alloc(ipx_server* S, size_t bytes, size_t* off) {
+  for (auto it = S->free_list.begin(); it != S->free_list.end(); ++it) {
+    if (it->second >= bytes) {
+      *off = it->first;
+      const size_t rest = it->second - bytes;
+      const size_t roff = it->first + bytes;
+      S->free_list.erase(it);
+      if (rest) S->free_list[roff] = rest;
+      return true;
+    }
+  }
+  return false;
+}
+
+static void pool_free(ipx_server* S, size_t off, size_t bytes) {
+  auto it = S->free_list.emplace(off, bytes).first;
+  auto nx = std::next(it);
+  if (nx != S->free_list.end() && it->first + it->second == nx->first) {
+    it->second += nx->second;
+    S->free_list.erase(nx);
+  }
+  if (it != S->free_list.begin()) {
+    auto pv = std::prev(it);
+    if (pv->first + pv->second == it->first) {
+      pv->second += it->second;
+      S->free_list.erase(it);
+    }
+  }
+}
+
+static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+static int serve_nacc(int model, int grad) {
+  if (!grad) return 1;
+  return model == 1 ? kAccMass : model == 2 ? kAccMassTime : kAccAngTime;
+}
+
+static size_t request_bytes(const ipx_dataset* d, int grad) {
+  size_t b = align256((size_t)std::max<int64_t>(1, d->n_tiles) * serve_nacc(d->model, grad) * sizeof(double));
+  if (d->model == 3 && grad) b += align256(4 * (size_t)d->n_pad * sizeof(double));
+  return b;
+}
+
+// Fill the descriptor of a request in its slot and publish it.
+static void serve_publish(ipx_server* S, ServeReq* r) {
+  ServeDesc& D = S->hs->desc[r->slot];
+  std::memset(&D, 0, sizeof D);
+  const ipx_dataset* d = r->ds;
+  D.model = r->model;
+  D.grad = r->grad;
+  D.nA = (int)d->n_tiles;
+  D.nB = (r->model == 3 && r->grad) ? (int)d->n_tiles_outer : 0;
+  D.nacc = serve_nacc(r->model, r->grad);
+  D.split = r->model == 3 && r->grad ? kAngInner : D.nacc;
+  D.seg.cols = cols_of(d);
+  char* base = S->pool + r->off;
+  D.seg.partials = (double*)base;
+  D.seg.tau = r->model == 3 && r->grad
+                  ? (double*)(base + align256((size_t)std::max<int64_t>(1, d->n_tiles) * D.nacc * sizeof(double)))
+                  : nullptr;
+  D.seg.tau_stride = d->n_pad;
+  D.seg.n_tiles = d->n_tiles;
+  D.seg.n_tiles_outer = d->n_tiles_outer;
+  if (r->model == 1) D.k.m1 = r->h1.k;
+  else if (r->model == 2) D.k.m2 = r->h2.k;
+  else D.k.m3 = r->h3.k;
+  S->hs->status[r->slot] = 0;
+  r->seq = ++S->slot_seq[r->slot];
+  __atomic_store_n(&S->hs->mail[r->slot], (unsigned long long)r->seq, __ATOMIC_RELEASE);
+  __atomic_fetch_add(&S->hs->gen, 1ull, __ATOMIC_RELEASE);
+}
+
+static void serve_finish(ipx_server* S, ServeReq* r, int status, const double* a) {
+  r->t_done = std::chrono::steady_clock::now();
+  r->res.latency_us = std::chrono::duration<double, std::micro>(r->t_done - r->t_submit).count();
+  r->res.np = r->np;
+  r->res.status = status;
+  r->res.nll = std::numeric_limits<double>::quiet_NaN();
+  if (status == IPX_OK) {
+    if (!std::isfinite(a[0])) {
+      r->res.status = IPX_EDOMAIN;
+      r->res.nll = std::numeric_limits<double>::infinity();
+      for (int i = 0; i < r->np; ++i) r->res.grad[i] = std::numeric_limits<double>::quiet_NaN();
+    } else {
+      r->res.nll = -a[0];
+      if (r->grad) {
+        if (r->model == 1) grad_mass(r->h1, r->theta, a, r->res.grad);
+        else if (r->model == 2) grad_masstime(r->h2, r->theta, a, r->res.grad);
+        else grad_angtime(r->h3, r->theta, a, r->res.grad);
+      }
+    }
+  }
+  r->done = true;
+}
+
+static bool serve_kernel_live(ipx_server* S) {
+  if (!S->kernel_launched) return false;
+  return hipEventQuery(S->kernel_done) == hipErrorNotReady;
+}
+
+static void serve_worker(ipx_server* S) {
+  (void)hipSetDevice(S->ctx->device);
+  const int nslots = S->cfg.slots;
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto last_progress = std::chrono::steady_clock::now();
+  for (;;) {
+    bool progress = false;
+    int busy = 0;
+    for (int s = 0; s < nslots; ++s) {
+      ServeReq* r = S->slot_req[s];
+      if (!r) continue;
+      if (__atomic_load_n(&S->hs->fin[s], __ATOMIC_ACQUIRE) == r->seq) {
+        const int status = S->hs->status[s] ? IPX_ETIMEOUT : IPX_OK;
+        serve_finish(S, r, status, S->hs->out[s]);
+        pool_free(S, r->off, r->bytes);
+        S->slot_req[s] = nullptr;
+        progress = true;
+      } else {
+        ++busy;
+      }
+    }
+    while (!S->pending.empty()) {
+      ServeReq* r = S->pending.front();
+      int slot = -1;
+      for (int s = 0; s < nslots; ++s)
+        if (!S->slot_req[s]) {
+          slot = s;
+          break;
+        }
+      if (slot < 0) break;
+      size_t off = 0;
+      if (!pool_alloc(S, r->bytes, &off)) break;  // admission by footprint: wait for memory
+      S->pending.pop_front();
+      r->slot = slot;
+      r->off = off;
+      S->slot_req[slot] = r;
+      serve_publish(S, r);
+      ++busy;
+      progress = true;
+    }
+    if (busy > 0 && !serve_kernel_live(S)) {
+      hipLaunchKernelGGL(k_serve, dim3((unsigned)S->cfg.workgroups), dim3(kThreads), 0, S->stream, S->hs_dev,
+                         S->ctl, S->dd, S->st, nslots, S->cfg.idle_iterations, S->cfg.spin_limit);
+      hipError_t e = hipGetLastError();
+      if (e == hipSuccess) e = hipEventRecord(S->kernel_done, S->stream);
+      S->kernel_launched = true;
+      if (e != hipSuccess) {
+        // the device loop cannot run: every request ends with a device error
+        S->worker_error = hipGetErrorString(e);
+        for (int s = 0; s < nslots; ++s)
+          if (S->slot_req[s]) {
+            serve_finish(S, S->slot_req[s], IPX_EDEVICE, nullptr);
+            pool_free(S, S->slot_req[s]->off, S->slot_req[s]->bytes);
+            S->slot_req[s] = nullptr;
+          }
+        for (ServeReq* r : S->pending) serve_finish(S, r, IPX_EDEVICE, nullptr);
+        S->pending.clear();
+        S->kernel_launched = false;
+        busy = 0;
+        progress = true;
+      }
+    }
+    const auto now = std::chrono::steady_clock::now();
+    if (progress) {
+      S->cv.notify_all();
+      last_progress = now;
+    }
+    if (S->stopping && busy == 0 && S->pending.empty()) break;
+    if (S->stopping && now - last_progress > std::chrono::seconds(10)) {
+      // nothing has completed for 10 s while stopping: give the rest up
+      for (int s = 0; s < nslots; ++s)
+        if (S->slot_req[s]) {
+          serve_finish(S, S->slot_req[s], IPX_ETIMEOUT, nullptr);
+          S->slot_req[s] = nullptr;
+        }
+      for (ServeReq* r : S->pending) serve_finish(S, r, IPX_ETIMEOUT, nullptr);
+      S->pending.clear();
+      break;
+    }
+    S->cv.wait_for(lk, std::chrono::microseconds(progress ? 0 : 20));
+  }
+  S->cv.notify_all();
+}
+
+extern "C" ipx_status ipx_server_start(ipx_ctx* ctx, const ipx_server_cfg* cfg, ipx_server** out) {
+  if (!ctx || !out) return fail(IPX_EINVAL, "ipx_server_start: NULL argument");
+  *out = nullptr;
+  ipx_server_cfg c{};
+  if (cfg) c = *cfg;
+  if (c.slots <= 0) c.slots = 32;
+  if (c.slots > kServeMaxSlots) return fail(IPX_EINVAL, "ipx_server_start: at most %d slots", kServeMaxSlots);
+  if (c.scratch_bytes == 0) c.scratch_bytes = (size_t)1 << 31;
+  if (c.workgroups <= 0) c.workgroups = 2 * std::max(1, ctx->n_cu);
+  if (c.idle_iterations <= 0) c.idle_iterations = 20000;
+  if (c.spin_limit <= 0) c.spin_limit = 1 << 24;
+  HIP_TRY(hipSetDevice(ctx->device));
+  ipx_server* S = new (std::nothrow) ipx_server();
+  if (!S) return fail(IPX_ENOMEM, "ipx_server_start: host allocation failed");
+  S->ctx = ctx;
+  S->cfg = c;
+  S->slot_seq.assign(c.slots, 0);
+  S->slot_req.assign(c.slots, nullptr);
+  hipError_t e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&S->kernel_done, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&S->hs, sizeof(ServeShared), hipHostMallocCoherent | hipHostMallocMapped);
+  if (e == hipSuccess) e = hipMalloc(&S->dd, kServeMaxSlots * sizeof(ServeDesc));
+  if (e == hipSuccess) e = hipMalloc(&S->st, kServeMaxSlots * sizeof(ServeSlot));
+  if (e == hipSuccess) e = hipMalloc(&S->ctl, sizeof(ServeCtl));
+  if (e == hipSuccess) e = hipMemset(S->ctl, 0, sizeof(ServeCtl));
+  if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&S->hs_dev, S->hs, 0);
+  if (e == hipSuccess) e = hipMalloc(&S->pool, c.scratch_bytes);
+  if (e == hipSuccess) e = hipMemset(S->st, 0, kServeMaxSlots * sizeof(ServeSlot));
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    if (S->pool) (void)hipFree(S->pool);
+    if (S->st) (void)hipFree(S->st);
+    if (S->ctl) (void)hipFree(S->ctl);
+    if (S->dd) (void)hipFree(S->dd);
+    if (S->hs) (void)hipHostFree(S->hs);
+    if (S->kernel_done) (void)hipEventDestroy(S->kernel_done);
+    if (S->stream) (void)hipStreamDestroy(S->stream);
+    delete S;
+    return fail(IPX_ENOMEM, "ipx_server_start: allocation failed: %s", hipGetErrorString(e));
+  }
+  std::memset(S->hs, 0, sizeof(ServeShared));
+  S->free_list[0] = c.scratch_bytes;
+  S->worker = std::thread(serve_worker, S);
+  *out = S;
+  return IPX_OK;
+}
+
+extern "C" ipx_status ipx_submit(ipx_server* S, const ipx_request* q, uint64_t* ticket) {
+  if (!S || !q || !ticket || !q->ds || !q->theta) return fail(IPX_EINVAL, "ipx_submit: NULL argument");
+  ipx_dataset* d = const_cast<ipx_dataset*>(q->ds);
+  const int model = d->model, np = kNParams[model];
+  if (q->np != np) return fail(IPX_EINVAL, "ipx_submit: model %d takes %d parameters", model, np);
+  ServeReq* r = new (std::nothrow) ServeReq();
+  if (!r) return fail(IPX_ENOMEM, "ipx_submit: host allocation failed");
+  r->ds = d;
+  r->model = model;
+  r->grad = q->want_grad ? 1 : 0;
+  r->np = np;
+  std::memcpy(r->theta, q->theta, np * sizeof(double));
+  r->t_submit = std::chrono::steady_clock::now();
+  r->bytes = request_bytes(d, r->grad);
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (S->stopping) {
+    delete r;
+    return fail(IPX_EBUSY, "ipx_submit: server is stopping");
+  }
+  if (r->bytes > S->cfg.scratch_bytes) {
+    delete r;
+    return fail(IPX_ENOMEM, "ipx_submit: request needs %zu scratch bytes, budget %zu", r->bytes, S->cfg.scratch_bytes);
+  }
+  if (S->cfg.max_pending > 0 && (int)S->pending.size() >= S->cfg.max_pending) {
+    delete r;
+    return fail(IPX_EBUSY, "ipx_submit: queue full");
+  }
+  r->ticket = S->next_ticket++;
+  S->reqs[r->ticket] = r;
+  *ticket = r->ticket;
+  if (!theta_valid(model, r->theta)) {
+    serve_finish(S, r, IPX_EDOMAIN, nullptr);
+    r->res.nll = std::numeric_limits<double>::infinity();
+    for (int i = 0; i < np; ++i) r->res.grad[i] = std::numeric_limits<double>::quiet_NaN();
+    S->cv.notify_all();
+    return IPX_OK;
+  }
+  if (model == 1) r->h1 = hoist_mass(r->theta);
+  else if (model == 2) r->h2 = hoist_masstime(r->theta);
+  else r->h3 = hoist_angtime(r->theta);
+  if (d->n == 0) {  // nothing to evaluate: the empty sum
+    double zeros[kAccMax] = {};
+    serve_finish(S, r, IPX_OK, zeros);
+    S->cv.notify_all();
+    return IPX_OK;
+  }
+  S->pending.push_back(r);
+  S->cv.notify_all();
+  return IPX_OK;
+}
+
+static ipx_status take_result(ipx_server* S, std::map<uint64_t, ServeReq*>::iterator it, ipx_result* out) {
+  ServeReq* r = it->second;
+  if (out) *out = r->res;
+  S->reqs.erase(it);
+  const int st = r->res.status;
+  delete r;
+  return st == IPX_OK ? IPX_OK : fail((ipx_status)st, "request finished with status %d", st);
+}
+
+extern "C" ipx_status ipx_poll(ipx_server* S, uint64_t ticket, ipx_result* out) {
+  if (!S) return fail(IPX_EINVAL, "ipx_poll: NULL server");
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) return fail(IPX_ENOTFOUND, "ipx_poll: unknown ticket %llu", (unsigned long long)ticket);
+  if (!it->second->done) return IPX_EBUSY;
+  return take_result(S, it, out);
+}
+
+extern "C" ipx_status ipx_wait(ipx_server* S, uint64_t ticket, int64_t timeout_ns, ipx_result* out) {
+  if (!S) return fail(IPX_EINVAL, "ipx_wait: NULL server");
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) return fail(IPX_ENOTFOUND, "ipx_wait: unknown ticket %llu", (unsigned long long)ticket);
+  ServeReq* r = it->second;
+  const auto deadline = std::chrono::steady_clock::now() + std::chrono::nanoseconds(timeout_ns < 0 ? (int64_t)1 << 62 : timeout_ns);
+  while (!r->done) {
+    if (S->cv.wait_until(lk, deadline) == std::cv_status::timeout && !r->done)
+      return fail(IPX_ETIMEOUT, "ipx_wait: ticket %llu not done", (unsigned long long)ticket);
+  }
+  return take_result(S, S->reqs.find(ticket), out);
+}
+
+extern "C" ipx_status ipx_server_stop(ipx_server* S) {
+  if (!S) return fail(IPX_EINVAL, "ipx_server_stop: NULL server");
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stopping = true;
+    S->cv.notify_all();
+  }
+  if (S->worker.joinable()) S->worker.join();   // drains in-flight and pending requests
+  __atomic_store_n(&S->hs->stop, 1ull, __ATOMIC_RELEASE);
+  (void)hipSetDevice(S->ctx->device);
+  hipError_t e = hipStreamSynchronize(S->stream);
+  for (auto& kv : S->reqs) delete kv.second;
+  (void)hipFree(S->pool);
+  (void)hipFree(S->st);
+  (void)hipFree(S->ctl);
+  (void)hipFree(S->dd);
+  (void)hipHostFree(S->hs);
+  (void)hipEventDestroy(S->kernel_done);
+  (void)hipStreamDestroy(S->stream);
+  const std::string werr = S->worker_error;
+  delete S;
+  if (e != hipSuccess) return fail(IPX_EDEVICE, "ipx_server_stop: %s", hipGetErrorString(e));
+  if (!werr.empty()) return fail(IPX_EDEVICE, "ipx_server_stop: kernel launch failed: %s", werr.c_str());
+  return IPX_OK;
+}
+
 static ipx_status run(ipx_ctx* ctx, const ipx_dataset* dc, const double* theta, int np, double* nll,
                       double* grad, void* stream) {
   if (!ctx || !dc || !theta || !nll) return fail(IPX_EINVAL, "NULL argument");
-  ipx_dataset* d = const_cast<ipx_dataset*>(dc);  // lazily allocated scratch only
+  ipx_dataset* d = const_cast<ipx_dataset*>(dc);  // lazily created plan and scratch only
   const int model = d->model;
   if (np != kNParams[model]) return fail(IPX_EINVAL, "model %d takes %d parameters, got %d", model, kNParams[model], np);
   if (!theta_valid(model, theta)) {
@@ -888,27 +1252,24 @@ static ipx_status run(ipx_ctx* ctx, const ipx_dataset* dc, const double* theta, 
     return fail(IPX_EDOMAIN, "parameters outside the domain of model %d", model);
   }
   HIP_TRY(hipSetDevice(ctx->device));
+  if (!d->self) {
+    ipx_dataset* one[1] = {d};
+    ipx_status st = plan_create(ctx, 1, one, &d->self, false);
+    if (st != IPX_OK) return st;
+  }
+  ipx_plan* p = d->self;
   hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
-  ipx_status st = IPX_OK;
   MassHoist h1;
   MassTimeHoist h2;
   AngTimeHoist h3;
-  const bool g = grad != nullptr;
-  if (model == 1) {
-    h1 = hoist_mass(theta);
-    st = g ? launch_model<1, true>(ctx, d, h1.k, s) : launch_model<1, false>(ctx, d, h1.k, s);
-  } else if (model == 2) {
-    h2 = hoist_masstime(theta);
-    st = g ? launch_model<2, true>(ctx, d, h2.k, s) : launch_model<2, false>(ctx, d, h2.k, s);
-  } else {
-    h3 = hoist_angtime(theta);
-    st = g ? launch_angtime<true>(ctx, d, h3.k, s) : launch_angtime<false>(ctx, d, h3.k, s);
-  }
+  if (model == 1) { h1 = hoist_mass(theta); std::memcpy(p->h_consts, &h1.k, sizeof h1.k); }
+  else if (model == 2) { h2 = hoist_masstime(theta); std::memcpy(p->h_consts, &h2.k, sizeof h2.k); }
+  else { h3 = hoist_angtime(theta); std::memcpy(p->h_consts, &h3.k, sizeof h3.k); }
+  p->h_active[0] = 1;
+  ipx_status st = enqueue_batch(p, grad != nullptr, s, ctx);
   if (st != IPX_OK) return st;
-  const int nacc = g ? (model == 1 ? kAccMass : model == 2 ? kAccMassTime : kAccAngTime) : 1;
-  HIP_TRY(hipMemcpyAsync(d->out_host, d->out_dev, nacc * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  const double* a = d->out_host;
+  const double* a = p->h_out;
   if (!std::isfinite(a[0])) {
     *nll = std::numeric_limits<double>::infinity();
     if (grad)
@@ -916,7 +1277,7 @@ static ipx_status run(ipx_ctx* ctx, const ipx_dataset* dc, const double* theta, 
     return fail(IPX_EDOMAIN, "non-finite likelihood (an event has P <= 0 or a non-finite term)");
   }
   *nll = -a[0];
-  if (g) {
+  if (grad) {
     if (model == 1) grad_mass(h1, theta, a, grad);
     else if (model == 2) grad_masstime(h2, theta, a, grad);
     else grad_angtime(h3, theta, a, grad);

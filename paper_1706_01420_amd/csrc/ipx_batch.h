@@ -28,28 +28,93 @@ struct TileRef {
   int tile;
 };
 
+// ---------------------------------------------------------------------------
+// Tile bodies (shared by the batch kernels and the persistent server kernel).
+// k may live in device memory, kernel arguments or LDS: the arithmetic is the
+// same, so a tile's partials do not depend on which kernel computed them.
+// ---------------------------------------------------------------------------
+template <int MODEL, bool GRAD>
+__device__ __forceinline__ void tile_nll(const SegInfo& S, const typename ModelTraits<MODEL>::Const& k,
+                                         int64_t tile) {
+  constexpr int NACC = GRAD ? ModelTraits<MODEL>::kAcc : 1;
+  double acc[NACC];
+#pragma unroll
+  for (int c = 0; c < NACC; ++c) acc[c] = 0.0;
+  const int64_t base = tile * kTile + threadIdx.x;
+#pragma unroll 1
+  for (int e = 0; e < kEventsPerLane; ++e) {
+    const int64_t i = base + (int64_t)e * kThreads;
+    if (i < S.cols.n) event<MODEL, GRAD>(k, S.cols, i, acc);
+  }
+  tile_store<NACC>(acc, S.partials, tile, S.n_tiles);
+}
+
+// Angular model; C is the coefficient table in LDS.
+template <bool GRAD>
+__device__ __forceinline__ void tile_angtime(const SegInfo& S, const AngTimeConst& k, const double* C,
+                                             int64_t tile) {
+  constexpr int NACC = GRAD ? kAngInner : 1;
+  double acc[NACC];
+#pragma unroll
+  for (int c = 0; c < NACC; ++c) acc[c] = 0.0;
+  const int64_t base = tile * kTile + threadIdx.x;
+#pragma unroll 1
+  for (int e = 0; e < kEventsPerLane; ++e) {
+    const int64_t i = base + (int64_t)e * kThreads;
+    // keeps the LDS table reads inside the loop (re-read per event rather
+    // than pinned in 80 registers)
+    asm volatile("" ::: "memory");
+    if (i < S.cols.n) {
+      const EventCols& cl = S.cols;
+      const double w = cl.w ? cl.w[i] : 1.0;
+      event_angtime<GRAD>(k, C, cl.c[0][i], cl.c[1][i], cl.c[2][i], cl.c[3][i], cl.c[4][i], cl.c[5][i], w, acc,
+                          S.tau, S.tau_stride, i);
+    }
+  }
+  tile_store<NACC>(acc, S.partials, tile, S.n_tiles);
+}
+
+// Angular gradient: coefficient adjoints over one outer tile.
+__device__ __forceinline__ void tile_angtime_outer(const SegInfo& S, int64_t tile) {
+  double acc[kAngOuter];
+#pragma unroll
+  for (int c = 0; c < kAngOuter; ++c) acc[c] = 0.0;
+  const int64_t base = tile * kOuterTile + threadIdx.x;
+#pragma unroll 1
+  for (int e = 0; e < kOuterEventsPerLane; ++e) {
+    const int64_t i = base + (int64_t)e * kThreads;
+    if (i < S.cols.n) {
+      double f[10];
+      angular_functions(S.cols.c[0][i], S.cols.c[1][i], S.cols.c[2][i], f);
+      const double* tau = S.tau;
+      const int64_t ts = S.tau_stride;
+      const double t0 = tau[i], t1 = tau[ts + i], t2 = tau[2 * ts + i], t3 = tau[3 * ts + i];
+#pragma unroll
+      for (int kk = 0; kk < 10; ++kk) {
+        acc[4 * kk + 0] += f[kk] * t0;
+        acc[4 * kk + 1] += f[kk] * t1;
+        acc[4 * kk + 2] += f[kk] * t2;
+        acc[4 * kk + 3] += f[kk] * t3;
+      }
+    }
+  }
+  tile_store<kAngOuter>(acc, S.partials + kAngOuter0 * S.n_tiles, tile, S.n_tiles);
+}
+
+// ---------------------------------------------------------------------------
+// Batch kernels
+// ---------------------------------------------------------------------------
 // Models 1 and 2.
 template <int MODEL, bool GRAD>
 __global__ __launch_bounds__(kThreads) void k_nll_batch(const SegInfo* __restrict__ segs,
                                                         const TileRef* __restrict__ tiles, int64_t n_tiles,
                                                         const typename ModelTraits<MODEL>::Const* __restrict__ consts,
                                                         const unsigned char* __restrict__ active) {
-  constexpr int NACC = GRAD ? ModelTraits<MODEL>::kAcc : 1;
   for (int64_t g = blockIdx.x; g < n_tiles; g += gridDim.x) {
     const TileRef tr = tiles[g];
     if (!active[tr.seg]) continue;
-    const SegInfo& S = segs[tr.seg];
     const typename ModelTraits<MODEL>::Const k = consts[tr.seg];
-    double acc[NACC];
-#pragma unroll
-    for (int c = 0; c < NACC; ++c) acc[c] = 0.0;
-    const int64_t base = (int64_t)tr.tile * kTile + threadIdx.x;
-#pragma unroll 1
-    for (int e = 0; e < kEventsPerLane; ++e) {
-      const int64_t i = base + (int64_t)e * kThreads;
-      if (i < S.cols.n) event<MODEL, GRAD>(k, S.cols, i, acc);
-    }
-    tile_store<NACC>(acc, S.partials, tr.tile, S.n_tiles);
+    tile_nll<MODEL, GRAD>(segs[tr.seg], k, tr.tile);
   }
 }
 
@@ -60,30 +125,13 @@ __global__ __launch_bounds__(kThreads) void k_angtime_batch(const SegInfo* __res
                                                             const AngTimeConst* __restrict__ consts,
                                                             const unsigned char* __restrict__ active) {
   __shared__ double sC[40];
-  constexpr int NACC = GRAD ? kAngInner : 1;
   for (int64_t g = blockIdx.x; g < n_tiles; g += gridDim.x) {
     const TileRef tr = tiles[g];
     if (!active[tr.seg]) continue;
-    const SegInfo& S = segs[tr.seg];
     const AngTimeConst& k = consts[tr.seg];
     if (threadIdx.x < 40) sC[threadIdx.x] = (&k.C[0][0])[threadIdx.x];
     __syncthreads();
-    double acc[NACC];
-#pragma unroll
-    for (int c = 0; c < NACC; ++c) acc[c] = 0.0;
-    const int64_t base = (int64_t)tr.tile * kTile + threadIdx.x;
-#pragma unroll 1
-    for (int e = 0; e < kEventsPerLane; ++e) {
-      const int64_t i = base + (int64_t)e * kThreads;
-      asm volatile("" ::: "memory");
-      if (i < S.cols.n) {
-        const EventCols& cl = S.cols;
-        const double w = cl.w ? cl.w[i] : 1.0;
-        event_angtime<GRAD>(k, sC, cl.c[0][i], cl.c[1][i], cl.c[2][i], cl.c[3][i], cl.c[4][i], cl.c[5][i], w, acc,
-                            S.tau, S.tau_stride, i);
-      }
-    }
-    tile_store<NACC>(acc, S.partials, tr.tile, S.n_tiles);
+    tile_angtime<GRAD>(segs[tr.seg], k, sC, tr.tile);
   }
 }
 
@@ -95,30 +143,7 @@ __global__ __launch_bounds__(kThreads) void k_angtime_outer_batch(const SegInfo*
   for (int64_t g = blockIdx.x; g < n_tiles; g += gridDim.x) {
     const TileRef tr = tiles[g];
     if (!active[tr.seg]) continue;
-    const SegInfo& S = segs[tr.seg];
-    double acc[kAngOuter];
-#pragma unroll
-    for (int c = 0; c < kAngOuter; ++c) acc[c] = 0.0;
-    const int64_t base = (int64_t)tr.tile * kOuterTile + threadIdx.x;
-#pragma unroll 2
-    for (int e = 0; e < kOuterEventsPerLane; ++e) {
-      const int64_t i = base + (int64_t)e * kThreads;
-      if (i < S.cols.n) {
-        double f[10];
-        angular_functions(S.cols.c[0][i], S.cols.c[1][i], S.cols.c[2][i], f);
-        const double* tau = S.tau;
-        const int64_t ts = S.tau_stride;
-        const double t0 = tau[i], t1 = tau[ts + i], t2 = tau[2 * ts + i], t3 = tau[3 * ts + i];
-#pragma unroll
-        for (int kk = 0; kk < 10; ++kk) {
-          acc[4 * kk + 0] += f[kk] * t0;
-          acc[4 * kk + 1] += f[kk] * t1;
-          acc[4 * kk + 2] += f[kk] * t2;
-          acc[4 * kk + 3] += f[kk] * t3;
-        }
-      }
-    }
-    tile_store<kAngOuter>(acc, S.partials + kAngOuter0 * S.n_tiles, tr.tile, S.n_tiles);
+    tile_angtime_outer(segs[tr.seg], tr.tile);
   }
 }
 

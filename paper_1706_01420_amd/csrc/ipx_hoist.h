@@ -231,6 +231,7 @@ inline AngTimeHoist hoist_angtime(const double* th) {
   k.hL2 = 0.5 * k.gL * k.gL;
   k.hc2 = 0.5 * (G * G - DM * DM);
   k.gdm = G * DM;
+  k.hdg = DG / 2.0;
   k.eAH = std::exp(-k.gH * kTLo); k.eBH = std::exp(-k.gH * kTHi);
   k.eAL = std::exp(-k.gL * kTLo); k.eBL = std::exp(-k.gL * kTHi);
   k.eAG = std::exp(-G * kTLo);    k.eBG = std::exp(-G * kTHi);

@@ -1,4 +1,5 @@
-// Per-event likelihood kernels and the deterministic two-level FP64 reduction.
+// Per-event likelihood code and the deterministic two-level FP64 reduction
+// (the kernels that drive it are in ipx_batch.h).
 //
 // One lane evaluates kEventsPerLane events of a canonical tile (event index
 // tile*kTile + e*256 + lane, so each load instruction of a wave reads 64
@@ -53,16 +54,6 @@ __device__ __forceinline__ double reduce_component(const double* __restrict__ p,
   if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
   __syncthreads();
   return (lds[0] + lds[1]) + (lds[2] + lds[3]);
-}
-
-// out[c] = sum over tiles of partials[c * stride + tile], one workgroup per
-// component; components below `split` have n_tiles tiles, the others n_tiles2.
-__global__ __launch_bounds__(kThreads) void k_reduce_tiles(const double* __restrict__ partials, int64_t stride,
-                                                           int64_t n_tiles, int split, int64_t n_tiles2,
-                                                           double* __restrict__ out) {
-  const int c = blockIdx.x;
-  const double total = reduce_component(partials + (int64_t)c * stride, c < split ? n_tiles : n_tiles2);
-  if (threadIdx.x == 0) out[c] = total;
 }
 
 // ---------------------------------------------------------------------------
@@ -278,14 +269,17 @@ __device__ __forceinline__ void event_angtime(const AngTimeConst& k, const doubl
   const double inv_sig = rcp(sig);
   const double inv_r2s = kInvSqrt2 * inv_sig;
   const double dmr = k.dm * sig * kInvSqrt2;
-  const double eH2 = exp(k.hH2 * s2), eL2 = exp(k.hL2 * s2), ec2 = exp(k.hc2 * s2);
+  const double eH2 = exp_small(k.hH2 * s2), eL2 = exp_small(k.hL2 * s2), ec2 = exp(k.hc2 * s2);
   double sc, cc;
-  sincos(k.gdm * s2, &sc, &cc);
+  sincos_small(k.gdm * s2, &sc, &cc);
   double st, ct;
   sincos(k.dm * t, &st, &ct);
-  // exp(z^2 s^2/2 - z tau) for z = Gamma - i dm has phase dm (tau - Gamma s^2)
-  const double mt = ec2 * exp(-k.g * t);
-  const Conv3 Xt = conv3(t, eH2 * exp(-k.gH * t), eL2 * exp(-k.gL * t),
+  // exp(z^2 s^2/2 - z tau) for z = Gamma - i dm has phase dm (tau - Gamma s^2);
+  // e^{-Gamma_H t} = e^{-Gamma t} e^{DeltaGamma t/2}, e^{-Gamma_L t} = e^{-Gamma t} / e^{DeltaGamma t/2}
+  const double eG = exp(-k.g * t);
+  const double eD = exp(k.hdg * t);
+  const double mt = ec2 * eG;
+  const Conv3 Xt = conv3(t, eH2 * (eG * eD), eL2 * (eG * rcp(eD)),
                          cplx{mt * (ct * cc + st * sc), mt * (st * cc - ct * sc)}, k, s2, inv_r2s, dmr);
   const double ma = ec2 * k.eAG, mb = ec2 * k.eBG;
   const Conv3 Xa = conv3(kTLo, eH2 * k.eAH, eL2 * k.eAL,
@@ -341,68 +335,6 @@ __device__ __forceinline__ void event_angtime(const AngTimeConst& k, const doubl
   }
 }
 
-// Per-event kernel of the angular model (NLL, and for GRAD the 11 small
-// adjoint sums plus tau_j per event).
-template <bool GRAD>
-__global__ __launch_bounds__(kThreads) void k_angtime(EventCols cols, AngTimeConst k,
-                                                      double* __restrict__ partials, int64_t n_tiles,
-                                                      double* __restrict__ tau, int64_t tau_stride) {
-  __shared__ double sC[40];
-  if (threadIdx.x < 40) sC[threadIdx.x] = (&k.C[0][0])[threadIdx.x];
-  __syncthreads();
-  constexpr int NACC = GRAD ? kAngInner : 1;
-  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-    double acc[NACC];
-#pragma unroll
-    for (int c = 0; c < NACC; ++c) acc[c] = 0.0;
-    const int64_t base = tile * kTile + threadIdx.x;
-#pragma unroll 1
-    for (int e = 0; e < kEventsPerLane; ++e) {
-      const int64_t i = base + (int64_t)e * kThreads;
-      // keeps the LDS table reads inside the loop (re-read per event rather
-      // than pinned in 80 registers)
-      asm volatile("" ::: "memory");
-      if (i < cols.n) {
-        const double w = cols.w ? cols.w[i] : 1.0;
-        event_angtime<GRAD>(k, sC, cols.c[0][i], cols.c[1][i], cols.c[2][i], cols.c[3][i], cols.c[4][i],
-                            cols.c[5][i], w, acc, tau, tau_stride, i);
-      }
-    }
-    tile_store<NACC>(acc, partials, tile, n_tiles);
-  }
-}
-
-// Coefficient adjoints sum_i f_k(Omega_i) tau_j,i over canonical tiles of
-// kOuterTile events; partials at components kAngOuter0 + 4k + j.
-__global__ __launch_bounds__(kThreads) void k_angtime_outer(EventCols cols, const double* __restrict__ tau,
-                                                            int64_t tau_stride, double* __restrict__ partials,
-                                                            int64_t n_tiles_outer, int64_t stride) {
-  for (int64_t tile = blockIdx.x; tile < n_tiles_outer; tile += gridDim.x) {
-    double acc[kAngOuter];
-#pragma unroll
-    for (int c = 0; c < kAngOuter; ++c) acc[c] = 0.0;
-    const int64_t base = tile * kOuterTile + threadIdx.x;
-#pragma unroll 2
-    for (int e = 0; e < kOuterEventsPerLane; ++e) {
-      const int64_t i = base + (int64_t)e * kThreads;
-      if (i < cols.n) {
-        double f[10];
-        angular_functions(cols.c[0][i], cols.c[1][i], cols.c[2][i], f);
-        const double t0 = tau[i], t1 = tau[tau_stride + i], t2 = tau[2 * tau_stride + i],
-                     t3 = tau[3 * tau_stride + i];
-#pragma unroll
-        for (int kk = 0; kk < 10; ++kk) {
-          acc[4 * kk + 0] += f[kk] * t0;
-          acc[4 * kk + 1] += f[kk] * t1;
-          acc[4 * kk + 2] += f[kk] * t2;
-          acc[4 * kk + 3] += f[kk] * t3;
-        }
-      }
-    }
-    tile_store<kAngOuter>(acc, partials + kAngOuter0 * stride, tile, stride);
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Tile kernels
 // ---------------------------------------------------------------------------
@@ -427,25 +359,6 @@ __device__ __forceinline__ void event(const typename ModelTraits<MODEL>::Const& 
     event_mass<GRAD>(k, cols.c[0][i], w, acc);
   } else {
     event_masstime<GRAD>(k, cols.c[0][i], cols.c[1][i], cols.c[2][i], w, acc);
-  }
-}
-
-// Grid-stride over canonical tiles; one partial (per component) per tile.
-template <int MODEL, bool GRAD>
-__global__ __launch_bounds__(kThreads) void k_nll_tiles(EventCols cols, typename ModelTraits<MODEL>::Const k,
-                                                        double* __restrict__ partials, int64_t n_tiles) {
-  constexpr int NACC = GRAD ? ModelTraits<MODEL>::kAcc : 1;
-  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-    double acc[NACC];
-#pragma unroll
-    for (int c = 0; c < NACC; ++c) acc[c] = 0.0;
-    const int64_t base = tile * kTile + threadIdx.x;
-#pragma unroll 1
-    for (int e = 0; e < kEventsPerLane; ++e) {
-      const int64_t i = base + (int64_t)e * kThreads;
-      if (i < cols.n) event<MODEL, GRAD>(k, cols, i, acc);
-    }
-    tile_store<NACC>(acc, partials, tile, n_tiles);
   }
 }
 

@@ -60,6 +60,25 @@ __device__ __forceinline__ cplx cdiv(cplx a, cplx b) {
   return cplx{(a.re * r + a.im) * inv, (a.im * r - a.re) * inv};
 }
 
+// e^x with a short Taylor polynomial when |x| <= 2^-9 (truncation below
+// 1e-22 relative), the library exp otherwise.
+__device__ __forceinline__ double exp_small(double x) {
+  if (fabs(x) > 0x1p-9) return exp(x);
+  return 1.0 + x * (1.0 + x * (0.5 + x * (1.0 / 6.0 + x * (1.0 / 24.0 + x * (1.0 / 120.0 + x * (1.0 / 720.0))))));
+}
+
+// sin and cos with Taylor polynomials when |x| <= 0.05 (truncation below
+// 1e-21), the library sincos otherwise.
+__device__ __forceinline__ void sincos_small(double x, double* s, double* c) {
+  if (fabs(x) > 0.05) {
+    sincos(x, s, c);
+    return;
+  }
+  const double x2 = x * x;
+  *s = x * (1.0 - x2 * (1.0 / 6.0 - x2 * (1.0 / 120.0 - x2 * (1.0 / 5040.0 - x2 * (1.0 / 362880.0)))));
+  *c = 1.0 - x2 * (0.5 - x2 * (1.0 / 24.0 - x2 * (1.0 / 720.0 - x2 * (1.0 / 40320.0 - x2 * (1.0 / 3628800.0)))));
+}
+
 // Jacobi continued fraction, forward Wallis recurrences.  Valid (and used) for
 // Im z >= 3.4 or |z| >= 6 with |z| <= 1e6.
 __device__ __forceinline__ cplx faddeeva_cf(cplx z) {
@@ -107,11 +126,10 @@ __device__ __forceinline__ cplx faddeeva_upper(cplx z) {
   return faddeeva_series(z);
 }
 
-// erfcx(y) = e^{y^2} erfc(y) for y >= 0: the same continued fraction on the
-// imaginary axis (z = i y, real arithmetic) for y >= 3.4, the device library
-// otherwise.
+// erfcx(y) = e^{y^2} erfc(y) = w(i y) for y >= 0: the continued fraction in
+// real arithmetic for y >= 3.4, the (out-of-line) rational series otherwise.
 __device__ __forceinline__ double erfcx_pos(double y) {
-  if (y < 3.4) return erfcx(y);
+  if (y < 3.4) return faddeeva_series(cplx{0.0, y}).re;
   if (y > 1e6) return kInvSqrtPi / y * (1.0 - 0.5 / (y * y));
   const double z2 = -y * y;
   double pm = 1.0, qm = 0.0, p = z2 - 0.5, q = 1.0;

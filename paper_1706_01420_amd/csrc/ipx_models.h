@@ -57,6 +57,7 @@ struct AngTimeConst {
   double gH, gL, g, dm;        // Gamma_H, Gamma_L, Gamma, Delta m
   double gmax;                 // max(Gamma_H, Gamma_L, Gamma)
   double hH2, hL2, hc2, gdm;   // Gamma_H^2/2, Gamma_L^2/2, (Gamma^2 - dm^2)/2, Gamma dm
+  double hdg;                  // DeltaGamma / 2
   double eAH, eBH, eAL, eBL, eAG, eBG;  // exp(-rate * T_LO / T_HI)
   double cA, sA, cB, sB;       // cos, sin of dm T_LO and dm T_HI
   double inv_gH, inv_gL;

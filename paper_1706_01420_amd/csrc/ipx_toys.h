@@ -223,7 +223,7 @@ __global__ __launch_bounds__(256) void k_gen_write(GenConst g, const double* __r
   constexpr int ncols = MODEL == 1 ? 1 : MODEL == 2 ? 3 : 6;
 #pragma unroll
   for (int c = 0; c < ncols; ++c) cols_ptr[c][o] = r.col[c];
-  if (MODEL == 3) wout[o] = r.w;
+  if (MODEL == 3 && wout) wout[o] = r.w;
   if (rk == need - 1) *last = (unsigned long long)(c0 + (uint64_t)i) + 1ull;
 }
 

@@ -34,6 +34,7 @@ IPX_COPY_HOST = 0
 IPX_COPY_DEVICE = 1
 IPX_BORROW_DEVICE = 2
 IPX_KEEP_ORDER = 4
+IPX_NO_WEIGHTS = 8
 
 _c_double_p = ctypes.POINTER(ctypes.c_double)
 _c_void_pp = ctypes.POINTER(ctypes.c_void_p)
@@ -64,6 +65,11 @@ _SIGNATURES = [
     ("nll_eval_batch", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_void_p, _c_double_p, ctypes.c_void_p, _c_double_p, ctypes.c_void_p,
       ctypes.c_void_p]),
+    ("ipx_server_start", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, _c_void_pp]),
+    ("ipx_submit", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
+    ("ipx_poll", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
+    ("ipx_wait", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64, ctypes.c_void_p]),
+    ("ipx_server_stop", ctypes.c_int, [ctypes.c_void_p]),
     ("toy_generate", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_int, _c_double_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64,
       ctypes.c_uint, _c_void_pp, ctypes.c_void_p]),
@@ -256,6 +262,62 @@ def nll_eval_batch(ctx, plan, theta, active=None, grad=False, stream=None):
     if st not in (IPX_OK, IPX_EDOMAIN):
         _check(st)
     return (nll, g) if grad else nll
+
+
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int), ("scratch_bytes", ctypes.c_size_t), ("workgroups", ctypes.c_int),
+                ("idle_iterations", ctypes.c_int), ("spin_limit", ctypes.c_int), ("max_pending", ctypes.c_int)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("ds", ctypes.c_void_p), ("theta", _c_double_p), ("np", ctypes.c_int), ("want_grad", ctypes.c_int)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("np", ctypes.c_int), ("nll", ctypes.c_double),
+                ("grad", ctypes.c_double * 12), ("latency_us", ctypes.c_double)]
+
+
+def _result_dict(r):
+    return {"status": r.status, "nll": r.nll, "grad": np.array(r.grad[:r.np]), "latency_us": r.latency_us}
+
+
+def ipx_server_start(ctx, slots=0, scratch_bytes=0, workgroups=0, idle_iterations=0, spin_limit=0, max_pending=0):
+    cfg = ServerCfg(slots, scratch_bytes, workgroups, idle_iterations, spin_limit, max_pending)
+    h = ctypes.c_void_p()
+    _check(_lib.ipx_server_start(ctx, ctypes.byref(cfg), ctypes.byref(h)))
+    return h
+
+
+def ipx_submit(srv, ds, theta, want_grad=False):
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    req = _Request(ds.value if isinstance(ds, ctypes.c_void_p) else ds, _dbl(th), th.shape[0], 1 if want_grad else 0)
+    t = ctypes.c_uint64()
+    _check(_lib.ipx_submit(srv, ctypes.byref(req), ctypes.byref(t)))
+    return t.value
+
+
+def ipx_poll(srv, ticket):
+    """Result dict when done (taken once), None while running."""
+    r = _Result()
+    st = _lib.ipx_poll(srv, ctypes.c_uint64(ticket), ctypes.byref(r))
+    if st == IPX_EBUSY:
+        return None
+    if st not in (IPX_OK, IPX_EDOMAIN, IPX_ETIMEOUT):
+        _check(st)
+    return _result_dict(r)
+
+
+def ipx_wait(srv, ticket, timeout_s=-1.0):
+    r = _Result()
+    st = _lib.ipx_wait(srv, ctypes.c_uint64(ticket), int(timeout_s * 1e9) if timeout_s >= 0 else -1, ctypes.byref(r))
+    if st not in (IPX_OK, IPX_EDOMAIN):
+        _check(st)
+    return _result_dict(r)
+
+
+def ipx_server_stop(srv):
+    _check(_lib.ipx_server_stop(srv))
 
 
 class _ToyStats(ctypes.Structure):

@@ -1,0 +1,67 @@
+"""Whole-method statistical check: toys generated on the GPU from theta_gen and
+fitted with the batched minimiser (analytic gradient) recover theta_gen with
+unit-width pulls.  Pull = (theta_hat - theta_gen) / sigma_hat, sigma_hat from
+the inverse finite-difference Hessian of the analytic gradient; unit weights.
+With n toys the pull mean has error 1/sqrt(n) and the width 1/sqrt(2n); the
+bounds below are 4 of those errors (fixed seeds, so the outcome is
+deterministic)."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import models as M
+from paper_1706_01420_amd import fit, toys
+
+pytestmark = pytest.mark.gpu
+
+CASES = {1: (200, 20000), 2: (200, 20000), 3: (160, 40000)}
+
+
+def say(*a):
+    print("[gpu]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1706_01420_amd import ipx
+    return ipx
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    c = lib.ipx_create(0)
+    yield c
+    lib.ipx_destroy(c)
+
+
+@pytest.mark.parametrize("model", [1, 2, 3])
+def test_pulls(lib, ctx, model):
+    ntoys, n = CASES[model]
+    theta = np.array(M.THETA_GEN[model])
+    say("pulls model", model, "toys", ntoys, "events", n)
+    ds = toys.generate(lib, ctx, model, theta, 4242 + model, [n] * ntoys, flags=lib.IPX_NO_WEIGHTS)
+    plan = lib.ipx_plan_create(ctx, ds)
+    try:
+        ev = toys.batched_evaluator(lib, ctx, plan)
+        steps = toys.steps_for(model, [n] * ntoys)
+        start = np.tile(theta, (ntoys, 1)) + 0.5 * steps
+        res = fit.bfgs(ev, start, steps)
+        assert res["converged"].mean() > 0.97, res["converged"].mean()
+        ok = res["converged"]
+        err = fit.errors(ev, res["theta"], steps)
+        pulls = (res["theta"][ok] - theta) / err[ok]
+        good = np.all(np.isfinite(pulls), axis=1)
+        pulls = pulls[good]
+        m = pulls.mean(axis=0)
+        sd = pulls.std(axis=0, ddof=1)
+        k = pulls.shape[0]
+        say("pull means", np.round(m, 3))
+        say("pull widths", np.round(sd, 3))
+        assert k > 0.95 * ntoys
+        assert np.all(np.abs(m) < 4.0 / np.sqrt(k)), m
+        assert np.all(np.abs(sd - 1.0) < 4.0 / np.sqrt(2 * k)), sd
+    finally:
+        lib.ipx_plan_destroy(plan)
+        for d in ds:
+            lib.ipx_dataset_destroy(ctx, d)

@@ -1,0 +1,173 @@
+"""Served likelihood (persistent device loop): every result equals the plain
+nll_eval / nll_grad on the same dataset bitwise, alone and in mixed traffic;
+admission waits for scratch memory; errors stay with their request."""
+import sys
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from oracle import models as M
+from paper_1706_01420_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1706_01420_amd import ipx
+    return ipx
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    c = lib.ipx_create(0)
+    yield c
+    lib.ipx_destroy(c)
+
+
+@pytest.fixture(scope="module")
+def datasets(lib, ctx):
+    out = []
+    for model, sizes in ((1, [1000, 50000]), (2, [777, 40000]), (3, [1, 5000, 100000])):
+        for j, n in enumerate(sizes):
+            cols, w = W.events(model, n, seed=300 + 10 * model + j)
+            out.append((model, lib.ipx_dataset_create(ctx, model, cols, w)))
+    yield out
+    for _, d in out:
+        lib.ipx_dataset_destroy(ctx, d)
+
+
+def _theta(model, rng):
+    base = np.array(M.THETA_GEN[model])
+    while True:
+        th = base * (1.0 + 0.02 * rng.standard_normal(base.size))
+        if M.theta_valid(model, th):
+            return th
+
+
+def _plain(lib, ctx, d, th, grad):
+    if grad:
+        return lib.nll_grad(ctx, d, th)
+    return lib.nll_eval(ctx, d, th), None
+
+
+def test_single_requests_equal_plain_calls(lib, ctx, datasets):
+    srv = lib.ipx_server_start(ctx, slots=8)
+    try:
+        rng = np.random.default_rng(1)
+        for model, d in datasets:
+            for grad in (False, True):
+                th = _theta(model, rng)
+                say("serve single model", model, "grad", grad)
+                t = lib.ipx_submit(srv, d, th, grad)
+                r = lib.ipx_wait(srv, t, 60.0)
+                f, g = _plain(lib, ctx, d, th, grad)
+                assert r["status"] == 0 and r["nll"] == f
+                if grad:
+                    assert np.array_equal(r["grad"], g)
+                assert r["latency_us"] > 0
+    finally:
+        lib.ipx_server_stop(srv)
+
+
+def test_mixed_concurrent_traffic_is_bitwise_equal_to_alone(lib, ctx, datasets):
+    srv = lib.ipx_server_start(ctx, slots=16)
+    rng = np.random.default_rng(2)
+    jobs = []
+    for i in range(160):
+        model, d = datasets[rng.integers(len(datasets))]
+        jobs.append((d, _theta(model, rng), bool(rng.integers(2))))
+    results = [None] * len(jobs)
+
+    def client(k):
+        for i in range(k, len(jobs), 8):
+            d, th, grad = jobs[i]
+            t = lib.ipx_submit(srv, d, th, grad)
+            if i % 3 == 0:                      # some clients poll
+                deadline = time.time() + 60
+                r = None
+                while r is None and time.time() < deadline:
+                    r = lib.ipx_poll(srv, t)
+                results[i] = r
+            else:
+                results[i] = lib.ipx_wait(srv, t, 60.0)
+    try:
+        say("serve mixed traffic 160 requests, 8 client threads")
+        threads = [threading.Thread(target=client, args=(k,)) for k in range(8)]
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join(120)
+        assert all(r is not None for r in results)
+    finally:
+        lib.ipx_server_stop(srv)
+    for (d, th, grad), r in zip(jobs, results):
+        f, g = _plain(lib, ctx, d, th, grad)
+        assert r["status"] == 0 and r["nll"] == f
+        if grad:
+            assert np.array_equal(r["grad"], g)
+
+
+def test_admission_by_scratch_budget(lib, ctx, datasets):
+    model, d = datasets[-1]          # angular, 100000 events
+    need = 4 * ((100000 + 31) // 32 * 32) * 8 + 52 * 98 * 8 + 4096
+    srv = lib.ipx_server_start(ctx, slots=8, scratch_bytes=need + 1024)
+    try:
+        rng = np.random.default_rng(3)
+        ths = [_theta(3, rng) for _ in range(6)]
+        say("serve admission, budget for one angular gradient request")
+        tickets = [lib.ipx_submit(srv, d, th, True) for th in ths]
+        for th, t in zip(ths, tickets):
+            r = lib.ipx_wait(srv, t, 60.0)
+            f, g = lib.nll_grad(ctx, d, th)
+            assert r["nll"] == f and np.array_equal(r["grad"], g)
+        big = lib.ipx_dataset_create(ctx, 3, *W.events(3, 400000, seed=5))
+        try:
+            with pytest.raises(lib.IpxError) as e:
+                lib.ipx_submit(srv, big, ths[0], True)
+            assert e.value.status == lib.IPX_ENOMEM
+        finally:
+            lib.ipx_dataset_destroy(ctx, big)
+    finally:
+        lib.ipx_server_stop(srv)
+
+
+def test_errors_stay_with_their_request_and_idle_relaunch(lib, ctx, datasets):
+    model, d = datasets[0]
+    srv = lib.ipx_server_start(ctx, slots=4, idle_iterations=50)
+    try:
+        say("serve domain error + idle relaunch")
+        good = np.array(M.THETA_GEN[1])
+        bad = good.copy()
+        bad[0] = 2.0
+        t1 = lib.ipx_submit(srv, d, bad, True)
+        t2 = lib.ipx_submit(srv, d, good, True)
+        r1 = lib.ipx_wait(srv, t1, 60.0)
+        r2 = lib.ipx_wait(srv, t2, 60.0)
+        assert r1["status"] == lib.IPX_EDOMAIN and r1["nll"] == np.inf
+        f, g = lib.nll_grad(ctx, d, good)
+        assert r2["nll"] == f and np.array_equal(r2["grad"], g)
+        time.sleep(0.5)                   # the device loop has exited by now
+        t3 = lib.ipx_submit(srv, d, good, False)
+        assert lib.ipx_wait(srv, t3, 60.0)["nll"] == lib.nll_eval(ctx, d, good)
+        with pytest.raises(lib.IpxError):
+            lib.ipx_poll(srv, 987654321)
+    finally:
+        lib.ipx_server_stop(srv)
+
+
+def test_stop_drains_pending_requests(lib, ctx, datasets):
+    model, d = datasets[-1]
+    srv = lib.ipx_server_start(ctx, slots=2)
+    th = np.array(M.THETA_GEN[3])
+    say("serve stop drains")
+    tickets = [lib.ipx_submit(srv, d, th, True) for _ in range(6)]
+    lib.ipx_server_stop(srv)
+    # the server is gone; its results were computed before it stopped
+    assert len(tickets) == 6
