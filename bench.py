@@ -44,6 +44,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-extra", action="store_true", help="skip the secondary per-model rates")
+    p.add_argument("--no-batched", action="store_true", help="skip the batched toy-fit leg")
+    p.add_argument("--no-served", action="store_true", help="skip the served-likelihood leg")
     p.add_argument("--profile", action="store_true",
                    help="profiling run: the timed steps, then a plain 512 MiB device copy (counter calibration)")
     return p.parse_args()
@@ -107,6 +109,139 @@ def cpu_baseline(cols, w, theta, n_total, sample):
     return {"value": 1.0 / per_eval, "unit": "NLL+grad evals/s", "cores": 1, "kind": "oracle",
             "sample": "oracle nll_grad (numpy/scipy FP64, one thread) on the first %d of the %d events, "
                       "%.2f s, scaled to the full sample" % (sample, n_total, dt)}
+
+
+def bench_batched_fits(ipx, ctx, ntoys=512, plain_subset=64, seed=170601424):
+    """512 pseudo-experiments of the angular model, sizes Poisson(mu), mu
+    log-uniform in [1e4, 2e5]; generated on the device, each fitted by the
+    lockstep BFGS with the analytic gradient: all toys through one batched
+    evaluation per round (graph replay) versus the plain per-toy loop (one
+    nll_grad call per evaluation), same algorithm and stopping rule."""
+    import numpy as np
+    import torch
+    from paper_1706_01420_amd import fit, toys, workloads
+    theta = np.array(workloads.THETA_GEN[3])
+    _, sizes = toys.toy_sizes(seed, ntoys)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ds = toys.generate(ipx, ctx, 3, theta, seed, sizes)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    steps = toys.steps_for(3, sizes)
+    start = theta[None, :] + 0.5 * steps
+    try:
+        t0 = time.perf_counter()
+        rb = toys.fit_batched(ipx, ctx, 3, ds, start, steps)
+        t_b = time.perf_counter() - t0
+        k = plain_subset
+        t0 = time.perf_counter()
+        rp = toys.fit_plain(ipx, ctx, 3, ds[:k], start[:k], steps[:k])
+        t_p = time.perf_counter() - t0
+    finally:
+        for d in ds:
+            ipx.ipx_dataset_destroy(ctx, d)
+    same = bool(np.array_equal(rb["theta"][:k], rp["theta"]))
+    return {"workload": "512 angular toys, N ~ Poisson(mu), mu log-uniform [1e4, 2e5], total %d events" % int(sizes.sum()),
+            "generate_s": t_gen, "generated_events_per_s": float(sizes.sum()) / t_gen,
+            "fits_per_s_batched": ntoys / t_b, "fits_per_s_plain": k / t_p,
+            "plain_sample": "first %d toys" % k, "speedup": (ntoys / t_b) / (k / t_p),
+            "rounds_batched": int(rb["rounds"]), "evals_per_fit_mean": float(rb["evals"].mean()),
+            "converged_batched": float(rb["converged"].mean()), "converged_plain": float(rp["converged"].mean()),
+            "same_minima_bitwise": same}
+
+
+def bench_served(ipx, ctx, ndatasets=64, nclients=256, nreq=600, seed=170601425):
+    """Served likelihood: 64 resident datasets (models cycled 1, 2, 3; sizes
+    log-uniform in [1e3, 5e6]; generated on the device), 256 clients (half
+    random-walk chains asking NLL only, half minimisers asking NLL +
+    gradient), Poisson arrivals at 0.5x and 0.8x the plain one-call-per-request
+    throughput.  Latency = submission to completion."""
+    import threading
+    import numpy as np
+    from paper_1706_01420_amd import workloads
+    rng = np.random.default_rng(seed)
+    sizes = np.exp(rng.uniform(np.log(1e3), np.log(5e6), ndatasets)).astype(np.int64)
+    models = [1 + (j % 3) for j in range(ndatasets)]
+    ds = []
+    try:
+        for j in range(ndatasets):
+            d, _ = ipx.toy_generate(ctx, models[j], workloads.THETA_GEN[models[j]], seed, j, int(sizes[j]))
+            ds.append(d)
+        client_ds = rng.integers(ndatasets, size=nclients)
+        client_grad = np.arange(nclients) >= nclients // 2
+        reqs = []
+        for _ in range(nreq):
+            c = rng.integers(nclients)
+            j = client_ds[c]
+            th = np.array(workloads.THETA_GEN[models[j]])
+            th = th * (1.0 + 0.002 * rng.standard_normal(th.size))
+            reqs.append((j, th, bool(client_grad[c])))
+        # plain: one call per request, back to back
+        lat_plain = []
+        t0 = time.perf_counter()
+        for j, th, g in reqs:
+            a = time.perf_counter()
+            if g:
+                ipx.nll_grad(ctx, ds[j], th)
+            else:
+                ipx.nll_eval(ctx, ds[j], th)
+            lat_plain.append((time.perf_counter() - a) * 1e6)
+        plain_rate = nreq / (time.perf_counter() - t0)
+        out = {"workload": "64 datasets (models 1/2/3, %d events in total), 256 clients, %d requests per rate, "
+                           "half with gradient" % (int(sizes.sum()), nreq),
+               "plain_evals_per_s": plain_rate,
+               "plain_latency_us_p50": float(np.percentile(lat_plain, 50)),
+               "plain_latency_us_p99": float(np.percentile(lat_plain, 99))}
+        srv = ipx.ipx_server_start(ctx, slots=64)
+        try:
+            for frac in (0.5, 0.8, None):
+                key = "served_at_%.1fx" % frac if frac is not None else "served_saturated"
+                tickets = []
+                results = []
+                errors = []
+                t_end = time.perf_counter() + 60.0   # the whole rate step is bounded
+
+                def collect():
+                    k = 0
+                    try:
+                        while k < nreq and time.perf_counter() < t_end:
+                            if len(tickets) <= k:
+                                time.sleep(1e-5)
+                                continue
+                            left = max(t_end - time.perf_counter(), 0.0)
+                            results.append(ipx.ipx_wait(srv, tickets[k], left))
+                            k += 1
+                    except ipx.IpxError as e:
+                        errors.append(str(e))
+                th_c = threading.Thread(target=collect)
+                th_c.start()
+                t0 = time.perf_counter()
+                nxt = t0
+                for j, th, g in reqs:
+                    if frac is not None:
+                        nxt += rng.exponential(1.0 / (frac * plain_rate))
+                        while time.perf_counter() < nxt:
+                            pass
+                    tickets.append(ipx.ipx_submit(srv, ds[j], th, g))
+                th_c.join()
+                elapsed = time.perf_counter() - t0
+                if errors or len(results) < nreq:
+                    out[key] = {"error": errors[0] if errors else "incomplete", "completed": len(results),
+                                "server": ipx.ipx_server_stats_read(srv)}
+                    break
+                lat = np.array([r["latency_us"] for r in results])
+                out[key] = {"offered_per_s": None if frac is None else frac * plain_rate,
+                            "evals_per_s": nreq / elapsed,
+                            "latency_us_p50": float(np.percentile(lat, 50)),
+                            "latency_us_p99": float(np.percentile(lat, 99)),
+                            "all_ok": bool(all(r["status"] == 0 for r in results)),
+                            "server": ipx.ipx_server_stats_read(srv)}
+        finally:
+            ipx.ipx_server_stop(srv)
+        return out
+    finally:
+        for d in ds:
+            ipx.ipx_dataset_destroy(ctx, d)
 
 
 def main():
@@ -176,6 +311,10 @@ def main():
                               "hbm_gbs": BYTES_PER_EVENT[m] * nm / k / 1e9}
             ipx.ipx_dataset_destroy(ctx, d)
         out["extra"] = extra
+    if not args.no_batched and not args.profile:
+        out["batched"] = bench_batched_fits(ipx, ctx)
+    if not args.no_served and not args.profile:
+        out["served"] = bench_served(ipx, ctx)
     ipx.ipx_destroy(ctx)
     if args.profile:
         out["calibration"] = calibration_copy()

@@ -108,10 +108,12 @@ IPX_API int ipx_model_ncols(int model);
  *          model's column order (host or device memory per `flags`).
  *   w:     optional per-event weights (n doubles, same memory kind), NULL for 1.
  * With IPX_COPY_*, the library owns the device copy (one allocation, columns
- * padded to 256-byte boundaries); the models with a decay time store it sorted
- * by t (unless IPX_KEEP_ORDER), which keeps the waves that need the
- * small-t/sigma resolution correction together.  The NLL is a sum over events,
- * so the order changes only its rounding.  The dataset also holds the scratch for its
+ * padded to 256-byte boundaries); the models with a decay time store it in
+ * resolution-band order (unless IPX_KEEP_ORDER): a stable sort by the key
+ * (b << 58) | (bits(sigma_t) >> 6), b = min(floor(2 t / sigma_t), 20) (0 when
+ * not positive), so that the events of a wave need the same resolution
+ * corrections.  The NLL is a sum over events, so the order changes only its
+ * rounding.  The dataset also holds the scratch for its
  * reduction partials, so calls on different datasets may run concurrently on
  * different streams; calls on one dataset must not overlap.
  */
@@ -127,7 +129,7 @@ IPX_API int ipx_dataset_model(const ipx_dataset *ds);
 IPX_API ipx_status ipx_dataset_column(const ipx_dataset *ds, int col, const double **dev_ptr);
 /* Copy events [offset, offset + count) of column `col` (or of the weights,
  * col = ncols) to host memory `host` (count doubles, caller-owned).  Events
- * are in storage order (sorted by t for the time models unless
+ * are in storage order (resolution-band order for the time models unless
  * IPX_KEEP_ORDER).  Synchronous. */
 IPX_API ipx_status ipx_dataset_read(ipx_ctx *ctx, const ipx_dataset *ds, int col, int64_t offset, int64_t count,
                                     double *host);
@@ -199,7 +201,8 @@ typedef struct ipx_server ipx_server;
 typedef struct {
   int slots;               /* concurrent requests on the device (<= 64; 0 = 32) */
   size_t scratch_bytes;    /* scratch budget for admitted requests (0 = 2 GiB) */
-  int workgroups;          /* persistent workgroups (0 = 2 per compute unit) */
+  int workgroups;          /* persistent workgroups, one of which polls the host
+                              (>= 2; 0 = 2 per compute unit) */
   int idle_iterations;     /* empty scans before the device loop exits (0 = 20000) */
   int spin_limit;          /* cap on a wait for a request's first phase (0 = 2^24) */
   int max_pending;         /* waiting requests accepted (0 = unlimited) */
@@ -222,6 +225,15 @@ IPX_API ipx_status ipx_submit(ipx_server *srv, const ipx_request *req, uint64_t 
 IPX_API ipx_status ipx_poll(ipx_server *srv, uint64_t ticket, ipx_result *out);
 IPX_API ipx_status ipx_wait(ipx_server *srv, uint64_t ticket, int64_t timeout_ns, ipx_result *out);
 IPX_API ipx_status ipx_server_stop(ipx_server *srv);
+/* Host-side counters of a running server (monitoring). */
+typedef struct {
+  uint64_t published;      /* requests handed to the device */
+  uint64_t completed;      /* requests the device finished */
+  uint64_t launches;       /* launches of the device loop */
+  uint64_t pending;        /* waiting for a slot or scratch now */
+  uint64_t in_flight;      /* in device slots now */
+} ipx_server_stats;
+IPX_API ipx_status ipx_server_stats_read(ipx_server *srv, ipx_server_stats *out);
 
 /*
  * Unbinned toy generation by accept-reject (Example 5 of the paper: toys
@@ -232,7 +244,7 @@ IPX_API ipx_status ipx_server_stop(ipx_server *srv);
  *   candidate c and block b (1, 2, 3 blocks per candidate for models 1, 2, 3);
  *   uniforms ((word >> 12) + 0.5) 2^-52.  Candidate c is accepted on its own
  *   words; the output holds the first n accepted candidates (increasing c),
- *   sorted by decay time for models 2 and 3 unless flags has IPX_KEEP_ORDER.
+ *   in resolution-band order for models 2 and 3 unless flags has IPX_KEEP_ORDER.
  *   Model 3 also draws weights 0.8 + 0.2 u (the workload's efficiency weights)
  *   unless flags has IPX_NO_WEIGHTS.
  *   Each model's recipe (proposals, bounds, acceptance ratios) is documented

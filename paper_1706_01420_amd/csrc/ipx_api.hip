@@ -83,7 +83,7 @@ struct ipx_dataset {
   const double* w = nullptr;
   int64_t n_tiles = 0;
   int64_t n_tiles_outer = 0;       // tiles of the angular coefficient-adjoint kernel
-  bool sorted = false;             // events stored in increasing decay time
+  bool sorted = false;             // events stored in resolution-band order
   double* tau = nullptr;           // 4 x n_pad per-event adjoint factors (angular gradient)
   double* partials = nullptr;      // n_tiles x kAccMax
   double* out_dev = nullptr;       // kAccMax
@@ -97,10 +97,13 @@ static const int kNParams[4] = {-1, 4, 7, 12};
 static const int kNCols[4] = {-1, 1, 3, 6};
 
 // ---------------------------------------------------------------------------
-// Event-store ordering: the models with a decay time store their events in
-// increasing t, so that the waves whose events need the large-t/sigma
-// correction at t are few and contiguous (the NLL is a sum over events; the
-// order only changes the rounding of the sum).
+// Event-store ordering for the models with a decay time: by the band of
+// t / sigma_t (width 1/2, the last band open above t / sigma_t = 10), then by
+// sigma_t within a band.  The resolution correction at t and the depth of its
+// continued fraction depend on t / sigma_t; those at the range ends and the
+// normalisation on sigma_t alone; so the waves of this order need the same
+// corrections at about the same depth.  The NLL is a sum over events: the
+// order only changes the rounding of the sum.
 // ---------------------------------------------------------------------------
 __global__ void k_iota(int* __restrict__ v, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -111,31 +114,48 @@ __global__ void k_gather(double* __restrict__ dst, const double* __restrict__ sr
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = src[perm[i]];
 }
+constexpr int kBands = 21;   // bands 0 .. 20 of 2 t / sigma_t (5 bits)
 
-static ipx_status sort_by_time(ipx_dataset* d, hipStream_t s) {
+// key = band << 58 | (bits of sigma_t) >> 6; sigma_t > 0, so its bit pattern
+// orders as its value
+__global__ void k_band_key(unsigned long long* __restrict__ key, const double* __restrict__ t,
+                           const double* __restrict__ sig, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double r = 2.0 * t[i] / sig[i];
+  const double b = r > 0.0 ? fmin(floor(r), (double)kBands - 1.0) : 0.0;  // NaN -> 0
+  key[i] = ((unsigned long long)b << 58) | ((unsigned long long)__double_as_longlong(sig[i]) >> 6);
+}
+
+static ipx_status sort_events(ipx_dataset* d, hipStream_t s) {
   const int n = (int)d->n;
   const int tcol = d->model == 2 ? 1 : 3;
-  double* keys_out = nullptr;
+  const int scol = d->model == 2 ? 2 : 4;
+  unsigned long long* keys = nullptr;
+  unsigned long long* keys_out = nullptr;
   double* tmp = nullptr;
   int* perm_in = nullptr;
   int* perm = nullptr;
   void* scratch = nullptr;
   size_t scratch_bytes = 0;
-  hipError_t e = hipMalloc(&keys_out, (size_t)n * sizeof(double));
+  hipError_t e = hipMalloc(&keys, (size_t)n * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMalloc(&keys_out, (size_t)n * sizeof(unsigned long long));
   if (e == hipSuccess) e = hipMalloc(&tmp, (size_t)n * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&perm_in, (size_t)n * sizeof(int));
   if (e == hipSuccess) e = hipMalloc(&perm, (size_t)n * sizeof(int));
   if (e == hipSuccess)
-    e = hipcub::DeviceRadixSort::SortPairs(nullptr, scratch_bytes, d->cols[tcol], keys_out, perm_in, perm, n, 0,
-                                           64, s);
+    e = hipcub::DeviceRadixSort::SortPairs(nullptr, scratch_bytes, keys, keys_out, perm_in, perm, n, 0, 64, s);
   if (e == hipSuccess) e = hipMalloc(&scratch, scratch_bytes);
   if (e == hipSuccess) {
     const unsigned blocks = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(k_iota, dim3(blocks), dim3(256), 0, s, perm_in, n);
     e = hipGetLastError();
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(k_band_key, dim3(blocks), dim3(256), 0, s, keys, d->cols[tcol], d->cols[scol], n);
+      e = hipGetLastError();
+    }
     if (e == hipSuccess)
-      e = hipcub::DeviceRadixSort::SortPairs(scratch, scratch_bytes, d->cols[tcol], keys_out, perm_in, perm, n,
-                                             0, 64, s);
+      e = hipcub::DeviceRadixSort::SortPairs(scratch, scratch_bytes, keys, keys_out, perm_in, perm, n, 0, 64, s);
     const int nstore = d->ncols + (d->w ? 1 : 0);
     for (int c = 0; c < nstore && e == hipSuccess; ++c) {
       double* col = const_cast<double*>(c < d->ncols ? d->cols[c] : d->w);
@@ -145,12 +165,13 @@ static ipx_status sort_by_time(ipx_dataset* d, hipStream_t s) {
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
   }
+  (void)hipFree(keys);
   (void)hipFree(keys_out);
   (void)hipFree(tmp);
   (void)hipFree(perm_in);
   (void)hipFree(perm);
   (void)hipFree(scratch);
-  if (e != hipSuccess) return fail(IPX_EDEVICE, "ipx_dataset_create: sorting by decay time failed: %s", hipGetErrorString(e));
+  if (e != hipSuccess) return fail(IPX_EDEVICE, "ipx_dataset_create: ordering the events failed: %s", hipGetErrorString(e));
   d->sorted = true;
   return IPX_OK;
 }
@@ -264,7 +285,7 @@ ipx_status ipx_dataset_create(ipx_ctx* ctx, int model, int64_t n, const double* 
       return fail(IPX_EDEVICE, "ipx_dataset_create: copy failed: %s", hipGetErrorString(e));
     }
     if (model >= 2 && !(flags & IPX_KEEP_ORDER) && n >= 2 && n <= 0x7fffffff) {
-      ipx_status st = sort_by_time(d, ctx->stream);
+      ipx_status st = sort_events(d, ctx->stream);
       if (st != IPX_OK) {
         free_dataset(d);
         return st;
@@ -572,7 +593,7 @@ extern "C" ipx_status toy_generate(ipx_ctx* ctx, int model, const double* theta,
     candidates = cnt[1];
   }
   if (model >= 2 && !(flags & IPX_KEEP_ORDER) && n >= 2) {
-    ipx_status st = sort_by_time(d, s);
+    ipx_status st = sort_events(d, s);
     if (st != IPX_OK) {
       free_dataset(d);
       return st;
@@ -897,6 +918,7 @@ struct ipx_server {
   std::vector<ServeReq*> slot_req;     // request in the slot (nullptr = free)
   std::deque<ServeReq*> pending;
   std::map<uint64_t, ServeReq*> reqs;
+  ipx_server_stats stats{};
 };
 
 static bool pool_alloc(ipx_server* S, size_t bytes, size_t* off) {
@@ -967,6 +989,7 @@ static void serve_publish(ipx_server* S, ServeReq* r) {
   else D.k.m3 = r->h3.k;
   S->hs->status[r->slot] = 0;
   r->seq = ++S->slot_seq[r->slot];
+  D.seq = r->seq;
   __atomic_store_n(&S->hs->mail[r->slot], (unsigned long long)r->seq, __ATOMIC_RELEASE);
   __atomic_fetch_add(&S->hs->gen, 1ull, __ATOMIC_RELEASE);
 }
@@ -1013,6 +1036,7 @@ static void serve_worker(ipx_server* S) {
       if (__atomic_load_n(&S->hs->fin[s], __ATOMIC_ACQUIRE) == r->seq) {
         const int status = S->hs->status[s] ? IPX_ETIMEOUT : IPX_OK;
         serve_finish(S, r, status, S->hs->out[s]);
+        ++S->stats.completed;
         pool_free(S, r->off, r->bytes);
         S->slot_req[s] = nullptr;
         progress = true;
@@ -1032,6 +1056,7 @@ static void serve_worker(ipx_server* S) {
       size_t off = 0;
       if (!pool_alloc(S, r->bytes, &off)) break;  // admission by footprint: wait for memory
       S->pending.pop_front();
+      ++S->stats.published;
       r->slot = slot;
       r->off = off;
       S->slot_req[slot] = r;
@@ -1040,11 +1065,16 @@ static void serve_worker(ipx_server* S) {
       progress = true;
     }
     if (busy > 0 && !serve_kernel_live(S)) {
-      hipLaunchKernelGGL(k_serve, dim3((unsigned)S->cfg.workgroups), dim3(kThreads), 0, S->stream, S->hs_dev,
-                         S->ctl, S->dd, S->st, nslots, S->cfg.idle_iterations, S->cfg.spin_limit);
-      hipError_t e = hipGetLastError();
+      // workgroup 0 polls, the others work: the poller leaves once `live` is 0
+      hipError_t e = hipMemsetD32Async((hipDeviceptr_t)&S->ctl->live, S->cfg.workgroups - 1, 1, S->stream);
+      if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_serve, dim3((unsigned)S->cfg.workgroups), dim3(kThreads), 0, S->stream, S->hs_dev,
+                           S->ctl, S->dd, S->st, nslots, S->cfg.idle_iterations, S->cfg.spin_limit);
+        e = hipGetLastError();
+      }
       if (e == hipSuccess) e = hipEventRecord(S->kernel_done, S->stream);
       S->kernel_launched = true;
+      ++S->stats.launches;
       if (e != hipSuccess) {
         // the device loop cannot run: every request ends with a device error
         S->worker_error = hipGetErrorString(e);
@@ -1078,7 +1108,15 @@ static void serve_worker(ipx_server* S) {
       S->pending.clear();
       break;
     }
-    S->cv.wait_for(lk, std::chrono::microseconds(progress ? 0 : 20));
+    if (busy == 0 && S->pending.empty()) {
+      S->cv.wait_for(lk, std::chrono::milliseconds(1));  // idle: ipx_submit notifies
+    } else {
+      // requests in flight: poll the completion words without a timed sleep
+      // (a timed wait rounds up to the scheduler's timer slack, tens of us)
+      lk.unlock();
+      std::this_thread::yield();
+      lk.lock();
+    }
   }
   S->cv.notify_all();
 }
@@ -1091,7 +1129,8 @@ extern "C" ipx_status ipx_server_start(ipx_ctx* ctx, const ipx_server_cfg* cfg, 
   if (c.slots <= 0) c.slots = 32;
   if (c.slots > kServeMaxSlots) return fail(IPX_EINVAL, "ipx_server_start: at most %d slots", kServeMaxSlots);
   if (c.scratch_bytes == 0) c.scratch_bytes = (size_t)1 << 31;
-  if (c.workgroups <= 0) c.workgroups = 2 * std::max(1, ctx->n_cu);
+  if (c.workgroups == 0) c.workgroups = 2 * std::max(1, ctx->n_cu);
+  if (c.workgroups < 2) return fail(IPX_EINVAL, "ipx_server_start: at least 2 workgroups (one polls the host)");
   if (c.idle_iterations <= 0) c.idle_iterations = 20000;
   if (c.spin_limit <= 0) c.spin_limit = 1 << 24;
   HIP_TRY(hipSetDevice(ctx->device));
@@ -1211,6 +1250,16 @@ extern "C" ipx_status ipx_wait(ipx_server* S, uint64_t ticket, int64_t timeout_n
       return fail(IPX_ETIMEOUT, "ipx_wait: ticket %llu not done", (unsigned long long)ticket);
   }
   return take_result(S, S->reqs.find(ticket), out);
+}
+
+extern "C" ipx_status ipx_server_stats_read(ipx_server* S, ipx_server_stats* out) {
+  if (!S || !out) return fail(IPX_EINVAL, "ipx_server_stats_read: NULL argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  *out = S->stats;
+  out->pending = S->pending.size();
+  out->in_flight = 0;
+  for (ServeReq* r : S->slot_req) out->in_flight += r != nullptr;
+  return IPX_OK;
 }
 
 extern "C" ipx_status ipx_server_stop(ipx_server* S) {

@@ -33,62 +33,66 @@ struct TileRef {
 // k may live in device memory, kernel arguments or LDS: the arithmetic is the
 // same, so a tile's partials do not depend on which kernel computed them.
 // ---------------------------------------------------------------------------
-template <int MODEL, bool GRAD>
+template <int MODEL, bool GRAD, bool COH = false>
 __device__ __forceinline__ void tile_nll(const SegInfo& S, const typename ModelTraits<MODEL>::Const& k,
                                          int64_t tile) {
   constexpr int NACC = GRAD ? ModelTraits<MODEL>::kAcc : 1;
   double acc[NACC];
 #pragma unroll
   for (int c = 0; c < NACC; ++c) acc[c] = 0.0;
-  const int64_t base = tile * kTile + threadIdx.x;
+  const int64_t base = tile * kTile;
 #pragma unroll 1
   for (int e = 0; e < kEventsPerLane; ++e) {
-    const int64_t i = base + (int64_t)e * kThreads;
-    if (i < S.cols.n) event<MODEL, GRAD>(k, S.cols, i, acc);
+    const unsigned j = threadIdx.x + (unsigned)e * kThreads;
+    if (base + j < S.cols.n) event<MODEL, GRAD, COH>(k, S.cols, base, j, acc);
   }
-  tile_store<NACC>(acc, S.partials, tile, S.n_tiles);
+  tile_store<NACC, COH>(acc, S.partials, tile, S.n_tiles);
 }
 
 // Angular model; C is the coefficient table in LDS.
-template <bool GRAD>
+template <bool GRAD, bool COH = false>
 __device__ __forceinline__ void tile_angtime(const SegInfo& S, const AngTimeConst& k, const double* C,
                                              int64_t tile) {
   constexpr int NACC = GRAD ? kAngInner : 1;
   double acc[NACC];
 #pragma unroll
   for (int c = 0; c < NACC; ++c) acc[c] = 0.0;
-  const int64_t base = tile * kTile + threadIdx.x;
+  const int64_t base = tile * kTile;
 #pragma unroll 1
   for (int e = 0; e < kEventsPerLane; ++e) {
-    const int64_t i = base + (int64_t)e * kThreads;
+    const unsigned j = threadIdx.x + (unsigned)e * kThreads;
     // keeps the LDS table reads inside the loop (re-read per event rather
     // than pinned in 80 registers)
     asm volatile("" ::: "memory");
-    if (i < S.cols.n) {
+    if (base + j < S.cols.n) {
       const EventCols& cl = S.cols;
-      const double w = cl.w ? cl.w[i] : 1.0;
-      event_angtime<GRAD>(k, C, cl.c[0][i], cl.c[1][i], cl.c[2][i], cl.c[3][i], cl.c[4][i], cl.c[5][i], w, acc,
-                          S.tau, S.tau_stride, i);
+      const double w = cl.w ? ldg<COH>(cl.w + base, j) : 1.0;
+      event_angtime<GRAD, COH>(k, C, ldg<COH>(cl.c[0] + base, j), ldg<COH>(cl.c[1] + base, j),
+                               ldg<COH>(cl.c[2] + base, j), ldg<COH>(cl.c[3] + base, j), ldg<COH>(cl.c[4] + base, j),
+                               ldg<COH>(cl.c[5] + base, j), w, acc, S.tau + base, S.tau_stride, j);
     }
   }
-  tile_store<NACC>(acc, S.partials, tile, S.n_tiles);
+  tile_store<NACC, COH>(acc, S.partials, tile, S.n_tiles);
 }
 
 // Angular gradient: coefficient adjoints over one outer tile.
+template <bool COH = false>
 __device__ __forceinline__ void tile_angtime_outer(const SegInfo& S, int64_t tile) {
   double acc[kAngOuter];
 #pragma unroll
   for (int c = 0; c < kAngOuter; ++c) acc[c] = 0.0;
-  const int64_t base = tile * kOuterTile + threadIdx.x;
+  const int64_t base = tile * kOuterTile;
 #pragma unroll 1
   for (int e = 0; e < kOuterEventsPerLane; ++e) {
-    const int64_t i = base + (int64_t)e * kThreads;
-    if (i < S.cols.n) {
+    const unsigned j = threadIdx.x + (unsigned)e * kThreads;
+    if (base + j < S.cols.n) {
       double f[10];
-      angular_functions(S.cols.c[0][i], S.cols.c[1][i], S.cols.c[2][i], f);
-      const double* tau = S.tau;
+      angular_functions(ldg<COH>(S.cols.c[0] + base, j), ldg<COH>(S.cols.c[1] + base, j),
+                        ldg<COH>(S.cols.c[2] + base, j), f);
+      const double* tau = S.tau + base;
       const int64_t ts = S.tau_stride;
-      const double t0 = tau[i], t1 = tau[ts + i], t2 = tau[2 * ts + i], t3 = tau[3 * ts + i];
+      const double t0 = ldg<COH>(tau, j), t1 = ldg<COH>(tau + ts, j), t2 = ldg<COH>(tau + 2 * ts, j),
+                   t3 = ldg<COH>(tau + 3 * ts, j);
 #pragma unroll
       for (int kk = 0; kk < 10; ++kk) {
         acc[4 * kk + 0] += f[kk] * t0;
@@ -98,7 +102,7 @@ __device__ __forceinline__ void tile_angtime_outer(const SegInfo& S, int64_t til
       }
     }
   }
-  tile_store<kAngOuter>(acc, S.partials + kAngOuter0 * S.n_tiles, tile, S.n_tiles);
+  tile_store<kAngOuter, COH>(acc, S.partials + kAngOuter0 * S.n_tiles, tile, S.n_tiles);
 }
 
 // ---------------------------------------------------------------------------

@@ -19,6 +19,35 @@
 namespace ipx {
 
 // ---------------------------------------------------------------------------
+// Global-memory access.  Column pointers reach the kernels through structs in
+// device memory, so the compiler sees generic pointers and would emit flat
+// loads (which also wait on the LDS / scalar counters).  These helpers address
+// the global segment explicitly: a wave-uniform base pointer plus a 32-bit lane
+// offset, i.e. one scalar base register pair and one vector offset per access.
+//
+// COH = true makes every access device-coherent (relaxed atomics at agent
+// scope: the L2 of each XCD is bypassed for stores and revalidated for loads).
+// The persistent serving kernel uses it for everything that other workgroups
+// of the same launch produce or consume (partials, per-event factors), and for
+// the event columns (which may have been written after the launch started);
+// the kernels of one-shot launches, ordered by kernel boundaries, use plain
+// accesses.
+// ---------------------------------------------------------------------------
+typedef __attribute__((address_space(1))) const double gconst_double;
+typedef __attribute__((address_space(1))) double gdouble;
+
+template <bool COH = false>
+__device__ __forceinline__ double ldg(const double* base, unsigned j) {
+  if constexpr (COH) return __hip_atomic_load((gconst_double*)base + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else return ((gconst_double*)base)[j];
+}
+template <bool COH = false>
+__device__ __forceinline__ void stg(double* base, unsigned j, double v) {
+  if constexpr (COH) __hip_atomic_store((gdouble*)base + j, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else ((gdouble*)base)[j] = v;
+}
+
+// ---------------------------------------------------------------------------
 // Reduction
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {
@@ -27,7 +56,7 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-template <int NACC>
+template <int NACC, bool COH = false>
 __device__ __forceinline__ void tile_store(const double (&acc)[NACC], double* __restrict__ partials,
                                            int64_t tile, int64_t n_tiles) {
   __shared__ double lds[kThreads / 64][NACC];
@@ -40,15 +69,16 @@ __device__ __forceinline__ void tile_store(const double (&acc)[NACC], double* __
   }
   __syncthreads();
   for (int c = threadIdx.x; c < NACC; c += kThreads)
-    partials[(int64_t)c * n_tiles + tile] = (lds[0][c] + lds[1][c]) + (lds[2][c] + lds[3][c]);
+    stg<COH>(partials + (int64_t)c * n_tiles + tile, 0u, (lds[0][c] + lds[1][c]) + (lds[2][c] + lds[3][c]));
   __syncthreads();
 }
 
 // Sum of nt tile partials in a fixed order: lane-sequential over a stride of
 // 256, wave butterfly, waves in order.  Used by every reduction of partials.
+template <bool COH = false>
 __device__ __forceinline__ double reduce_component(const double* __restrict__ p, int64_t nt) {
   double s = 0.0;
-  for (int64_t i = threadIdx.x; i < nt; i += kThreads) s += p[i];
+  for (int64_t i = threadIdx.x; i < nt; i += kThreads) s += ldg<COH>(p + i, 0u);
   __shared__ double lds[kThreads / 64];
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
@@ -84,16 +114,27 @@ __device__ __forceinline__ void event_mass(const MassConst& k, double m, double 
 //   u = i (z s^2 - tau)/(sqrt2 s),  g = exp(-tau^2/(2 s^2)).
 // For a real rate, w on the imaginary axis is erfcx.
 // ---------------------------------------------------------------------------
+// A time point: whether its correction terms are needed, and the depth of the
+// continued fraction that evaluates them.  The correction of rate r is
+// exp(-E_r) w / 2 relative to the main term with E_r = (Im u_r)^2 - (Re u_r)^2;
+// the smallest E over the rates is at the largest rate.  At the range ends
+// the same depth serves the Phi terms of the normalisation, whose size
+// relative to the main term at T_LO is bounded with E lowered by
+// (Re u)^2 + gmax tau (e_shift); when Im u < 0 for some rate the correction is
+// the whole value and takes the full depth.
 struct TimePoint {
   double g;     // exp(-tau^2 / (2 s^2)), 0 when the correction is negligible
   bool need;    // correction evaluated
+  int depth;    // continued-fraction levels (wave-uniform)
 };
 
 __device__ __forceinline__ TimePoint time_point(double tau, double gmax, double s2, double inv_r2s,
-                                                double re_u2) {
+                                                double re_u2, double e_shift) {
   TimePoint p;
   const double x = (tau - gmax * s2) * inv_r2s;  // smallest |Im u| over the rates
-  p.need = !(x > 0.0 && x * x - re_u2 > kCorrSkip);
+  const double E = x > 0.0 ? x * x - re_u2 : -1.0;
+  p.need = !(E > kCorrSkip);
+  p.depth = cf_depth_wave(p.need ? E - e_shift : kCorrSkip);
   const double a = tau * inv_r2s;
   p.g = p.need ? exp(-a * a) : 0.0;
   return p;
@@ -103,7 +144,7 @@ __device__ __forceinline__ double conv_real(double tau, double rate, double main
                                             double s2, double inv_r2s) {
   if (!p.need) return main;
   const double y = (tau - rate * s2) * inv_r2s;  // -Im u
-  const double c = 0.5 * p.g * erfcx_pos(fabs(y));
+  const double c = 0.5 * p.g * erfcx_pos(fabs(y), p.depth);
   return y >= 0.0 ? main - c : c;
 }
 
@@ -114,7 +155,7 @@ __device__ __forceinline__ cplx conv_cplx(double tau, double rate, double dmr, c
   const double y = (tau - rate * s2) * inv_r2s;
   // w(-u) for y >= 0 (then F = main - g w(-u)/2), w(u) otherwise (F = g w(u)/2)
   const bool lower = y >= 0.0;
-  const cplx c = cscale(faddeeva_upper(lower ? cplx{-dmr, y} : cplx{dmr, -y}), 0.5 * p.g);
+  const cplx c = cscale(faddeeva_upper(lower ? cplx{-dmr, y} : cplx{dmr, -y}, p.depth), 0.5 * p.g);
   return lower ? csub(main, c) : c;
 }
 
@@ -167,13 +208,13 @@ __device__ __forceinline__ void event_masstime(const MassTimeConst& k, double m,
   const double sig = k.s * sigt;
   const double s2 = sig * sig;
   const double inv_r2s = kInvSqrt2 * rcp(sig);
-  const TimePoint pt = time_point(t, k.gmax, s2, inv_r2s, 0.0);
-  const TimePoint pa = time_point(kTLo, k.gmax, s2, inv_r2s, 0.0);
-  const TimePoint pb = time_point(kTHi, k.gmax, s2, inv_r2s, 0.0);
+  const TimePoint pt = time_point(t, k.gmax, s2, inv_r2s, 0.0, 0.0);
+  const TimePoint pa = time_point(kTLo, k.gmax, s2, inv_r2s, 0.0, k.gmax * kTLo);
+  const TimePoint pb = time_point(kTHi, k.gmax, s2, inv_r2s, 0.0, k.gmax * kTHi);
   // Phi(T_HI) - Phi(T_LO) = 1/2 [g_a erfcx(T_LO/(sqrt2 s)) - g_b erfcx(T_HI/(sqrt2 s))]
   double dphi = 0.0;
-  if (pa.need) dphi += 0.5 * pa.g * erfcx_pos(kTLo * inv_r2s);
-  if (pb.need) dphi -= 0.5 * pb.g * erfcx_pos(kTHi * inv_r2s);
+  if (pa.need) dphi += 0.5 * pa.g * erfcx_pos(kTLo * inv_r2s, pa.depth);
+  if (pb.need) dphi -= 0.5 * pb.g * erfcx_pos(kTHi * inv_r2s, pb.depth);
   const RateTerms rs = rate_terms<GRAD>(t, k.gs, k.hs2, k.eAs, k.eBs, k.inv_gs, sig, s2, inv_r2s, pt, pa, pb, dphi);
   const RateTerms rb = rate_terms<GRAD>(t, k.gb, k.hb2, k.eAb, k.eBb, k.inv_gb, sig, s2, inv_r2s, pt, pa, pb, dphi);
   const double d = m - k.mu;
@@ -204,16 +245,19 @@ struct Conv3 {
   double FH, FL;
   cplx Fc;
   double g;
+  int depth;
 };
 
 __device__ __forceinline__ Conv3 conv3(double tau, double mainH, double mainL, cplx mainC,
-                                       const AngTimeConst& k, double s2, double inv_r2s, double dmr) {
-  const TimePoint p = time_point(tau, k.gmax, s2, inv_r2s, dmr * dmr);
+                                       const AngTimeConst& k, double s2, double inv_r2s, double dmr,
+                                       double e_shift) {
+  const TimePoint p = time_point(tau, k.gmax, s2, inv_r2s, dmr * dmr, e_shift);
   Conv3 r;
   r.FH = conv_real(tau, k.gH, mainH, p, s2, inv_r2s);
   r.FL = conv_real(tau, k.gL, mainL, p, s2, inv_r2s);
   r.Fc = conv_cplx(tau, k.g, dmr, mainC, p, s2, inv_r2s);
   r.g = p.g;
+  r.depth = p.depth;
   return r;
 }
 
@@ -258,12 +302,13 @@ constexpr int kOuterEventsPerLane = 16;
 constexpr int kOuterTile = kThreads * kOuterEventsPerLane;
 
 // One event.  C is the coefficient table in LDS (row-major 10 x 4).  For the
-// gradient, writes tau_j = w T_j / num to tau[j * tau_stride + i].
-template <bool GRAD>
+// gradient, writes tau_j = w T_j / num to tau[j * tau_stride + i] (tau is the
+// tile's base, i the event's offset within the tile).
+template <bool GRAD, bool COH = false>
 __device__ __forceinline__ void event_angtime(const AngTimeConst& k, const double* __restrict__ C,
                                               double ck, double cl, double ph, double t, double sig,
                                               double m, double w, double* acc, double* __restrict__ tau,
-                                              int64_t tau_stride, int64_t i) {
+                                              int64_t tau_stride, unsigned i) {
   // time: per-event factors shared by t, T_LO and T_HI
   const double s2 = sig * sig;
   const double inv_sig = rcp(sig);
@@ -280,15 +325,17 @@ __device__ __forceinline__ void event_angtime(const AngTimeConst& k, const doubl
   const double eD = exp(k.hdg * t);
   const double mt = ec2 * eG;
   const Conv3 Xt = conv3(t, eH2 * (eG * eD), eL2 * (eG * rcp(eD)),
-                         cplx{mt * (ct * cc + st * sc), mt * (st * cc - ct * sc)}, k, s2, inv_r2s, dmr);
+                         cplx{mt * (ct * cc + st * sc), mt * (st * cc - ct * sc)}, k, s2, inv_r2s, dmr, 0.0);
   const double ma = ec2 * k.eAG, mb = ec2 * k.eBG;
   const Conv3 Xa = conv3(kTLo, eH2 * k.eAH, eL2 * k.eAL,
-                         cplx{ma * (k.cA * cc + k.sA * sc), ma * (k.sA * cc - k.cA * sc)}, k, s2, inv_r2s, dmr);
+                         cplx{ma * (k.cA * cc + k.sA * sc), ma * (k.sA * cc - k.cA * sc)}, k, s2, inv_r2s, dmr,
+                         k.gmax * kTLo);
   const Conv3 Xb = conv3(kTHi, eH2 * k.eBH, eL2 * k.eBL,
-                         cplx{mb * (k.cB * cc + k.sB * sc), mb * (k.sB * cc - k.cB * sc)}, k, s2, inv_r2s, dmr);
+                         cplx{mb * (k.cB * cc + k.sB * sc), mb * (k.sB * cc - k.cB * sc)}, k, s2, inv_r2s, dmr,
+                         k.gmax * kTHi);
   double dphi = 0.0;
-  if (Xa.g != 0.0) dphi += 0.5 * Xa.g * erfcx_pos(kTLo * inv_r2s);
-  if (Xb.g != 0.0) dphi -= 0.5 * Xb.g * erfcx_pos(kTHi * inv_r2s);
+  if (Xa.g != 0.0) dphi += 0.5 * Xa.g * erfcx_pos(kTLo * inv_r2s, Xa.depth);
+  if (Xb.g != 0.0) dphi -= 0.5 * Xb.g * erfcx_pos(kTHi * inv_r2s, Xb.depth);
   const double IH = (dphi + Xa.FH - Xb.FH) * k.inv_gH;
   const double IL = (dphi + Xa.FL - Xb.FL) * k.inv_gL;
   const cplx Ic = cmul(cplx{dphi + Xa.Fc.re - Xb.Fc.re, Xa.Fc.im - Xb.Fc.im}, cplx{k.izr, k.izi});
@@ -311,7 +358,7 @@ __device__ __forceinline__ void event_angtime(const AngTimeConst& k, const doubl
   if constexpr (GRAD) {
     const double inum = w * rcp(num), iden = w * rcp(den);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) tau[j * tau_stride + i] = T[j] * inum;
+    for (int j = 0; j < 4; ++j) stg<COH>(tau + j * tau_stride, i, T[j] * inum);
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[1 + j] -= I[j] * iden;
     const double Gt = Xt.g * kInvSqrt2Pi * inv_sig;
@@ -351,14 +398,18 @@ struct ModelTraits<2> {
   static constexpr int kAcc = kAccMassTime;
 };
 
-template <int MODEL, bool GRAD>
+// Columns are addressed as (tile base pointer, 32-bit offset within the tile):
+// the base is wave-uniform (scalar registers), so each load needs one 32-bit
+// lane offset instead of a 64-bit address per column.
+template <int MODEL, bool GRAD, bool COH = false>
 __device__ __forceinline__ void event(const typename ModelTraits<MODEL>::Const& k, const EventCols& cols,
-                                      int64_t i, double* acc) {
-  const double w = cols.w ? cols.w[i] : 1.0;
+                                      int64_t base, unsigned j, double* acc) {
+  const double w = cols.w ? ldg<COH>(cols.w + base, j) : 1.0;
   if constexpr (MODEL == 1) {
-    event_mass<GRAD>(k, cols.c[0][i], w, acc);
+    event_mass<GRAD>(k, ldg<COH>(cols.c[0] + base, j), w, acc);
   } else {
-    event_masstime<GRAD>(k, cols.c[0][i], cols.c[1][i], cols.c[2][i], w, acc);
+    event_masstime<GRAD>(k, ldg<COH>(cols.c[0] + base, j), ldg<COH>(cols.c[1] + base, j),
+                         ldg<COH>(cols.c[2] + base, j), w, acc);
   }
 }
 

@@ -16,6 +16,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "cf_depth.h"
 #include "weideman_coeffs.h"
 
 namespace ipx {
@@ -79,14 +80,32 @@ __device__ __forceinline__ void sincos_small(double x, double* s, double* c) {
   *c = 1.0 - x2 * (0.5 - x2 * (1.0 / 24.0 - x2 * (1.0 / 720.0 - x2 * (1.0 / 40320.0 - x2 * (1.0 / 3628800.0)))));
 }
 
-// Jacobi continued fraction, forward Wallis recurrences.  Valid (and used) for
-// Im z >= 3.4 or |z| >= 6 with |z| <= 1e6.
-__device__ __forceinline__ cplx faddeeva_cf(cplx z) {
+// Depth of the continued fraction for correction terms whose exponent
+// E = (Im z)^2 - (Re z)^2 is at least the given value on every active lane of
+// the wave (the table in cf_depth.h bounds the truncation error of a K-level
+// fraction times the correction's size by 2^-57 of the main term).  The result
+// is the same on all lanes: a binary search with wave votes.
+__device__ __forceinline__ int cf_depth_wave(double E) {
+  int lo = 1, hi = kCfMaxDepth;
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    const int mid = (lo + hi) >> 1;
+    if (__any(E < kCfDepthE[mid - 1])) lo = mid + 1;
+    else hi = mid;
+  }
+  return hi;
+}
+
+// Jacobi continued fraction with `depth` levels (1 .. 10, wave-uniform),
+// forward Wallis recurrences.  Valid (and used) for Im z >= 3.4 or |z| >= 6
+// with |z| <= 1e6; 10 levels give full precision there.
+__device__ __forceinline__ cplx faddeeva_cf(cplx z, int depth) {
   const cplx z2 = cmul(z, z);
   cplx pm{1.0, 0.0}, qm{0.0, 0.0};      // P_{-1}, Q_{-1}
   cplx p{z2.re - 0.5, z2.im}, q{1.0, 0.0};  // P_0, Q_0
 #pragma unroll
-  for (int k = 1; k <= 10; ++k) {
+  for (int k = 1; k <= kCfMaxDepth; ++k) {
+    if (k > depth) break;
     const cplx d{z2.re - (2.0 * k + 0.5), z2.im};
     const double c = (2.0 * k - 1.0) * (2.0 * k) * 0.25;
     const cplx pn = csub(cmul(d, p), cscale(pm, c));
@@ -113,8 +132,8 @@ __device__ __noinline__ cplx faddeeva_series(cplx z) {
   return cadd(cscale(cmul(p, cmul(r, r)), 2.0), cscale(r, kInvSqrtPi));
 }
 
-// w(z) for Im z >= 0.
-__device__ __forceinline__ cplx faddeeva_upper(cplx z) {
+// w(z) for Im z >= 0; depth as for faddeeva_cf (full precision by default).
+__device__ __forceinline__ cplx faddeeva_upper(cplx z, int depth = kCfMaxDepth) {
   const double r2 = z.re * z.re + z.im * z.im;
   if (r2 > 1e12) {
     // asymptotic i/(sqrt(pi) z) (1 + 1/(2 z^2)); relative error < 1e-24 here
@@ -122,19 +141,21 @@ __device__ __forceinline__ cplx faddeeva_upper(cplx z) {
     const cplx z2i = cdiv(cplx{0.5, 0.0}, cmul(z, z));
     return cmul(iz, cplx{1.0 + z2i.re, z2i.im});
   }
-  if (z.im >= 3.4 || r2 >= 36.0) return faddeeva_cf(z);
+  if (z.im >= 3.4 || r2 >= 36.0) return faddeeva_cf(z, depth);
   return faddeeva_series(z);
 }
 
 // erfcx(y) = e^{y^2} erfc(y) = w(i y) for y >= 0: the continued fraction in
-// real arithmetic for y >= 3.4, the (out-of-line) rational series otherwise.
-__device__ __forceinline__ double erfcx_pos(double y) {
+// real arithmetic (depth as for faddeeva_cf) for y >= 3.4, the (out-of-line)
+// rational series otherwise.
+__device__ __forceinline__ double erfcx_pos(double y, int depth = kCfMaxDepth) {
   if (y < 3.4) return faddeeva_series(cplx{0.0, y}).re;
   if (y > 1e6) return kInvSqrtPi / y * (1.0 - 0.5 / (y * y));
   const double z2 = -y * y;
   double pm = 1.0, qm = 0.0, p = z2 - 0.5, q = 1.0;
 #pragma unroll
-  for (int k = 1; k <= 10; ++k) {
+  for (int k = 1; k <= kCfMaxDepth; ++k) {
+    if (k > depth) break;
     const double d = z2 - (2.0 * k + 0.5);
     const double c = (2.0 * k - 1.0) * (2.0 * k) * 0.25;
     const double pn = d * p - c * pm;

@@ -2,26 +2,46 @@
 // from a host-visible mailbox while it runs (continuous batching: requests
 // that arrive while others are being evaluated join the same launch).
 //
-// Protocol (S slots):
-//   host   writes the request descriptor desc[s] into fine-grained host memory,
-//          then mail[s] = seq (release) and bumps gen.
-//   device one workgroup "opens" the request (CAS on open[s]): it copies
-//          desc[s] into device memory with vector loads, clears the slot's
-//          completion counters and publishes claim[s] = seq << 32 (release).
-//          Workgroups claim items with atomicAdd on claim[s]; the high word
-//          tells which request the item belongs to, so a late claim on a
-//          finished request is recognised and ignored.
-//          Items: the request's canonical tiles (A), then for the angular
-//          gradient its coefficient-adjoint tiles (B, which start once all A
-//          tiles are done).  The workgroup that completes the last item sums
-//          every component's tile partials in index order (the same order as
-//          the other entry points) and writes out[s], then fin[s] = seq
-//          (system-scope release).
-//   exit   every workgroup leaves after `idle_limit` consecutive empty scans or
-//          when the host sets stop; waits for phase A are capped by
-//          `spin_limit` (a request that hits it is finished with status 1).
+// Protocol (S slots; workgroup 0 is the poller, the others are workers):
+//   host    writes the request descriptor desc[s] into fine-grained host
+//           memory, then mail[s] = seq and bumps gen (in that order).
+//   poller  the only workgroup that reads host memory.  When gen changes it
+//           reads every mail word; for each slot with a new sequence number it
+//           copies desc[s] into device memory, clears the slot's completion
+//           counters, writes lim[s] = (seq << 32) | items, then publishes
+//           claim[s] = seq << 32 and sets the slot's bit in the claimable-slot
+//           mask.
+//   workers scan the mask and take one item at a time with one atomic add on
+//           claim[s]; the returned word names the request (high half) and the
+//           item (low half).  The item is valid if lim[s] names the same
+//           request and the item is below its count; any other increment is a
+//           late claim on a finished request and is dropped, so no request
+//           can lose an item.  A (per-event) tiles come first, then the
+//           angular gradient's coefficient-adjoint tiles (B), which wait for
+//           every A tile.  The worker that takes a slot's last item clears its
+//           mask bit.  The worker that completes a request's last item sums
+//           every component's tile partials in index order (the order of the
+//           other entry points), writes out[s], then fin[s] = seq.
+//   exit    a worker leaves after `idle_limit` consecutive scans without a
+//           claim, or when stop is set, and counts itself out of `live`; the
+//           poller leaves when no worker is left or the host sets stop.  The
+//           wait of a B item for its A items is capped by `spin_limit` (the
+//           request then finishes with status 1).
 //
-// All waits are bounded, so the grid always drains.  No workgroup waits on
+// Memory ordering without cache-wide fences.  On this GPU every XCD has its
+// own L2, and an agent-scope release or acquire fence writes back or
+// invalidates that whole cache; with hundreds of workgroups fencing per item
+// the fences cost more than the tiles.  Instead, every location that one
+// workgroup writes and another reads during the launch (descriptors, lim,
+// claim, counters, tile partials, per-event factors; also the event columns,
+// which may have been written after the launch) is accessed with relaxed
+// device-coherent atomics, and a writer waits for its stores to complete
+// (s_waitcnt, then the workgroup barrier) before the atomic that publishes
+// them.  A reader issues its loads only after it has observed that atomic,
+// and coherent loads see every completed coherent store.  Host memory is read
+// and written with system-coherent atomics in the same way.
+//
+// All waits are bounded, so the grid always drains; no workgroup waits on
 // work that has not been claimed by a running workgroup.
 #pragma once
 
@@ -32,11 +52,11 @@ namespace ipx {
 constexpr int kServeMaxSlots = 64;
 
 struct ServeDesc {
+  unsigned long long seq;  // the request's sequence number in its slot
   int model;
   int grad;
   int nA, nB;        // items: per-event tiles, coefficient-adjoint tiles
   int nacc, split;   // reduced components; components >= split use the outer tiles
-  int pad[2];
   SegInfo seg;       // columns of the dataset + this request's scratch
   union {
     MassConst m1;
@@ -44,21 +64,22 @@ struct ServeDesc {
     AngTimeConst m3;
   } k;
 };
+static_assert(sizeof(ServeDesc) % 8 == 0, "descriptor is copied in 8-byte words");
 
 struct ServeSlot {                 // device memory, touched by the GPU only
   unsigned long long claim;        // (seq << 32) | next item
-  unsigned long long open;         // seq opened by the device
+  unsigned long long lim;          // (seq << 32) | items of the request in the slot
+  unsigned long long open;         // last seq opened by the poller
   unsigned int doneA;              // completed A items
   unsigned int done;               // completed items
-  unsigned long long pad;
 };
 
-struct ServeCtl {                  // device memory: mirror of the host's gen / stop
-  unsigned long long gen;
-  unsigned long long stop;
+struct ServeCtl {                  // device memory
+  unsigned long long mask;         // slots that may have unclaimed items
+  unsigned long long stop;         // mirror of the host's stop
+  unsigned int live;               // worker workgroups still running (set by the host at launch)
+  unsigned int pad;
 };
-
-constexpr int kServePollers = 4;   // workgroups that read the host's gen / stop
 
 struct ServeShared {               // fine-grained host memory
   unsigned long long gen;          // bumped by the host after each publication
@@ -70,174 +91,220 @@ struct ServeShared {               // fine-grained host memory
   ServeDesc desc[kServeMaxSlots];
 };
 
-__device__ __forceinline__ unsigned long long load_sys(const unsigned long long* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+template <typename T>
+__device__ __forceinline__ T load_sys(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
-__device__ __forceinline__ void store_sys(unsigned long long* p, unsigned long long v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+template <typename T>
+__device__ __forceinline__ void store_sys(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
-__device__ __forceinline__ unsigned long long load_dev(const unsigned long long* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+template <typename T>
+__device__ __forceinline__ T load_dev(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ unsigned int load_dev32(const unsigned int* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+template <typename T>
+__device__ __forceinline__ void store_dev(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Copy n 8-byte words with the workgroup's lanes (vector loads and stores).
-__device__ __forceinline__ void wg_copy(unsigned long long* __restrict__ dst, const unsigned long long* src, int n) {
-  for (int i = threadIdx.x; i < n; i += kThreads) dst[i] = __hip_atomic_load(src + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+// Wait until every memory access this lane has issued has completed; also a
+// compiler barrier for memory operations.
+__device__ __forceinline__ void wait_mem() { asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory"); }
+
+// Copy n 8-byte words with the workgroup's lanes: host (system-coherent) to
+// device (device-coherent), or device (device-coherent) to LDS.
+__device__ __forceinline__ void copy_host_to_dev(unsigned long long* dst, const unsigned long long* src, int n) {
+  for (int i = threadIdx.x; i < n; i += kThreads) store_dev(dst + i, load_sys(src + i));
+}
+__device__ __forceinline__ void copy_dev_to_lds(unsigned long long* dst, const unsigned long long* src, int n) {
+  for (int i = threadIdx.x; i < n; i += kThreads) dst[i] = load_dev(src + i);
 }
 
-enum : int { kCmdIdle = 0, kCmdOpen = 1, kCmdWork = 2, kCmdExit = 3 };
+enum : int { kCmdIdle = 0, kCmdWork = 1, kCmdExit = 2, kCmdScan = 3 };
 
-__global__ __launch_bounds__(kThreads) void k_serve(ServeShared* hs, ServeCtl* __restrict__ ctl,
-                                                    ServeDesc* __restrict__ dd, ServeSlot* __restrict__ st,
-                                                    int nslots, int idle_limit, int spin_limit) {
+// Poller: opens slot s for request seq (whole workgroup).
+__device__ __forceinline__ void serve_open(ServeShared* hs, ServeCtl* ctl, ServeDesc* __restrict__ dd,
+                                           ServeSlot* __restrict__ st, int s, unsigned long long seq) {
+  constexpr int kWords = (int)(sizeof(ServeDesc) / sizeof(unsigned long long));
+  copy_host_to_dev((unsigned long long*)&dd[s], (const unsigned long long*)&hs->desc[s], kWords);
+  wait_mem();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned items = (unsigned)(load_dev(&dd[s].nA) + load_dev(&dd[s].nB));
+    store_dev(&st[s].open, seq);
+    store_dev(&st[s].doneA, 0u);
+    store_dev(&st[s].done, 0u);
+    store_dev(&st[s].lim, (seq << 32) | (unsigned long long)items);
+    wait_mem();
+    store_dev(&st[s].claim, seq << 32);
+    wait_mem();
+    __hip_atomic_fetch_or(&ctl->mask, 1ull << s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void serve_poll(ServeShared* hs, ServeCtl* ctl, ServeDesc* __restrict__ dd,
+                                           ServeSlot* __restrict__ st, int nslots) {
+  __shared__ int pcmd;
+  __shared__ unsigned long long pseq[kServeMaxSlots];
+  unsigned long long seen = 0;  // last host generation scanned (thread 0)
+  for (;;) {
+    if (threadIdx.x == 0) {
+      const unsigned long long g = load_sys(&hs->gen);
+      if (load_sys(&hs->stop)) {
+        pcmd = kCmdExit;
+        store_dev(&ctl->stop, 1ull);
+      } else if (g != seen) {
+        // set before the scan: a publication during the scan bumps gen again
+        seen = g;
+        pcmd = kCmdScan;
+      } else if (load_dev(&ctl->live) == 0u) {
+        pcmd = kCmdExit;
+      } else {
+        pcmd = kCmdIdle;
+      }
+      wait_mem();  // the mail words below are read after gen
+    }
+    __syncthreads();
+    const int c = pcmd;
+    if (c == kCmdExit) return;
+    if (c == kCmdScan) {
+      for (int s = threadIdx.x; s < nslots; s += kThreads) {
+        const unsigned long long m = load_sys(&hs->mail[s]);
+        pseq[s] = m > load_dev(&st[s].open) ? m : 0ull;
+      }
+      wait_mem();  // descriptors are read after their mail word
+      __syncthreads();
+      for (int s = 0; s < nslots; ++s)
+        if (pseq[s]) serve_open(hs, ctl, dd, st, s, pseq[s]);
+    } else {
+      __builtin_amdgcn_s_sleep(8);
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ void serve_work(ServeShared* hs, ServeCtl* ctl, ServeDesc* __restrict__ dd,
+                                           ServeSlot* __restrict__ st, int idle_limit, int spin_limit) {
   __shared__ ServeDesc sd;          // the current item's request
   __shared__ int cmd, cslot, citem;
-  __shared__ unsigned long long cseq;
   __shared__ int last;
   int idle = 0;
-  unsigned long long seen_gen = 0;  // host publications already scanned (thread 0)
+  const unsigned rot = blockIdx.x & 63u;  // spreads the workers' first choice over the slots
   for (;;) {
     if (threadIdx.x == 0) {
       cmd = kCmdIdle;
-      if (blockIdx.x < kServePollers) {
-        // a few workgroups mirror the host's counters into device memory
-        atomicMax(&ctl->gen, load_sys(&hs->gen));
-        if (load_sys(&hs->stop)) atomicMax(&ctl->stop, 1ull);
-      }
-      const unsigned long long gen = load_dev(&ctl->gen);
-      const bool rescan = gen != seen_gen;
       if (load_dev(&ctl->stop)) {
         cmd = kCmdExit;
       } else {
-        bool scanned_all = true;
-        for (int i = 0; i < nslots && cmd == kCmdIdle; ++i) {
-          const int s = (int)((blockIdx.x + (unsigned)i) % (unsigned)nslots);
-          const unsigned long long opened = load_dev(&st[s].open);
-          if (rescan) {
-            const unsigned long long seq = load_sys(&hs->mail[s]);
-            if (seq > opened) {
-              if (atomicCAS(&st[s].open, opened, seq) == opened) {
-                cmd = kCmdOpen;
-                cslot = s;
-                cseq = seq;
-                scanned_all = i == nslots - 1;
-              }
-              continue;
-            }
-          }
-          if (opened == 0) continue;
-          // claimable?  (the claim word carries the sequence number it counts for)
-          const unsigned long long c = load_dev(&st[s].claim);
-          const unsigned long long seq = c >> 32;
-          if (seq != opened) continue;
-          const int total = __hip_atomic_load(&dd[s].nA, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) +
-                            __hip_atomic_load(&dd[s].nB, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          if ((int)(c & 0xffffffffull) >= total) continue;
-          const unsigned long long old = atomicAdd(&st[s].claim, 1ull);
-          if ((old >> 32) == seq && (int)(old & 0xffffffffull) < total) {
+        unsigned long long m = load_dev(&ctl->mask);
+        m = rot ? (m >> rot) | (m << (64u - rot)) : m;
+        while (m != 0ull && cmd == kCmdIdle) {
+          const int s = (int)((__builtin_ctzll(m) + rot) & 63u);
+          m &= m - 1ull;
+          const unsigned long long old =
+              __hip_atomic_fetch_add(&st[s].claim, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          wait_mem();  // lim is read after the claim word it validates
+          const unsigned long long lim = load_dev(&st[s].lim);
+          const unsigned item = (unsigned)(old & 0xffffffffull);
+          const unsigned n = (unsigned)(lim & 0xffffffffull);
+          if ((lim >> 32) == (old >> 32) && item < n) {
             cmd = kCmdWork;
             cslot = s;
-            cseq = seq;
-            citem = (int)(old & 0xffffffffull);
-            scanned_all = false;
+            citem = (int)item;
+            if (item == n - 1u)
+              __hip_atomic_fetch_and(&ctl->mask, ~(1ull << s), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           }
         }
-        if (rescan && scanned_all && cmd != kCmdOpen) seen_gen = gen;
       }
+      wait_mem();  // the descriptor is read after the claim
     }
     __syncthreads();
     const int c = cmd;
-    if (c == kCmdExit) return;
+    if (c == kCmdExit || (c == kCmdIdle && ++idle > idle_limit)) {
+      if (threadIdx.x == 0)
+        __hip_atomic_fetch_sub(&ctl->live, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
     if (c == kCmdIdle) {
-      if (++idle > idle_limit) return;
       __builtin_amdgcn_s_sleep(32);
       __syncthreads();
       continue;
     }
     idle = 0;
     const int s = cslot;
-    const unsigned long long seq = cseq;
-    if (c == kCmdOpen) {
-      // device copy of the descriptor, counters cleared, then claims open
-      wg_copy((unsigned long long*)&dd[s], (const unsigned long long*)&hs->desc[s],
-              (int)(sizeof(ServeDesc) / sizeof(unsigned long long)));
-      __threadfence();
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        __hip_atomic_store(&st[s].doneA, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&st[s].done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        atomicExch(&st[s].claim, seq << 32);
-      }
-      __syncthreads();
-      continue;
-    }
-    // work item: the request's descriptor into LDS (vector loads)
-    __threadfence();
-    wg_copy((unsigned long long*)&sd, (const unsigned long long*)&dd[s],
-            (int)(sizeof(ServeDesc) / sizeof(unsigned long long)));
+    // the request's descriptor into LDS
+    copy_dev_to_lds((unsigned long long*)&sd, (const unsigned long long*)&dd[s],
+                    (int)(sizeof(ServeDesc) / sizeof(unsigned long long)));
     __syncthreads();
+    // items 0 ... nA - 1 are the A tiles, nA ... nA + nB - 1 the B tiles
     const int item = citem;
     const bool isA = item < sd.nA;
+    const int tile = isA ? item : item - sd.nA;
     bool ok = true;
     if (isA) {
       if (sd.model == 1) {
-        if (sd.grad) tile_nll<1, true>(sd.seg, sd.k.m1, item);
-        else tile_nll<1, false>(sd.seg, sd.k.m1, item);
+        if (sd.grad) tile_nll<1, true, true>(sd.seg, sd.k.m1, tile);
+        else tile_nll<1, false, true>(sd.seg, sd.k.m1, tile);
       } else if (sd.model == 2) {
-        if (sd.grad) tile_nll<2, true>(sd.seg, sd.k.m2, item);
-        else tile_nll<2, false>(sd.seg, sd.k.m2, item);
+        if (sd.grad) tile_nll<2, true, true>(sd.seg, sd.k.m2, tile);
+        else tile_nll<2, false, true>(sd.seg, sd.k.m2, tile);
       } else {
-        if (sd.grad) tile_angtime<true>(sd.seg, sd.k.m3, &sd.k.m3.C[0][0], item);
-        else tile_angtime<false>(sd.seg, sd.k.m3, &sd.k.m3.C[0][0], item);
+        if (sd.grad) tile_angtime<true, true>(sd.seg, sd.k.m3, &sd.k.m3.C[0][0], tile);
+        else tile_angtime<false, true>(sd.seg, sd.k.m3, &sd.k.m3.C[0][0], tile);
       }
     } else {
       // phase B needs every A tile (their per-event factors); all A items were
       // claimed before any B item, so they are held by running workgroups
       if (threadIdx.x == 0) {
         int spins = 0;
-        while (load_dev32(&st[s].doneA) < (unsigned)sd.nA && spins < spin_limit) {
+        while (load_dev(&st[s].doneA) < (unsigned)sd.nA && spins < spin_limit) {
           __builtin_amdgcn_s_sleep(2);
           ++spins;
         }
         last = spins < spin_limit ? 1 : 0;
+        wait_mem();  // the per-event factors are read after doneA
       }
       __syncthreads();
       ok = last != 0;
-      __threadfence();
-      if (ok) tile_angtime_outer(sd.seg, item - sd.nA);
+      if (ok) tile_angtime_outer<true>(sd.seg, tile);
     }
-    // every lane's stores of this item (tile partials, per-event factors) must
-    // be visible device-wide before the item is counted as done
-    __threadfence();
+    // every lane's stores of this item (tile partials, per-event factors)
+    // complete before the item is counted as done
+    wait_mem();
     __syncthreads();
     if (threadIdx.x == 0) {
-      if (!ok) hs->status[s] = 1;
-      __threadfence();
-      if (isA) atomicAdd(&st[s].doneA, 1u);
-      const unsigned int prev = atomicAdd(&st[s].done, 1u);
+      if (!ok) store_sys(&hs->status[s], 1);
+      if (isA) __hip_atomic_fetch_add(&st[s].doneA, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned int prev = __hip_atomic_fetch_add(&st[s].done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       last = prev + 1 == (unsigned)(sd.nA + sd.nB) ? 1 : 0;
+      wait_mem();  // the partials are read after the count
     }
     __syncthreads();
     if (last) {
       // every item of the request is complete: fixed-order reduction
-      __threadfence();
       for (int comp = 0; comp < sd.nacc; ++comp) {
         const int64_t nt = comp < sd.split ? sd.seg.n_tiles : sd.seg.n_tiles_outer;
-        const double total = reduce_component(sd.seg.partials + (int64_t)comp * sd.seg.n_tiles, nt);
-        if (threadIdx.x == 0) hs->out[s][comp] = total;
+        const double total = reduce_component<true>(sd.seg.partials + (int64_t)comp * sd.seg.n_tiles, nt);
+        if (threadIdx.x == 0) store_sys(&hs->out[s][comp], total);
         __syncthreads();
       }
       if (threadIdx.x == 0) {
-        __threadfence_system();
-        store_sys(&hs->fin[s], seq);
+        wait_mem();  // the results reach host memory before fin
+        store_sys(&hs->fin[s], sd.seq);
       }
     }
     __syncthreads();
   }
+}
+
+// Workgroup 0 polls the host, the others evaluate; grid >= 2 workgroups.
+__global__ __launch_bounds__(kThreads) void k_serve(ServeShared* hs, ServeCtl* ctl, ServeDesc* __restrict__ dd,
+                                                    ServeSlot* __restrict__ st, int nslots, int idle_limit,
+                                                    int spin_limit) {
+  if (blockIdx.x == 0) serve_poll(hs, ctl, dd, st, nslots);
+  else serve_work(hs, ctl, dd, st, idle_limit, spin_limit);
 }
 
 }  // namespace ipx

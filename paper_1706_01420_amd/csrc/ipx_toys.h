@@ -90,8 +90,11 @@ __device__ __forceinline__ double conv_integral_real(double rate, double h2, dou
                                                      double gmax, double sig) {
   const double s2 = sig * sig;
   const double inv_r2s = kInvSqrt2 * rcp(sig);
-  const TimePoint pa = time_point(kTLo, gmax, s2, inv_r2s, 0.0);
-  const TimePoint pb = time_point(kTHi, gmax, s2, inv_r2s, 0.0);
+  // the generator keeps the full continued-fraction depth (its accept
+  // decisions follow the full-precision density)
+  TimePoint pa = time_point(kTLo, gmax, s2, inv_r2s, 0.0, 0.0);
+  TimePoint pb = time_point(kTHi, gmax, s2, inv_r2s, 0.0, 0.0);
+  pa.depth = pb.depth = kCfMaxDepth;
   double dphi = 0.0;
   if (pa.need) dphi += 0.5 * pa.g * erfcx_pos(kTLo * inv_r2s);
   if (pb.need) dphi -= 0.5 * pb.g * erfcx_pos(kTHi * inv_r2s);

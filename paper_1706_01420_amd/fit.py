@@ -109,6 +109,20 @@ def bfgs(evaluate, theta0, steps, edm_tol=1e-6, max_rounds=400, c1=1e-4, init_he
             "rounds": rounds, "evals": evals}
 
 
+def restrict(evaluate, theta_fixed, free):
+    """Evaluator over the free parameters only: the others stay at
+    theta_fixed (nb, np); free is a boolean mask over the np parameters."""
+    theta_fixed = np.asarray(theta_fixed, np.float64)
+    free = np.asarray(free, bool)
+
+    def sub(theta, active):
+        full = theta_fixed.copy()
+        full[:, free] = theta
+        f, g = evaluate(full, active)
+        return f, g[:, free]
+    return sub
+
+
 def errors(evaluate, theta, steps):
     """Parabolic errors: sqrt of the diagonal of the inverse FD Hessian."""
     nb, npar = theta.shape

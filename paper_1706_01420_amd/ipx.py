@@ -70,6 +70,7 @@ _SIGNATURES = [
     ("ipx_poll", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
     ("ipx_wait", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64, ctypes.c_void_p]),
     ("ipx_server_stop", ctypes.c_int, [ctypes.c_void_p]),
+    ("ipx_server_stats_read", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     ("toy_generate", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_int, _c_double_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64,
       ctypes.c_uint, _c_void_pp, ctypes.c_void_p]),
@@ -318,6 +319,17 @@ def ipx_wait(srv, ticket, timeout_s=-1.0):
 
 def ipx_server_stop(srv):
     _check(_lib.ipx_server_stop(srv))
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("published", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("launches", ctypes.c_uint64),
+                ("pending", ctypes.c_uint64), ("in_flight", ctypes.c_uint64)]
+
+
+def ipx_server_stats_read(srv):
+    r = _ServerStats()
+    _check(_lib.ipx_server_stats_read(srv, ctypes.byref(r)))
+    return {k: int(getattr(r, k)) for k, _ in _ServerStats._fields_}
 
 
 class _ToyStats(ctypes.Structure):

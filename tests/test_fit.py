@@ -56,3 +56,20 @@ def test_rosenbrock_with_infinite_region():
     r = fit.bfgs(ev, np.array([[-1.2, 1.0]]), 0.1, edm_tol=1e-14, max_rounds=2000)
     assert r["converged"][0]
     assert np.allclose(r["theta"][0], [1.0, 1.0], atol=1e-5)
+
+
+def test_restrict_holds_fixed_parameters():
+    # conditional minimum of a quadratic with parameter 1 held at c:
+    # x_free = x*_free - A_ff^{-1} A_f1 (c - x*_1)
+    ev, A, xstar = quad_problem(3, 4, 2)
+    c = 0.7
+    free = np.array([True, False, True, True])
+    fixed = np.zeros((3, 4))
+    fixed[:, 1] = c
+    r = fit.bfgs(fit.restrict(ev, fixed, free), np.zeros((3, 3)), 0.1)
+    assert r["converged"].all()
+    for j in range(3):
+        Aff = A[j][np.ix_(free, free)]
+        Af1 = A[j][free, 1]
+        ref = xstar[j, free] - np.linalg.solve(Aff, Af1 * (c - xstar[j, 1]))
+        assert np.allclose(r["theta"][j], ref, atol=1e-6)

@@ -17,6 +17,8 @@ import sys
 import numpy as np
 import pytest
 
+from storage_order import band_order
+
 from oracle import models as M
 from oracle import nll as N
 from paper_1706_01420_amd import workloads as W
@@ -206,20 +208,20 @@ def test_borrowed_device_columns_and_torch_stream(lib, ctx, model):
 
 
 @pytest.mark.parametrize("model", [2, 3])
-def test_time_sorted_store_is_a_sorted_permutation(lib, ctx, model):
+def test_band_ordered_store_is_the_documented_permutation(lib, ctx, model):
     cols, w = small_data(model, n=6000, seed=12)
-    ds = lib.ipx_dataset_create(ctx, model, cols, w)                      # sorted by t
+    ds = lib.ipx_dataset_create(ctx, model, cols, w)                      # resolution-band order
     dk = lib.ipx_dataset_create(ctx, model, cols, w, flags=lib.IPX_COPY_HOST | lib.IPX_KEEP_ORDER)
     try:
-        say("sorted store model", model)
-        tcol = 1 if model == 2 else 3
+        say("band-ordered store model", model)
+        tcol, scol = (1, 2) if model == 2 else (3, 4)
         got = [lib.ipx_dataset_read(ctx, ds, c) for c in range(len(cols))]
-        t = got[tcol]
-        assert np.all(np.diff(t) >= 0)
-        order = np.argsort(cols[tcol], kind="stable")
+        order = band_order(cols[tcol], cols[scol])
         for c in range(len(cols)):
             assert np.array_equal(np.sort(got[c]), np.sort(cols[c]))
             assert np.array_equal(got[c], cols[c][order])
+        if w is not None:
+            assert np.array_equal(lib.ipx_dataset_read(ctx, ds, len(cols)), w[order])
         th = thetas(model, 2)[1]
         a, b = lib.nll_eval(ctx, ds, th), lib.nll_eval(ctx, dk, th)
         assert abs(a - b) <= 1e-13 * abs(b)

@@ -16,6 +16,13 @@ from paper_1706_01420_amd import fit, toys
 pytestmark = pytest.mark.gpu
 
 CASES = {1: (200, 20000), 2: (200, 20000), 3: (160, 40000)}
+# Parameters held at their generated values.  In the mass x decay-time model
+# the resolution scale s only enters through the resolution tail at the lower
+# time bound (0.3 ps, at least 5 sigma_t away for sigma_t <= 0.06 ps): away
+# from it the Gaussian factor exp(Gamma^2 s^2 sigma_t^2 / 2) of the convolved
+# exponential cancels between the per-event density and its normalisation, so
+# the samples carry almost no information on s and it is not fitted.
+FIXED = {1: (), 2: (6,), 3: ()}
 
 
 def say(*a):
@@ -43,14 +50,16 @@ def test_pulls(lib, ctx, model):
     ds = toys.generate(lib, ctx, model, theta, 4242 + model, [n] * ntoys, flags=lib.IPX_NO_WEIGHTS)
     plan = lib.ipx_plan_create(ctx, ds)
     try:
-        ev = toys.batched_evaluator(lib, ctx, plan)
-        steps = toys.steps_for(model, [n] * ntoys)
-        start = np.tile(theta, (ntoys, 1)) + 0.5 * steps
+        free = np.ones(theta.size, bool)
+        free[list(FIXED[model])] = False
+        ev = fit.restrict(toys.batched_evaluator(lib, ctx, plan), np.tile(theta, (ntoys, 1)), free)
+        steps = toys.steps_for(model, [n] * ntoys)[:, free]
+        start = np.tile(theta[free], (ntoys, 1)) + 0.5 * steps
         res = fit.bfgs(ev, start, steps)
         assert res["converged"].mean() > 0.97, res["converged"].mean()
         ok = res["converged"]
         err = fit.errors(ev, res["theta"], steps)
-        pulls = (res["theta"][ok] - theta) / err[ok]
+        pulls = (res["theta"][ok] - theta[free]) / err[ok]
         good = np.all(np.isfinite(pulls), axis=1)
         pulls = pulls[good]
         m = pulls.mean(axis=0)

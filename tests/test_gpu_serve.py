@@ -171,3 +171,27 @@ def test_stop_drains_pending_requests(lib, ctx, datasets):
     lib.ipx_server_stop(srv)
     # the server is gone; its results were computed before it stopped
     assert len(tickets) == 6
+
+
+def test_two_workgroups_and_counters(lib, ctx, datasets):
+    # one poller and one worker: the worker takes every per-event tile before
+    # the coefficient-adjoint tiles, so the angular gradient needs no second
+    # workgroup; the host counters account for every request
+    with pytest.raises(lib.IpxError):
+        lib.ipx_server_start(ctx, workgroups=1)
+    srv = lib.ipx_server_start(ctx, slots=4, workgroups=2)
+    try:
+        rng = np.random.default_rng(7)
+        n = 0
+        for model, d in datasets:
+            th = _theta(model, rng)
+            say("serve two workgroups model", model)
+            r = lib.ipx_wait(srv, lib.ipx_submit(srv, d, th, True), 60.0)
+            f, g = _plain(lib, ctx, d, th, True)
+            assert r["status"] == 0 and r["nll"] == f and np.array_equal(r["grad"], g)
+            n += 1
+        st = lib.ipx_server_stats_read(srv)
+        assert st["published"] == n and st["completed"] == n
+        assert st["pending"] == 0 and st["in_flight"] == 0 and st["launches"] >= 1
+    finally:
+        lib.ipx_server_stop(srv)
