@@ -22,18 +22,69 @@ METRIC = "NLL+grad evaluations/sec and events/sec (FP64); fits/sec batched vs pl
 PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 FLOP/clk
 PEAK_HBM_GBS = 8000.0
 
-# Algorithmic FP64 operations per event, counted on the formulas (not on the
-# generated code): +, -, x, / and sqrt 1; a*b+c 2; exp and log 20; a sin/cos
-# pair 40; erfcx by its 10-level continued fraction 74; complex w 230.  The
-# resolution correction is counted for the fraction of events that need it
-# (91 % at the lower time bound, 13 % at the event time, 0 at the upper bound
-# for sigma_t ~ U(0.03, 0.06) ps).  Table and derivation in the design doc.
-FLOP_PER_EVENT = {
+# Algorithmic FP64 operations, counted on the formulas (not on the generated
+# code): +, -, x, / and sqrt 1; a*b+c 2; exp and log 20; a sin/cos pair 40.
+# Per event outside the resolution corrections:
+FLOP_BASE = {
     (1, False): 73, (1, True): 93,
-    (2, False): 444, (2, True): 584,
-    (3, False): 966, (3, True): 1090,      # angular: per-event kernel
+    (2, False): 193, (2, True): 348,
+    (3, False): 467, (3, True): 592,      # angular: per-event kernel
 }
 FLOP_OUTER = 162                           # angular gradient: coefficient-adjoint kernel
+# A resolution correction needed at one time point costs a + b K with K the
+# continued-fraction depth of the wave (a real erfcx is 6 + 7K, the complex w
+# 25 + 21K): at the range ends (with the Phi term of the normalisation) and at
+# the event time t.
+CORR_FLOP = {2: {"range": (56, 21), "t": (46, 14)}, 3: {"range": (88, 42), "t": (78, 35)}}
+# Continued-fraction depth table (paper_1706_01420_amd/csrc/cf_depth.h).
+CF_DEPTH_E = [24.625, 20.875, 17.875, 15.625, 13.750, 12.375, 10.625, 8.375, 6.375]
+CORR_SKIP = 42.0
+T_LO, T_HI = 0.3, 15.0
+
+
+def _wave_depths(x, re2, e_shift):
+    """Per-lane need flag and the wave's depth at one time point, as the
+    kernel decides them (waves = 64 consecutive stored events)."""
+    import numpy as np
+    with np.errstate(invalid="ignore"):
+        E = np.where(x > 0.0, x * x - re2, -1.0)
+    need = ~(E > CORR_SKIP)
+    eff = np.where(need, E - e_shift, CORR_SKIP)
+    k_lane = 1 + sum((eff < th).astype(np.int64) for th in CF_DEPTH_E)
+    n = k_lane.size
+    pad = (-n) % 64
+    kw = np.concatenate([k_lane, np.ones(pad, np.int64)]).reshape(-1, 64).max(axis=1)
+    return need, np.repeat(kw, 64)[:n]
+
+
+def algorithmic_flops(model, t, sig_t, theta, grad):
+    """FP64 operations of one evaluation of the per-event kernel over the
+    stored events (t, sigma_t in storage order): the base count per event plus
+    every needed correction at the depth its wave uses."""
+    import numpy as np
+    n = t.size
+    total = float(FLOP_BASE[(model, grad)]) * n
+    if model == 1:
+        return total
+    if model == 2:
+        gmax = max(1.0 / theta[4], 1.0 / theta[5])
+        sig = theta[6] * sig_t
+        re2 = np.zeros(n)
+    else:
+        g, dg, dm = theta[6], theta[7], theta[8]
+        gmax = g + abs(dg) / 2.0
+        sig = sig_t
+        re2 = (dm * sig / np.sqrt(2.0)) ** 2
+    inv_r2s = 1.0 / (np.sqrt(2.0) * sig)
+    s2 = sig * sig
+    for tau, kind, shift in ((t, "t", 0.0), (T_LO, "range", gmax * T_LO), (T_HI, "range", gmax * T_HI)):
+        x = (tau - gmax * s2) * inv_r2s
+        need, kw = _wave_depths(x, re2, shift)
+        a, b = CORR_FLOP[model][kind]
+        total += float(np.sum(np.where(need, a + b * kw, 0)))
+    return total
+
+
 BYTES_PER_EVENT = {1: 8, 2: 24, 3: 56}
 
 
@@ -54,8 +105,8 @@ def parse():
 # HBM traffic of the dominant kernel from the rocprofv3 FETCH_SIZE / WRITE_SIZE
 # runs (scaled by the calibration copy), valid for the kernel sources whose
 # hash is recorded with it; reported as null once those sources change.
-TRAFFIC = {"sources_sha256": "176fd9ef256fd8767696d4026f015fba862209d3167680d99e071f11a8c36aff", "bytes_per_launch": 354470336}
-KERNEL_SOURCES = ["ipx_kernels.h", "ipx_batch.h", "ipx_math.h", "ipx_models.h", "weideman_coeffs.h"]
+TRAFFIC = {"sources_sha256": "15cc26b63a45043adfe49e989d381504bf68ef63bd6b966e2e8fe8bfb9f67f3f", "bytes_per_launch": 354516771}
+KERNEL_SOURCES = ["ipx_kernels.h", "ipx_batch.h", "ipx_math.h", "ipx_models.h", "weideman_coeffs.h", "cf_depth.h"]
 
 
 def kernel_sources_hash():
@@ -264,7 +315,9 @@ def main():
 
     step_s, kernel_s = timed_rate(ipx, ctx, ds, theta, args.steps, args.warmup, grad=True)
     value = 1.0 / step_s
-    flops = FLOP_PER_EVENT[(model, True)] * n
+    # the stored (reordered) decay times and widths decide the corrections
+    t_st, s_st = ipx.ipx_dataset_read(ctx, ds, 3), ipx.ipx_dataset_read(ctx, ds, 4)
+    flops = algorithmic_flops(model, t_st, s_st, theta, True)
     achieved = flops / kernel_s / 1e12
     out = {
         "metric": METRIC,
@@ -288,13 +341,14 @@ def main():
                      "traffic": TRAFFIC["bytes_per_launch"] if TRAFFIC["sources_sha256"] == kernel_sources_hash() else None,
                      "traffic_unit": "bytes",
                      "kernel": "k_angtime_batch<true>", "kernel_us": kernel_s * 1e6,
-                     "flop_per_event": FLOP_PER_EVENT[(model, True)]},
+                     "flop_per_event": flops / n},
     }
     extra = {}
     if not args.no_extra:
         e_step, e_kern = timed_rate(ipx, ctx, ds, theta, max(args.steps // 2, 5), 2, grad=False)
+        fe = algorithmic_flops(model, t_st, s_st, theta, False)
         extra["angtime_nll_eval"] = {"evals_per_s": 1 / e_step, "kernel_us": e_kern * 1e6,
-                                     "tflops": FLOP_PER_EVENT[(3, False)] * n / e_kern / 1e12}
+                                     "flop_per_event": fe / n, "tflops": fe / e_kern / 1e12}
     ipx.ipx_dataset_destroy(ctx, ds)
     if not args.no_extra:
         for m in (1, 2):
@@ -302,12 +356,16 @@ def main():
             c, wm = workloads.events(m, nm)
             d = ipx.ipx_dataset_create(ctx, m, c, wm)
             th = np.array(workloads.THETA_GEN[m])
+            tm = sm = None
+            if m == 2:
+                tm, sm = ipx.ipx_dataset_read(ctx, d, 1), ipx.ipx_dataset_read(ctx, d, 2)
             for grad in (False, True):
                 s, k = timed_rate(ipx, ctx, d, th, max(args.steps // 2, 5), 2, grad)
                 key = ("mass" if m == 1 else "masstime") + ("_nll_grad" if grad else "_nll_eval")
+                fm = algorithmic_flops(m, tm, sm, th, grad) if m == 2 else FLOP_BASE[(m, grad)] * nm
                 extra[key] = {"n_events": nm, "evals_per_s": 1 / s, "us_per_eval": s * 1e6,
-                              "kernel_us": k * 1e6,
-                              "tflops": FLOP_PER_EVENT[(m, grad)] * nm / k / 1e12,
+                              "kernel_us": k * 1e6, "flop_per_event": fm / nm,
+                              "tflops": fm / k / 1e12,
                               "hbm_gbs": BYTES_PER_EVENT[m] * nm / k / 1e9}
             ipx.ipx_dataset_destroy(ctx, d)
         out["extra"] = extra

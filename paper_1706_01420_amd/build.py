@@ -33,6 +33,10 @@ def command(out=LIB, extra=()):
             # and come back through per-iteration lane reads (measured: the
             # angular gradient kernel 15 % faster)
             "-mllvm", "-disable-machine-licm",
+            # a*b+c fused where the source writes it, never across statements:
+            # the same tile code inlined into different kernels (one-shot,
+            # batched, served) then rounds identically
+            "-ffp-contract=on",
             "-I", os.path.join(ROOT, "include"), "-I", CSRC,
             *extra, "-o", out] + [os.path.join(CSRC, s) for s in SOURCES]
 
