@@ -33,8 +33,9 @@ FLOP_BASE = {
 FLOP_OUTER = 162                           # angular gradient: coefficient-adjoint kernel
 # A resolution correction needed at one time point costs a + b K with K the
 # continued-fraction depth of the wave (a real erfcx is 6 + 7K, the complex w
-# 25 + 21K): at the range ends (with the Phi term of the normalisation) and at
-# the event time t.
+# 25 + 21K; the levels after the first run in pairs, so K is the table's depth
+# rounded up to odd, at most 10): at the range ends (with the Phi term of the
+# normalisation) and at the event time t.
 CORR_FLOP = {2: {"range": (56, 21), "t": (46, 14)}, 3: {"range": (88, 42), "t": (78, 35)}}
 # Continued-fraction depth table (paper_1706_01420_amd/csrc/cf_depth.h).
 CF_DEPTH_E = [24.625, 20.875, 17.875, 15.625, 13.750, 12.375, 10.625, 8.375, 6.375]
@@ -54,6 +55,7 @@ def _wave_depths(x, re2, e_shift):
     n = k_lane.size
     pad = (-n) % 64
     kw = np.concatenate([k_lane, np.ones(pad, np.int64)]).reshape(-1, 64).max(axis=1)
+    kw = np.where(kw >= 10, 10, kw | 1)     # levels run in pairs after the first
     return need, np.repeat(kw, 64)[:n]
 
 

@@ -33,9 +33,9 @@ struct TileRef {
 // k may live in device memory, kernel arguments or LDS: the arithmetic is the
 // same, so a tile's partials do not depend on which kernel computed them.
 // ---------------------------------------------------------------------------
-template <int MODEL, bool GRAD, bool COH = false>
+template <int MODEL, bool GRAD, bool COH, int CAP>
 __device__ __forceinline__ void tile_nll(const SegInfo& S, const typename ModelTraits<MODEL>::Const& k,
-                                         int64_t tile) {
+                                         int64_t tile, RedBuf<CAP>& red) {
   constexpr int NACC = GRAD ? ModelTraits<MODEL>::kAcc : 1;
   double acc[NACC];
 #pragma unroll
@@ -46,13 +46,13 @@ __device__ __forceinline__ void tile_nll(const SegInfo& S, const typename ModelT
     const unsigned j = threadIdx.x + (unsigned)e * kThreads;
     if (base + j < S.cols.n) event<MODEL, GRAD, COH>(k, S.cols, base, j, acc);
   }
-  tile_store<NACC, COH>(acc, S.partials, tile, S.n_tiles);
+  tile_store<NACC, COH>(acc, S.partials, tile, S.n_tiles, red);
 }
 
 // Angular model; C is the coefficient table in LDS.
-template <bool GRAD, bool COH = false>
+template <bool GRAD, bool COH, int CAP>
 __device__ __forceinline__ void tile_angtime(const SegInfo& S, const AngTimeConst& k, const double* C,
-                                             int64_t tile) {
+                                             int64_t tile, RedBuf<CAP>& red) {
   constexpr int NACC = GRAD ? kAngInner : 1;
   double acc[NACC];
 #pragma unroll
@@ -72,12 +72,12 @@ __device__ __forceinline__ void tile_angtime(const SegInfo& S, const AngTimeCons
                                ldg<COH>(cl.c[5] + base, j), w, acc, S.tau + base, S.tau_stride, j);
     }
   }
-  tile_store<NACC, COH>(acc, S.partials, tile, S.n_tiles);
+  tile_store<NACC, COH>(acc, S.partials, tile, S.n_tiles, red);
 }
 
 // Angular gradient: coefficient adjoints over one outer tile.
-template <bool COH = false>
-__device__ __forceinline__ void tile_angtime_outer(const SegInfo& S, int64_t tile) {
+template <bool COH, int CAP>
+__device__ __forceinline__ void tile_angtime_outer(const SegInfo& S, int64_t tile, RedBuf<CAP>& red) {
   double acc[kAngOuter];
 #pragma unroll
   for (int c = 0; c < kAngOuter; ++c) acc[c] = 0.0;
@@ -102,7 +102,7 @@ __device__ __forceinline__ void tile_angtime_outer(const SegInfo& S, int64_t til
       }
     }
   }
-  tile_store<kAngOuter, COH>(acc, S.partials + kAngOuter0 * S.n_tiles, tile, S.n_tiles);
+  tile_store<kAngOuter, COH>(acc, S.partials + kAngOuter0 * S.n_tiles, tile, S.n_tiles, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -114,11 +114,13 @@ __global__ __launch_bounds__(kThreads) void k_nll_batch(const SegInfo* __restric
                                                         const TileRef* __restrict__ tiles, int64_t n_tiles,
                                                         const typename ModelTraits<MODEL>::Const* __restrict__ consts,
                                                         const unsigned char* __restrict__ active) {
+  constexpr int kCap = GRAD ? ModelTraits<MODEL>::kAcc : 1;
+  __shared__ RedBuf<kCap> red;
   for (int64_t g = blockIdx.x; g < n_tiles; g += gridDim.x) {
     const TileRef tr = tiles[g];
     if (!active[tr.seg]) continue;
     const typename ModelTraits<MODEL>::Const k = consts[tr.seg];
-    tile_nll<MODEL, GRAD>(segs[tr.seg], k, tr.tile);
+    tile_nll<MODEL, GRAD, false>(segs[tr.seg], k, tr.tile, red);
   }
 }
 
@@ -129,13 +131,14 @@ __global__ __launch_bounds__(kThreads) void k_angtime_batch(const SegInfo* __res
                                                             const AngTimeConst* __restrict__ consts,
                                                             const unsigned char* __restrict__ active) {
   __shared__ double sC[40];
+  __shared__ RedBuf<GRAD ? kAngInner : 1> red;
   for (int64_t g = blockIdx.x; g < n_tiles; g += gridDim.x) {
     const TileRef tr = tiles[g];
     if (!active[tr.seg]) continue;
     const AngTimeConst& k = consts[tr.seg];
     if (threadIdx.x < 40) sC[threadIdx.x] = (&k.C[0][0])[threadIdx.x];
     __syncthreads();
-    tile_angtime<GRAD>(segs[tr.seg], k, sC, tr.tile);
+    tile_angtime<GRAD, false>(segs[tr.seg], k, sC, tr.tile, red);
   }
 }
 
@@ -144,10 +147,11 @@ __global__ __launch_bounds__(kThreads) void k_angtime_outer_batch(const SegInfo*
                                                                   const TileRef* __restrict__ tiles,
                                                                   int64_t n_tiles,
                                                                   const unsigned char* __restrict__ active) {
+  __shared__ RedBuf<kAngOuter / 2> red;
   for (int64_t g = blockIdx.x; g < n_tiles; g += gridDim.x) {
     const TileRef tr = tiles[g];
     if (!active[tr.seg]) continue;
-    tile_angtime_outer(segs[tr.seg], tr.tile);
+    tile_angtime_outer<false>(segs[tr.seg], tr.tile, red);
   }
 }
 

@@ -5,10 +5,10 @@
 // tile*kTile + e*256 + lane, so each load instruction of a wave reads 64
 // consecutive doubles of a column), keeping the running sums of ln P and, for
 // the gradient kernels, of the adjoints in registers.  At the end of a tile
-// the sums are reduced across the wave by an xor butterfly (every lane ends
-// with the same, order-fixed total), across the four waves through LDS in wave
-// order, and written as one partial per tile (component-major).  A second
-// kernel sums the tile partials of each component in index order.
+// the sums are reduced across each wave through an LDS transpose (one lane per
+// component adds the 64 lane values in a fixed order), across the four waves
+// in wave order, and written as one partial per tile (component-major).  A
+// second kernel sums the tile partials of each component in index order.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -56,20 +56,51 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-template <int NACC, bool COH = false>
+// Tile reduction through LDS.  Each wave writes its lanes' sums column-wise
+// into an LDS block (component-major rows of 64 lanes, padded to 65 doubles
+// so that the row reads below spread over the banks); then lane c of the wave
+// adds row c in a fixed order (four interleaved partial sums over the lanes,
+// combined pairwise).  Components are done in chunks of at most CAP rows (the
+// block the kernel provides: kThreads / 64 waves x CAP rows x kRedPitch).  The
+// four wave totals are combined in wave order.  Every order is a function of
+// the tile's lane layout only.
+constexpr int kRedPitch = 65;
+
+template <int CAP>
+struct RedBuf {
+  double rows[kThreads / 64][CAP][kRedPitch];
+  double wsum[kThreads / 64][kAccMax];
+};
+
+template <int NACC, bool COH, int CAP>
 __device__ __forceinline__ void tile_store(const double (&acc)[NACC], double* __restrict__ partials,
-                                           int64_t tile, int64_t n_tiles) {
-  __shared__ double lds[kThreads / 64][NACC];
+                                           int64_t tile, int64_t n_tiles, RedBuf<CAP>& red) {
+  constexpr int kChunk = NACC < CAP ? NACC : CAP;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int c = 0; c < NACC; ++c) {
-    const double v = wave_sum(acc[c]);
-    if (lane == 0) lds[wave][c] = v;
+  for (int c0 = 0; c0 < NACC; c0 += kChunk) {
+#pragma unroll
+    for (int c = 0; c < kChunk; ++c)
+      if (c0 + c < NACC) red.rows[wave][c][lane] = acc[c0 + c];
+    __syncthreads();
+    if (lane < kChunk && c0 + lane < NACC) {
+      const double* row = red.rows[wave][lane];
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll 4
+      for (int r = 0; r < 64; r += 4) {
+        s0 += row[r];
+        s1 += row[r + 1];
+        s2 += row[r + 2];
+        s3 += row[r + 3];
+      }
+      red.wsum[wave][c0 + lane] = (s0 + s1) + (s2 + s3);
+    }
+    __syncthreads();
   }
-  __syncthreads();
   for (int c = threadIdx.x; c < NACC; c += kThreads)
-    stg<COH>(partials + (int64_t)c * n_tiles + tile, 0u, (lds[0][c] + lds[1][c]) + (lds[2][c] + lds[3][c]));
+    stg<COH>(partials + (int64_t)c * n_tiles + tile, 0u,
+             (red.wsum[0][c] + red.wsum[1][c]) + (red.wsum[2][c] + red.wsum[3][c]));
   __syncthreads();
 }
 

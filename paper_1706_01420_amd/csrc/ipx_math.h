@@ -96,22 +96,78 @@ __device__ __forceinline__ int cf_depth_wave(double E) {
   return hi;
 }
 
+// One level K of the Jacobi fraction's Wallis recurrences, constants folded at
+// compile time: P_K = (z^2 - (2K + 1/2)) P_{K-1} - c_K P_{K-2}, the same for
+// Q, c_K = (2K - 1)(2K)/4.  The two newest numerators live in p and pm and are
+// updated in place, alternating (odd K writes pm, even K writes p), so that
+// every early exit leaves them in the same registers.
+template <int K>
+__device__ __forceinline__ void cf_level(const cplx& z2, cplx& p, cplx& q, cplx& pm, cplx& qm) {
+  constexpr double a = 2.0 * K + 0.5;
+  constexpr double c = (2.0 * K - 1.0) * (2.0 * K) * 0.25;
+  const cplx d{z2.re - a, z2.im};
+  if constexpr (K % 2 == 1) {
+    pm = csub(cmul(d, p), cscale(pm, c));
+    qm = csub(cmul(d, q), cscale(qm, c));
+  } else {
+    p = csub(cmul(d, pm), cscale(p, c));
+    q = csub(cmul(d, qm), cscale(q, c));
+  }
+}
+
+template <int K>
+__device__ __forceinline__ void cf_level(const double& z2, double& p, double& q, double& pm, double& qm) {
+  constexpr double a = 2.0 * K + 0.5;
+  constexpr double c = (2.0 * K - 1.0) * (2.0 * K) * 0.25;
+  const double d = z2 - a;
+  if constexpr (K % 2 == 1) {
+    pm = d * p - c * pm;
+    qm = d * q - c * qm;
+  } else {
+    p = d * pm - c * p;
+    q = d * qm - c * q;
+  }
+}
+
+// Levels 1 .. depth' with depth' = depth rounded up to odd, at most 10 (depth
+// wave-uniform, 1 .. kCfMaxDepth): uniform branches around pairs of
+// straight-line levels.  On return (p, q) hold P_depth', Q_depth'.
+template <typename T>
+__device__ __forceinline__ void cf_levels(const T& z2, T& p, T& q, T& pm, T& qm, int depth) {
+  static_assert(kCfMaxDepth == 10, "the level calls below spell out 10 levels");
+  cf_level<1>(z2, p, q, pm, qm);
+  if (depth >= 2) {
+    cf_level<2>(z2, p, q, pm, qm);
+    cf_level<3>(z2, p, q, pm, qm);
+    if (depth >= 4) {
+      cf_level<4>(z2, p, q, pm, qm);
+      cf_level<5>(z2, p, q, pm, qm);
+      if (depth >= 6) {
+        cf_level<6>(z2, p, q, pm, qm);
+        cf_level<7>(z2, p, q, pm, qm);
+        if (depth >= 8) {
+          cf_level<8>(z2, p, q, pm, qm);
+          cf_level<9>(z2, p, q, pm, qm);
+          if (depth >= 10) cf_level<10>(z2, p, q, pm, qm);
+        }
+      }
+    }
+  }
+  // an odd last level leaves the newest numerators in pm, qm
+  if (depth < 10) {
+    p = pm;
+    q = qm;
+  }
+}
+
 // Jacobi continued fraction with `depth` levels (1 .. 10, wave-uniform),
 // forward Wallis recurrences.  Valid (and used) for Im z >= 3.4 or |z| >= 6
 // with |z| <= 1e6; 10 levels give full precision there.
 __device__ __forceinline__ cplx faddeeva_cf(cplx z, int depth) {
   const cplx z2 = cmul(z, z);
-  cplx pm{1.0, 0.0}, qm{0.0, 0.0};      // P_{-1}, Q_{-1}
+  cplx pm{1.0, 0.0}, qm{0.0, 0.0};          // P_{-1}, Q_{-1}
   cplx p{z2.re - 0.5, z2.im}, q{1.0, 0.0};  // P_0, Q_0
-#pragma unroll
-  for (int k = 1; k <= kCfMaxDepth; ++k) {
-    if (k > depth) break;
-    const cplx d{z2.re - (2.0 * k + 0.5), z2.im};
-    const double c = (2.0 * k - 1.0) * (2.0 * k) * 0.25;
-    const cplx pn = csub(cmul(d, p), cscale(pm, c));
-    const cplx qn = csub(cmul(d, q), cscale(qm, c));
-    pm = p; qm = q; p = pn; q = qn;
-  }
+  cf_levels(z2, p, q, pm, qm, depth);
   // w = i z Q / (sqrt(pi) P)
   const cplx izq = cmul(cplx{-z.im, z.re}, q);
   return cdiv(cscale(izq, kInvSqrtPi), p);
@@ -153,15 +209,7 @@ __device__ __forceinline__ double erfcx_pos(double y, int depth = kCfMaxDepth) {
   if (y > 1e6) return kInvSqrtPi / y * (1.0 - 0.5 / (y * y));
   const double z2 = -y * y;
   double pm = 1.0, qm = 0.0, p = z2 - 0.5, q = 1.0;
-#pragma unroll
-  for (int k = 1; k <= kCfMaxDepth; ++k) {
-    if (k > depth) break;
-    const double d = z2 - (2.0 * k + 0.5);
-    const double c = (2.0 * k - 1.0) * (2.0 * k) * 0.25;
-    const double pn = d * p - c * pm;
-    const double qn = d * q - c * qm;
-    pm = p; qm = q; p = pn; q = qn;
-  }
+  cf_levels(z2, p, q, pm, qm, depth);
   return -y * q * kInvSqrtPi * rcp(p);
 }
 

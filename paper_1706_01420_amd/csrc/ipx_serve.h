@@ -188,6 +188,7 @@ __device__ __forceinline__ void serve_poll(ServeShared* hs, ServeCtl* ctl, Serve
 __device__ __forceinline__ void serve_work(ServeShared* hs, ServeCtl* ctl, ServeDesc* __restrict__ dd,
                                            ServeSlot* __restrict__ st, int idle_limit, int spin_limit) {
   __shared__ ServeDesc sd;          // the current item's request
+  __shared__ RedBuf<kAngOuter / 2> red;
   __shared__ int cmd, cslot, citem;
   __shared__ int last;
   int idle = 0;
@@ -245,14 +246,14 @@ __device__ __forceinline__ void serve_work(ServeShared* hs, ServeCtl* ctl, Serve
     bool ok = true;
     if (isA) {
       if (sd.model == 1) {
-        if (sd.grad) tile_nll<1, true, true>(sd.seg, sd.k.m1, tile);
-        else tile_nll<1, false, true>(sd.seg, sd.k.m1, tile);
+        if (sd.grad) tile_nll<1, true, true>(sd.seg, sd.k.m1, tile, red);
+        else tile_nll<1, false, true>(sd.seg, sd.k.m1, tile, red);
       } else if (sd.model == 2) {
-        if (sd.grad) tile_nll<2, true, true>(sd.seg, sd.k.m2, tile);
-        else tile_nll<2, false, true>(sd.seg, sd.k.m2, tile);
+        if (sd.grad) tile_nll<2, true, true>(sd.seg, sd.k.m2, tile, red);
+        else tile_nll<2, false, true>(sd.seg, sd.k.m2, tile, red);
       } else {
-        if (sd.grad) tile_angtime<true, true>(sd.seg, sd.k.m3, &sd.k.m3.C[0][0], tile);
-        else tile_angtime<false, true>(sd.seg, sd.k.m3, &sd.k.m3.C[0][0], tile);
+        if (sd.grad) tile_angtime<true, true>(sd.seg, sd.k.m3, &sd.k.m3.C[0][0], tile, red);
+        else tile_angtime<false, true>(sd.seg, sd.k.m3, &sd.k.m3.C[0][0], tile, red);
       }
     } else {
       // phase B needs every A tile (their per-event factors); all A items were
@@ -268,7 +269,7 @@ __device__ __forceinline__ void serve_work(ServeShared* hs, ServeCtl* ctl, Serve
       }
       __syncthreads();
       ok = last != 0;
-      if (ok) tile_angtime_outer<true>(sd.seg, tile);
+      if (ok) tile_angtime_outer<true>(sd.seg, tile, red);
     }
     // every lane's stores of this item (tile partials, per-event factors)
     // complete before the item is counted as done
