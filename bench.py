@@ -107,7 +107,7 @@ def parse():
 # HBM traffic of the dominant kernel from the rocprofv3 FETCH_SIZE / WRITE_SIZE
 # runs (scaled by the calibration copy), valid for the kernel sources whose
 # hash is recorded with it; reported as null once those sources change.
-TRAFFIC = {"sources_sha256": "15cc26b63a45043adfe49e989d381504bf68ef63bd6b966e2e8fe8bfb9f67f3f", "bytes_per_launch": 354516771}
+TRAFFIC = {"sources_sha256": "b5f07dca766a115e2f8b1999c40c8a6e8fd7f87b5926cdbddf5575c20c14acca", "bytes_per_launch": 376497318}
 KERNEL_SOURCES = ["ipx_kernels.h", "ipx_batch.h", "ipx_math.h", "ipx_models.h", "weideman_coeffs.h", "cf_depth.h"]
 
 

@@ -110,9 +110,9 @@ IPX_API int ipx_model_ncols(int model);
  * With IPX_COPY_*, the library owns the device copy (one allocation, columns
  * padded to 256-byte boundaries); the models with a decay time store it in
  * resolution-band order (unless IPX_KEEP_ORDER): a stable sort by the key
- * (b << 58) | (bits(sigma_t) >> 6), b = min(floor(2 t / sigma_t), 20) (0 when
- * not positive), so that the events of a wave need the same resolution
- * corrections.  The NLL is a sum over events, so the order changes only its
+ * (b << 58) | ((2^63 - 1 - bits(sigma_t)) >> 6), b = min(floor(2 t / sigma_t),
+ * 20) (0 when not positive), i.e. by band, then by decreasing sigma_t, so that
+ * the events of a wave need the same resolution corrections.  The NLL is a sum over events, so the order changes only its
  * rounding.  The dataset also holds the scratch for its
  * reduction partials, so calls on different datasets may run concurrently on
  * different streams; calls on one dataset must not overlap.
@@ -261,6 +261,18 @@ typedef struct {
 IPX_API ipx_status toy_generate(ipx_ctx *ctx, int model, const double *theta_gen, int np, uint64_t seed,
                                 uint64_t toy_id, int64_t n, unsigned flags, ipx_dataset **out,
                                 ipx_toy_stats *stats);
+/*
+ * Many toys at once (Example 5 of the paper: hundreds of pseudo-experiments):
+ * out[j] (ntoys caller-owned datasets) holds exactly what toy_generate with
+ * toy_id = toy_ids[j] and n = n[j] gives, with the same flags; each round
+ * generates the candidates of every toy still short of events in one launch.
+ * stats (nullable) has ntoys entries; n_violations counts the candidates
+ * evaluated, which may extend past the last accepted one differently from
+ * toy_generate.  On error no dataset is returned (out[j] = NULL).
+ */
+IPX_API ipx_status toy_generate_batch(ipx_ctx *ctx, int model, const double *theta_gen, int np, uint64_t seed,
+                                      int ntoys, const uint64_t *toy_ids, const int64_t *n, unsigned flags,
+                                      ipx_dataset **out, ipx_toy_stats *stats);
 
 /*
  * Timing of the dominant kernel of nll_eval/nll_grad, measured with HIP events

@@ -99,11 +99,14 @@ static const int kNCols[4] = {-1, 1, 3, 6};
 // ---------------------------------------------------------------------------
 // Event-store ordering for the models with a decay time: by the band of
 // t / sigma_t (width 1/2, the last band open above t / sigma_t = 10), then by
-// sigma_t within a band.  The resolution correction at t and the depth of its
-// continued fraction depend on t / sigma_t; those at the range ends and the
-// normalisation on sigma_t alone; so the waves of this order need the same
-// corrections at about the same depth.  The NLL is a sum over events: the
-// order only changes the rounding of the sum.
+// decreasing sigma_t within a band.  The resolution correction at t and the
+// depth of its continued fraction depend on t / sigma_t; those at the range
+// ends and the normalisation on sigma_t alone; so the waves of this order need
+// the same corrections at about the same depth.  Tiles run in storage order:
+// the low bands (correction at t) and the wide resolutions (deep corrections
+// at the range ends) come first and the cheapest tiles last, which keeps the
+// tail of a launch short.  The NLL is a sum over events: the order only
+// changes the rounding of the sum.
 // ---------------------------------------------------------------------------
 __global__ void k_iota(int* __restrict__ v, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -116,15 +119,16 @@ __global__ void k_gather(double* __restrict__ dst, const double* __restrict__ sr
 }
 constexpr int kBands = 21;   // bands 0 .. 20 of 2 t / sigma_t (5 bits)
 
-// key = band << 58 | (bits of sigma_t) >> 6; sigma_t > 0, so its bit pattern
-// orders as its value
+// key = band << 58 | (2^63 - 1 - bits of sigma_t) >> 6; sigma_t > 0, so its
+// bit pattern orders as its value (decreasing here)
 __global__ void k_band_key(unsigned long long* __restrict__ key, const double* __restrict__ t,
                            const double* __restrict__ sig, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double r = 2.0 * t[i] / sig[i];
   const double b = r > 0.0 ? fmin(floor(r), (double)kBands - 1.0) : 0.0;  // NaN -> 0
-  key[i] = ((unsigned long long)b << 58) | ((unsigned long long)__double_as_longlong(sig[i]) >> 6);
+  key[i] = ((unsigned long long)b << 58) |
+           ((0x7fffffffffffffffull - (unsigned long long)__double_as_longlong(sig[i])) >> 6);
 }
 
 static ipx_status sort_events(ipx_dataset* d, hipStream_t s) {
@@ -489,6 +493,37 @@ static ipx_status gen_batch(const GenConst& g, GenScratch& sc, uint64_t c0, int6
   return IPX_OK;
 }
 
+// A dataset of n events for the generator to fill: one allocation of the
+// columns (and weights), the reduction partials, the result buffers.
+static hipError_t alloc_toy_dataset(int model, int64_t n, bool weighted, ipx_dataset** out) {
+  *out = nullptr;
+  const int ncols = kNCols[model];
+  ipx_dataset* d = new (std::nothrow) ipx_dataset();
+  if (!d) return hipErrorOutOfMemory;
+  d->model = model;
+  d->n = n;
+  d->ncols = ncols;
+  d->n_pad = (n + 31) / 32 * 32;
+  d->n_tiles = (n + kTile - 1) / kTile;
+  d->n_tiles_outer = (n + kOuterTile - 1) / kOuterTile;
+  const int nstore = ncols + (weighted ? 1 : 0);
+  const size_t bytes = (size_t)nstore * (size_t)(d->n_pad > 0 ? d->n_pad : 32) * sizeof(double);
+  hipError_t e = hipMalloc(&d->base, bytes);
+  const int64_t tiles_alloc = d->n_tiles > 0 ? d->n_tiles : 1;
+  if (e == hipSuccess) e = hipMalloc(&d->partials, (size_t)tiles_alloc * kAccMax * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&d->out_dev, kAccMax * sizeof(double));
+  if (e == hipSuccess) e = hipHostMalloc(&d->out_host, kAccMax * sizeof(double), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    free_dataset(d);
+    return e;
+  }
+  d->bytes = bytes + (size_t)tiles_alloc * kAccMax * sizeof(double) + kAccMax * sizeof(double);
+  for (int c = 0; c < ncols; ++c) d->cols[c] = d->base + (size_t)c * d->n_pad;
+  if (weighted) d->w = d->base + (size_t)ncols * d->n_pad;
+  *out = d;
+  return hipSuccess;
+}
+
 extern "C" ipx_status toy_generate(ipx_ctx* ctx, int model, const double* theta, int np, uint64_t seed,
                                    uint64_t toy_id, int64_t n, unsigned flags, ipx_dataset** out,
                                    ipx_toy_stats* stats) {
@@ -507,37 +542,13 @@ extern "C" ipx_status toy_generate(ipx_ctx* ctx, int model, const double* theta,
 
   // output dataset, columns written in candidate order
   const int ncols = kNCols[model];
-  ipx_dataset* d = new (std::nothrow) ipx_dataset();
-  if (!d) return fail(IPX_ENOMEM, "toy_generate: host allocation failed");
-  d->model = model;
-  d->n = n;
-  d->ncols = ncols;
-  d->n_pad = (n + 31) / 32 * 32;
-  d->n_tiles = (n + kTile - 1) / kTile;
-  d->n_tiles_outer = (n + kOuterTile - 1) / kOuterTile;
   const bool weighted = model == 3 && !(flags & IPX_NO_WEIGHTS);
-  const int nstore = ncols + (weighted ? 1 : 0);
-  const size_t bytes = (size_t)nstore * (size_t)(d->n_pad > 0 ? d->n_pad : 32) * sizeof(double);
-  hipError_t e = hipMalloc(&d->base, bytes);
-  const int64_t tiles_alloc = d->n_tiles > 0 ? d->n_tiles : 1;
-  if (e == hipSuccess) e = hipMalloc(&d->partials, (size_t)tiles_alloc * kAccMax * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc(&d->out_dev, kAccMax * sizeof(double));
-  if (e == hipSuccess) e = hipHostMalloc(&d->out_host, kAccMax * sizeof(double), hipHostMallocDefault);
-  if (e != hipSuccess) {
-    free_dataset(d);
-    return fail(IPX_ENOMEM, "toy_generate: allocation failed: %s", hipGetErrorString(e));
-  }
-  d->bytes = bytes + (size_t)tiles_alloc * kAccMax * sizeof(double) + kAccMax * sizeof(double);
+  ipx_dataset* d = nullptr;
+  hipError_t e = alloc_toy_dataset(model, n, weighted, &d);
+  if (e != hipSuccess) return fail(IPX_ENOMEM, "toy_generate: allocation failed: %s", hipGetErrorString(e));
   double* colp_host[6] = {};
-  for (int c = 0; c < ncols; ++c) {
-    colp_host[c] = d->base + (size_t)c * d->n_pad;
-    d->cols[c] = colp_host[c];
-  }
-  double* wout = nullptr;
-  if (weighted) {
-    wout = d->base + (size_t)ncols * d->n_pad;
-    d->w = wout;
-  }
+  for (int c = 0; c < ncols; ++c) colp_host[c] = const_cast<double*>(d->cols[c]);
+  double* wout = const_cast<double*>(d->w);
 
   uint64_t candidates = 0, violations = 0;
   if (n > 0) {
@@ -604,6 +615,200 @@ extern "C" ipx_status toy_generate(ipx_ctx* ctx, int model, const double* theta,
     stats->n_violations = violations;
   }
   *out = d;
+  return IPX_OK;
+}
+
+// Batched generation: every toy's candidates of a round in one flags launch,
+// one prefix sum and one write launch; rounds repeat for the toys still short
+// of events.  Each toy's events, candidates and order are those of
+// toy_generate with the same arguments.
+struct GenBatchScratch {
+  GenSeg* segs = nullptr;
+  int* flags = nullptr;
+  int* rank = nullptr;
+  void* scan = nullptr;
+  size_t scan_bytes = 0;
+  double* C = nullptr;
+  unsigned long long* viol = nullptr;
+  unsigned long long* last = nullptr;
+  int64_t* acc = nullptr;
+  ~GenBatchScratch() {
+    (void)hipFree(segs); (void)hipFree(flags); (void)hipFree(rank); (void)hipFree(scan); (void)hipFree(C);
+    (void)hipFree(viol); (void)hipFree(last); (void)hipFree(acc);
+  }
+};
+
+template <int MODEL>
+static ipx_status gen_round(const GenConst& g, GenBatchScratch& sc, int nseg, int64_t total, hipStream_t s) {
+  const unsigned blocks = (unsigned)((total + 255) / 256);
+  hipLaunchKernelGGL((k_gen_flags_batch<MODEL>), dim3(blocks), dim3(256), 0, s, g, (const double*)sc.C,
+                     (const GenSeg*)sc.segs, nseg, total, sc.flags, sc.viol);
+  HIP_TRY(hipGetLastError());
+  size_t bytes = sc.scan_bytes;
+  HIP_TRY(hipcub::DeviceScan::ExclusiveSum(sc.scan, bytes, sc.flags, sc.rank, (int)total, s));
+  hipLaunchKernelGGL((k_gen_write_batch<MODEL>), dim3(blocks), dim3(256), 0, s, g, (const double*)sc.C,
+                     (const GenSeg*)sc.segs, nseg, total, (const int*)sc.flags, (const int*)sc.rank, sc.last);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_gen_counts, dim3((unsigned)((nseg + 255) / 256)), dim3(256), 0, s, (const GenSeg*)sc.segs,
+                     nseg, (const int*)sc.flags, (const int*)sc.rank, sc.acc);
+  HIP_TRY(hipGetLastError());
+  return IPX_OK;
+}
+
+static const int64_t kGenBatchCap = (int64_t)1 << 26;   // candidates per round
+
+extern "C" ipx_status toy_generate_batch(ipx_ctx* ctx, int model, const double* theta, int np, uint64_t seed,
+                                         int ntoys, const uint64_t* toy_ids, const int64_t* n, unsigned flags,
+                                         ipx_dataset** out, ipx_toy_stats* stats) {
+  if (!ctx || !theta || !out || (ntoys > 0 && (!toy_ids || !n)))
+    return fail(IPX_EINVAL, "toy_generate_batch: NULL argument");
+  if (ntoys < 0) return fail(IPX_EINVAL, "toy_generate_batch: ntoys = %d", ntoys);
+  for (int j = 0; j < ntoys; ++j) out[j] = nullptr;
+  if (model < 1 || model > 3) return fail(IPX_EINVAL, "toy_generate_batch: unknown model %d", model);
+  if (np != kNParams[model])
+    return fail(IPX_EINVAL, "toy_generate_batch: model %d takes %d parameters", model, kNParams[model]);
+  for (int j = 0; j < ntoys; ++j)
+    if (n[j] < 0 || n[j] > 0x7fffffff)
+      return fail(IPX_EINVAL, "toy_generate_batch: n[%d] = %lld out of range", j, (long long)n[j]);
+  if (flags & ~(IPX_KEEP_ORDER | IPX_NO_WEIGHTS)) return fail(IPX_EINVAL, "toy_generate_batch: bad flags %u", flags);
+  if (!theta_valid(model, theta)) return fail(IPX_EDOMAIN, "toy_generate_batch: parameters outside the domain");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  GenSetup h;
+  gen_setup(model, theta, seed, 0, h);
+  if (!(h.g.M > 0.0) || !std::isfinite(h.g.M))
+    return fail(IPX_EDOMAIN, "toy_generate_batch: no finite acceptance bound");
+  const bool weighted = model == 3 && !(flags & IPX_NO_WEIGHTS);
+  auto release = [&]() {
+    for (int j = 0; j < ntoys; ++j) {
+      if (out[j]) free_dataset(out[j]);
+      out[j] = nullptr;
+    }
+  };
+  for (int j = 0; j < ntoys; ++j) {
+    hipError_t e = alloc_toy_dataset(model, n[j], weighted, &out[j]);
+    if (e != hipSuccess) {
+      release();
+      return fail(IPX_ENOMEM, "toy_generate_batch: allocation failed: %s", hipGetErrorString(e));
+    }
+  }
+  std::vector<int64_t> got(ntoys, 0);
+  std::vector<uint64_t> c0(ntoys, 0);
+  std::vector<unsigned long long> viol(ntoys, 0), last(ntoys, 0);
+  int64_t total_need = 0;
+  for (int j = 0; j < ntoys; ++j) total_need += n[j];
+  if (total_need > 0) {
+    GenBatchScratch sc;
+    const int64_t cap = std::min<int64_t>(kGenBatchCap, std::max<int64_t>(65536, (int64_t)(total_need / kGenEfficiency[model] * 1.1)
+                                                                         + (int64_t)ntoys * 4096));
+    hipError_t e = hipMalloc(&sc.segs, (size_t)std::max(ntoys, 1) * sizeof(GenSeg));
+    if (e == hipSuccess) e = hipMalloc(&sc.flags, (size_t)cap * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&sc.rank, (size_t)cap * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&sc.C, 40 * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&sc.viol, (size_t)ntoys * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMalloc(&sc.last, (size_t)ntoys * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMalloc(&sc.acc, (size_t)ntoys * sizeof(int64_t));
+    if (e == hipSuccess) e = hipcub::DeviceScan::ExclusiveSum(nullptr, sc.scan_bytes, sc.flags, sc.rank, (int)cap, s);
+    if (e == hipSuccess) e = hipMalloc(&sc.scan, sc.scan_bytes);
+    if (e == hipSuccess) e = hipMemcpyAsync(sc.C, h.C, sizeof h.C, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(sc.viol, viol.data(), viol.size() * sizeof(unsigned long long), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(sc.last, last.data(), last.size() * sizeof(unsigned long long), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      release();
+      return fail(IPX_ENOMEM, "toy_generate_batch: scratch allocation failed: %s", hipGetErrorString(e));
+    }
+    double eff = kGenEfficiency[model];
+    std::vector<GenSeg> segs;
+    std::vector<int> seg_toy;
+    std::vector<int64_t> acc;
+    int next = 0;   // round-robin start over the toys still short of events
+    for (;;) {
+      segs.clear();
+      seg_toy.clear();
+      int64_t total = 0;
+      for (int k = 0; k < ntoys; ++k) {
+        const int j = (next + k) % ntoys;
+        const int64_t need = n[j] - got[j];
+        if (need <= 0) continue;
+        const int64_t count = std::max<int64_t>(4096, (int64_t)(need / eff * 1.05) + 4096);
+        if (total + count > cap && !segs.empty()) break;
+        const int64_t cnt = std::min<int64_t>(count, cap - total);
+        GenSeg g{};
+        g.toy = toy_ids[j];
+        g.c0 = c0[j];
+        g.start = total;
+        g.count = cnt;
+        g.out_base = got[j];
+        g.need = need;
+        for (int c = 0; c < kNCols[model]; ++c) g.cols[c] = const_cast<double*>(out[j]->cols[c]);
+        g.w = const_cast<double*>(out[j]->w);
+        segs.push_back(g);
+        seg_toy.push_back(j);
+        total += cnt;
+        if (total >= cap) break;
+      }
+      if (segs.empty()) break;
+      next = (seg_toy.back() + 1) % ntoys;
+      const int nseg = (int)segs.size();
+      // per-segment counters live at the segment's index: reset them
+      std::vector<unsigned long long> zeros(nseg, 0ull);
+      hipError_t e2 = hipMemcpyAsync(sc.segs, segs.data(), nseg * sizeof(GenSeg), hipMemcpyHostToDevice, s);
+      if (e2 == hipSuccess) e2 = hipMemcpyAsync(sc.viol, zeros.data(), nseg * sizeof(unsigned long long), hipMemcpyHostToDevice, s);
+      if (e2 == hipSuccess) e2 = hipMemcpyAsync(sc.last, zeros.data(), nseg * sizeof(unsigned long long), hipMemcpyHostToDevice, s);
+      if (e2 != hipSuccess) {
+        release();
+        return fail(IPX_EDEVICE, "toy_generate_batch: upload failed: %s", hipGetErrorString(e2));
+      }
+      ipx_status st = model == 1 ? gen_round<1>(h.g, sc, nseg, total, s)
+                    : model == 2 ? gen_round<2>(h.g, sc, nseg, total, s)
+                                 : gen_round<3>(h.g, sc, nseg, total, s);
+      if (st != IPX_OK) {
+        release();
+        return st;
+      }
+      acc.assign(nseg, 0);
+      std::vector<unsigned long long> v(nseg), l(nseg);
+      e2 = hipMemcpyAsync(acc.data(), sc.acc, nseg * sizeof(int64_t), hipMemcpyDeviceToHost, s);
+      if (e2 == hipSuccess) e2 = hipMemcpyAsync(v.data(), sc.viol, nseg * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
+      if (e2 == hipSuccess) e2 = hipMemcpyAsync(l.data(), sc.last, nseg * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
+      if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
+      if (e2 != hipSuccess) {
+        release();
+        return fail(IPX_EDEVICE, "toy_generate_batch: readback failed: %s", hipGetErrorString(e2));
+      }
+      int64_t acc_sum = 0, cnt_sum = 0;
+      for (int k = 0; k < nseg; ++k) {
+        const int j = seg_toy[k];
+        viol[j] += v[k];
+        if (l[k]) last[j] = l[k];
+        got[j] += std::min<int64_t>(acc[k], n[j] - got[j]);
+        c0[j] += (uint64_t)segs[k].count;
+        acc_sum += acc[k];
+        cnt_sum += segs[k].count;
+        if (c0[j] > (1ull << 48)) {
+          release();
+          return fail(IPX_EDOMAIN, "toy_generate_batch: acceptance too low in toy %d", j);
+        }
+      }
+      if (acc_sum > 0) eff = std::max(1e-4, (double)acc_sum / (double)cnt_sum);
+    }
+  }
+  if (model >= 2 && !(flags & IPX_KEEP_ORDER)) {
+    for (int j = 0; j < ntoys; ++j) {
+      if (n[j] < 2) continue;
+      ipx_status st = sort_events(out[j], s);
+      if (st != IPX_OK) {
+        release();
+        return st;
+      }
+    }
+  }
+  if (stats)
+    for (int j = 0; j < ntoys; ++j) {
+      stats[j].n_candidates = last[j];
+      stats[j].n_violations = viol[j];
+    }
   return IPX_OK;
 }
 

@@ -125,8 +125,11 @@ __global__ __launch_bounds__(kThreads) void k_nll_batch(const SegInfo* __restric
 }
 
 // Angular model: per-event kernel.
+// The gradient instance is held to 128 VGPRs (4 waves/SIMD; its natural
+// allocation is 129, i.e. 3 waves, and the extra wave shortens the tail of the
+// launch more than the few spilled registers cost).
 template <bool GRAD>
-__global__ __launch_bounds__(kThreads) void k_angtime_batch(const SegInfo* __restrict__ segs,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(GRAD ? 4 : 1))) void k_angtime_batch(const SegInfo* __restrict__ segs,
                                                             const TileRef* __restrict__ tiles, int64_t n_tiles,
                                                             const AngTimeConst* __restrict__ consts,
                                                             const unsigned char* __restrict__ active) {
@@ -143,11 +146,11 @@ __global__ __launch_bounds__(kThreads) void k_angtime_batch(const SegInfo* __res
 }
 
 // Angular model: coefficient adjoints over the outer tiles of each segment.
-__global__ __launch_bounds__(kThreads) void k_angtime_outer_batch(const SegInfo* __restrict__ segs,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_angtime_outer_batch(const SegInfo* __restrict__ segs,
                                                                   const TileRef* __restrict__ tiles,
                                                                   int64_t n_tiles,
                                                                   const unsigned char* __restrict__ active) {
-  __shared__ RedBuf<kAngOuter / 2> red;
+  __shared__ RedBuf<kAngOuter / 4> red;   // 4 passes of 10 components: 22 KB, 4 workgroups per CU
   for (int64_t g = blockIdx.x; g < n_tiles; g += gridDim.x) {
     const TileRef tr = tiles[g];
     if (!active[tr.seg]) continue;

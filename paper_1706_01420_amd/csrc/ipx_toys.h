@@ -230,4 +230,84 @@ __global__ __launch_bounds__(256) void k_gen_write(GenConst g, const double* __r
   if (rk == need - 1) *last = (unsigned long long)(c0 + (uint64_t)i) + 1ull;
 }
 
+// ---------------------------------------------------------------------------
+// Batched generation: the candidates of many toys in one launch.  Segment j
+// covers global positions [start, start + count) and maps position i to
+// candidate c0 + (i - start) of toy j; each toy keeps its own key, candidate
+// order and output, so its events are those a single-toy generation gives.
+// ---------------------------------------------------------------------------
+struct GenSeg {
+  uint64_t toy;        // Philox key word 1
+  uint64_t c0;         // first candidate of this round
+  int64_t start;       // first global position
+  int64_t count;       // candidates of this round
+  int64_t out_base;    // events already written
+  int64_t need;        // events still needed
+  double* cols[6];
+  double* w;           // nullptr: no weight column
+};
+
+__device__ __forceinline__ int gen_find_seg(const GenSeg* __restrict__ segs, int nseg, int64_t i) {
+  int lo = 0, hi = nseg - 1;   // the last segment with start <= i
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (segs[mid].start <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int MODEL>
+__global__ __launch_bounds__(256) void k_gen_flags_batch(GenConst g, const double* __restrict__ Cg,
+                                                         const GenSeg* __restrict__ segs, int nseg, int64_t total,
+                                                         int* __restrict__ flags,
+                                                         unsigned long long* __restrict__ violations) {
+  __shared__ double sC[40];
+  if (MODEL == 3 && threadIdx.x < 40) sC[threadIdx.x] = Cg[threadIdx.x];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int j = gen_find_seg(segs, nseg, i);
+  GenConst gj = g;
+  gj.toy = segs[j].toy;
+  const Candidate r = gen_candidate<MODEL>(gj, sC, segs[j].c0 + (uint64_t)(i - segs[j].start));
+  flags[i] = r.accept ? 1 : 0;
+  if (r.violation) atomicAdd(&violations[j], 1ull);
+}
+
+template <int MODEL>
+__global__ __launch_bounds__(256) void k_gen_write_batch(GenConst g, const double* __restrict__ Cg,
+                                                         const GenSeg* __restrict__ segs, int nseg, int64_t total,
+                                                         const int* __restrict__ flags, const int* __restrict__ rank,
+                                                         unsigned long long* __restrict__ last) {
+  __shared__ double sC[40];
+  if (MODEL == 3 && threadIdx.x < 40) sC[threadIdx.x] = Cg[threadIdx.x];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total || !flags[i]) return;
+  const int j = gen_find_seg(segs, nseg, i);
+  const GenSeg& sg = segs[j];
+  const int64_t rk = (int64_t)rank[i] - (int64_t)rank[sg.start];
+  if (rk >= sg.need) return;
+  GenConst gj = g;
+  gj.toy = sg.toy;
+  const uint64_t c = sg.c0 + (uint64_t)(i - sg.start);
+  const Candidate r = gen_candidate<MODEL>(gj, sC, c);
+  const int64_t o = sg.out_base + rk;
+  constexpr int ncols = MODEL == 1 ? 1 : MODEL == 2 ? 3 : 6;
+#pragma unroll
+  for (int cc = 0; cc < ncols; ++cc) sg.cols[cc][o] = r.col[cc];
+  if (MODEL == 3 && sg.w) sg.w[o] = r.w;
+  if (rk == sg.need - 1) last[j] = (unsigned long long)c + 1ull;
+}
+
+// accepted[j] = candidates of segment j accepted in this round
+__global__ void k_gen_counts(const GenSeg* __restrict__ segs, int nseg, const int* __restrict__ flags,
+                             const int* __restrict__ rank, int64_t* __restrict__ accepted) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nseg) return;
+  const int64_t a = segs[j].start, b = a + segs[j].count - 1;
+  accepted[j] = (int64_t)rank[b] + flags[b] - (int64_t)rank[a];
+}
+
 }  // namespace ipx

@@ -74,6 +74,9 @@ _SIGNATURES = [
     ("toy_generate", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_int, _c_double_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64,
       ctypes.c_uint, _c_void_pp, ctypes.c_void_p]),
+    ("toy_generate_batch", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_int, _c_double_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p,
+      ctypes.c_void_p, ctypes.c_uint, ctypes.c_void_p, ctypes.c_void_p]),
     ("ipx_timing_enable", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     ("ipx_timing_read", ctypes.c_int,
      [ctypes.c_void_p, _c_double_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]),
@@ -237,6 +240,28 @@ def nll_grad(ctx, ds, theta, stream=None):
     return out.value, g
 
 
+class _NLL(torch.autograd.Function):
+    """-ln L as a differentiable torch scalar: the forward runs nll_grad and
+    keeps the gradient, the backward scales it by the incoming gradient."""
+
+    @staticmethod
+    def forward(fctx, theta, ctx, ds):
+        f, g = nll_grad(ctx, ds, theta.detach().to("cpu", torch.float64).numpy())
+        fctx.save_for_backward(torch.from_numpy(g))
+        return torch.tensor(f, dtype=theta.dtype, device=theta.device)
+
+    @staticmethod
+    def backward(fctx, grad_out):
+        (g,) = fctx.saved_tensors
+        return grad_out * g.to(device=grad_out.device, dtype=grad_out.dtype), None, None
+
+
+def nll(ctx, ds, theta):
+    """NLL of dataset ds at theta (a 1-D float64 torch tensor); differentiable
+    with respect to theta through the analytic gradient."""
+    return _NLL.apply(theta, ctx, ds)
+
+
 def ipx_plan_create(ctx, datasets):
     arr = (ctypes.c_void_p * len(datasets))(*[d.value for d in datasets])
     h = ctypes.c_void_p()
@@ -344,6 +369,23 @@ def toy_generate(ctx, model, theta_gen, seed, toy_id, n, flags=0):
     _check(_lib.toy_generate(ctx, int(model), _dbl(th), th.shape[0], ctypes.c_uint64(seed), ctypes.c_uint64(toy_id),
                              int(n), int(flags), ctypes.byref(h), ctypes.byref(st)))
     return h, {"n_candidates": st.n_candidates, "n_violations": st.n_violations}
+
+
+def toy_generate_batch(ctx, model, theta_gen, seed, toy_ids, sizes, flags=0):
+    """Generate many toys at once; returns (list of dataset handles, list of
+    stats dicts), toy j equal to toy_generate(..., toy_ids[j], sizes[j], flags)."""
+    th = np.ascontiguousarray(theta_gen, dtype=np.float64)
+    ids = np.ascontiguousarray(toy_ids, dtype=np.uint64)
+    ns = np.ascontiguousarray(sizes, dtype=np.int64)
+    k = ids.shape[0]
+    if ns.shape[0] != k:
+        raise ValueError("toy_ids and sizes differ in length")
+    outs = (ctypes.c_void_p * max(k, 1))()
+    st = (_ToyStats * max(k, 1))()
+    _check(_lib.toy_generate_batch(ctx, int(model), _dbl(th), th.shape[0], ctypes.c_uint64(seed), k,
+                                   ids.ctypes.data, ns.ctypes.data, int(flags), outs, st))
+    return ([ctypes.c_void_p(outs[j]) for j in range(k)],
+            [{"n_candidates": st[j].n_candidates, "n_violations": st[j].n_violations} for j in range(k)])
 
 
 def ipx_timing_enable(ctx, enable=True):

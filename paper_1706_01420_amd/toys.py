@@ -3,7 +3,7 @@
 Sizes: as the paper suggests for Example 5, the number of events of each toy
 is Poisson-fluctuated on the host: mean mu_j log-uniform in [1e4, 2e5], drawn
 with numpy's Philox generator keyed by the study seed, then N_j ~ Poisson(mu_j).
-Events: toy_generate with key (seed, toy_id = j).
+Events: toy_generate_batch with key (seed, toy_id = j) for toy j.
 Fits: fit.bfgs either through one nll_eval_batch per round (batched, graph
 replay) or through nll_grad per toy (plain loop); the per-toy arithmetic is the
 same, so both give the same minima.
@@ -29,14 +29,15 @@ def toy_sizes(seed, ntoys, lo=1e4, hi=2e5):
 
 
 def generate(ipx, ctx, model, theta_gen, seed, sizes, flags=0):
-    """One dataset per toy (toy_id = index)."""
-    out = []
-    for j, n in enumerate(sizes):
-        ds, st = ipx.toy_generate(ctx, model, theta_gen, seed, j, int(n), flags)
+    """One dataset per toy (toy_id = index), all toys through one batched
+    generation."""
+    ds, stats = ipx.toy_generate_batch(ctx, model, theta_gen, seed, np.arange(len(sizes)), np.asarray(sizes), flags)
+    for j, st in enumerate(stats):
         if st["n_violations"]:
+            for d in ds:
+                ipx.ipx_dataset_destroy(ctx, d)
             raise RuntimeError("acceptance bound violated in toy %d" % j)
-        out.append(ds)
-    return out
+    return ds
 
 
 def batched_evaluator(ipx, ctx, plan):

@@ -301,3 +301,20 @@ def test_full_size_gradient_on_subsample(lib, ctx):
     finally:
         for d in (ds, da, db):
             lib.ipx_dataset_destroy(ctx, d)
+
+
+def test_torch_autograd_mirror(lib, ctx):
+    import torch
+    cols, w = small_data(3, n=3000, seed=21)
+    ds = lib.ipx_dataset_create(ctx, 3, cols, w)
+    try:
+        say("torch autograd mirror")
+        th = thetas(3, 2)[1]
+        f, g = lib.nll_grad(ctx, ds, th)
+        t = torch.tensor(th, dtype=torch.float64, requires_grad=True)
+        out = lib.nll(ctx, ds, t)
+        assert out.item() == f
+        (2.5 * out).backward()
+        assert np.array_equal(t.grad.numpy(), 2.5 * g)
+    finally:
+        lib.ipx_dataset_destroy(ctx, ds)

@@ -107,3 +107,43 @@ def test_toy_generate_errors(lib, ctx):
         assert lib.ipx_dataset_size(ds) == 0 and st["n_candidates"] == 0
     finally:
         lib.ipx_dataset_destroy(ctx, ds)
+
+
+@pytest.mark.parametrize("model", [1, 2, 3])
+def test_toy_generate_batch_equals_single_toys(lib, ctx, model):
+    seed = 77
+    theta = M.THETA_GEN[model]
+    ids = [3, 0, 11, 5, 9]
+    sizes = [5000, 0, 1, 12345, 777]
+    for flags in (lib.IPX_KEEP_ORDER, 0):
+        say("toy_generate_batch model", model, "flags", flags)
+        batch, bstats = lib.toy_generate_batch(ctx, model, theta, seed, ids, sizes, flags)
+        try:
+            for j, (tid, n) in enumerate(zip(ids, sizes)):
+                d, st = lib.toy_generate(ctx, model, theta, seed, tid, n, flags)
+                try:
+                    assert lib.ipx_dataset_size(batch[j]) == n
+                    assert bstats[j]["n_candidates"] == st["n_candidates"]
+                    assert bstats[j]["n_violations"] == 0 and st["n_violations"] == 0
+                    if n:
+                        a, wa = _read_all(lib, ctx, batch[j], model)
+                        b, wb = _read_all(lib, ctx, d, model)
+                        for c in range(M.NCOLS[model]):
+                            assert np.array_equal(a[c], b[c])
+                        assert (wa is None and wb is None) or np.array_equal(wa, wb)
+                finally:
+                    lib.ipx_dataset_destroy(ctx, d)
+        finally:
+            for d in batch:
+                lib.ipx_dataset_destroy(ctx, d)
+
+
+def test_toy_generate_batch_errors(lib, ctx):
+    say("toy_generate_batch errors")
+    th = M.THETA_GEN[1]
+    with pytest.raises(lib.IpxError):
+        lib.toy_generate_batch(ctx, 1, th, 1, [0, 1], [10, -1])
+    with pytest.raises(lib.IpxError):
+        lib.toy_generate_batch(ctx, 4, th, 1, [0], [10])
+    ds, st = lib.toy_generate_batch(ctx, 1, th, 1, [], [])
+    assert ds == [] and st == []

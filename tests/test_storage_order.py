@@ -11,7 +11,7 @@ from storage_order import band_order
 def _key(t, s):
     r = 2.0 * t / s
     b = min(math.floor(r), 20) if r > 0.0 else 0
-    return (b, struct.unpack("<Q", struct.pack("<d", s))[0] >> 6)
+    return (b, ((1 << 63) - 1 - struct.unpack("<Q", struct.pack("<d", s))[0]) >> 6)
 
 
 def test_band_order_matches_tuple_sort():
