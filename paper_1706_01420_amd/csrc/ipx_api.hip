@@ -825,12 +825,13 @@ struct ipx_plan {
   TileRef* d_tiles = nullptr;
   TileRef* d_tiles_outer = nullptr;
   int64_t n_tiles = 0, n_tiles_outer = 0;
-  void* d_consts = nullptr;
-  unsigned char* d_active = nullptr;
-  double* d_out = nullptr;
-  void* h_consts = nullptr;        // pinned staging, copied by the graph
+  void* h_consts = nullptr;        // pinned [constants | active flags], written by the host
   unsigned char* h_active = nullptr;
-  double* h_out = nullptr;
+  void* d_consts = nullptr;        // the same block's device address (read by the kernels)
+  unsigned char* d_active = nullptr;
+  size_t stage_bytes = 0;
+  double* h_out = nullptr;         // pinned results, written by the reduction kernel
+  double* h_out_dev = nullptr;     // its device address
   hipGraphExec_t exec[2] = {nullptr, nullptr};  // [eval, grad]
   bool counted = false;            // holds a reference on each dataset
   hipStream_t exec_stream[2] = {nullptr, nullptr};
@@ -842,9 +843,7 @@ static void free_plan(struct ipx_plan* p) {
   for (int i = 0; i < 2; ++i)
     if (p->exec[i]) (void)hipGraphExecDestroy(p->exec[i]);
   (void)hipFree(p->d_segs); (void)hipFree(p->d_tiles); (void)hipFree(p->d_tiles_outer);
-  (void)hipFree(p->d_consts); (void)hipFree(p->d_active); (void)hipFree(p->d_out);
   if (p->h_consts) (void)hipHostFree(p->h_consts);
-  if (p->h_active) (void)hipHostFree(p->h_active);
   if (p->h_out) (void)hipHostFree(p->h_out);
   delete p;
 }
@@ -901,12 +900,16 @@ static ipx_status plan_create(ipx_ctx* ctx, int nb, ipx_dataset* const* ds, ipx_
   if (e == hipSuccess) e = hipMalloc(&p->d_segs, nb * sizeof(SegInfo));
   if (e == hipSuccess) e = hipMalloc(&p->d_tiles, std::max<size_t>(1, tiles.size()) * sizeof(TileRef));
   if (e == hipSuccess) e = hipMalloc(&p->d_tiles_outer, std::max<size_t>(1, outer.size()) * sizeof(TileRef));
-  if (e == hipSuccess) e = hipMalloc(&p->d_consts, nb * p->const_size);
-  if (e == hipSuccess) e = hipMalloc(&p->d_active, nb);
-  if (e == hipSuccess) e = hipMalloc(&p->d_out, (size_t)nb * kAccMax * sizeof(double));
-  if (e == hipSuccess) e = hipHostMalloc(&p->h_consts, nb * p->const_size, hipHostMallocDefault);
-  if (e == hipSuccess) e = hipHostMalloc((void**)&p->h_active, nb, hipHostMallocDefault);
+  const size_t cbytes = (nb * p->const_size + 255) / 256 * 256;
+  p->stage_bytes = cbytes + (size_t)nb;
+  if (e == hipSuccess) e = hipHostMalloc(&p->h_consts, p->stage_bytes, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostGetDevicePointer(&p->d_consts, p->h_consts, 0);
+  if (e == hipSuccess) {
+    p->d_active = (unsigned char*)p->d_consts + cbytes;
+    p->h_active = (unsigned char*)p->h_consts + cbytes;
+  }
   if (e == hipSuccess) e = hipHostMalloc((void**)&p->h_out, (size_t)nb * kAccMax * sizeof(double), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&p->h_out_dev, p->h_out, 0);
   if (e == hipSuccess) e = hipMemcpy(p->d_segs, segs.data(), nb * sizeof(SegInfo), hipMemcpyHostToDevice);
   if (e == hipSuccess && !tiles.empty())
     e = hipMemcpy(p->d_tiles, tiles.data(), tiles.size() * sizeof(TileRef), hipMemcpyHostToDevice);
@@ -949,14 +952,15 @@ static ipx_status timing_end(ipx_ctx* ctx, hipStream_t s) {
   return IPX_OK;
 }
 
-// Stream operations of one (batched) evaluation: constants and active flags
-// to the device, the per-event kernel (timed through `timer` when given), for
-// the angular gradient the coefficient-adjoint kernel, the per-segment
-// reductions, results back to pinned host memory.
+// Stream operations of one (batched) evaluation: the per-event kernel (timed
+// through `timer` when given), for the angular gradient the
+// coefficient-adjoint kernel, the per-segment reductions.  The kernels read the
+// hoisted constants and active flags from pinned host memory (written by the
+// host before the launch; the few hundred bytes are cached on the device after
+// the first workgroup's read) and the reductions write the results into pinned
+// host memory, so an evaluation needs no copies.
 static ipx_status enqueue_batch(ipx_plan* p, bool grad, hipStream_t s, ipx_ctx* timer) {
   const int nb = p->nb;
-  HIP_TRY(hipMemcpyAsync(p->d_consts, p->h_consts, nb * p->const_size, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(p->d_active, p->h_active, nb, hipMemcpyHostToDevice, s));
   const unsigned grid = (unsigned)std::max<int64_t>(1, p->n_tiles);
   int nacc = 1, split = 1;
   {
@@ -994,9 +998,11 @@ static ipx_status enqueue_batch(ipx_plan* p, bool grad, hipStream_t s, ipx_ctx* 
     ipx_status st = timing_end(timer, s);
     if (st != IPX_OK) return st;
   }
-  hipLaunchKernelGGL(k_reduce_batch, dim3(nacc, nb), dim3(kThreads), 0, s, p->d_segs, p->d_active, split, p->d_out);
+  // the totals go straight to pinned host memory (visible once the stream
+  // has synchronised)
+  hipLaunchKernelGGL(k_reduce_batch, dim3(nacc, nb), dim3(kThreads), 0, s, p->d_segs, p->d_active, split,
+                     p->h_out_dev);
   HIP_TRY(hipGetLastError());
-  HIP_TRY(hipMemcpyAsync(p->h_out, p->d_out, (size_t)nb * kAccMax * sizeof(double), hipMemcpyDeviceToHost, s));
   return IPX_OK;
 }
 

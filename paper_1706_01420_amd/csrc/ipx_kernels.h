@@ -149,10 +149,11 @@ __device__ __forceinline__ void event_mass(const MassConst& k, double m, double 
 // continued fraction that evaluates them.  The correction of rate r is
 // exp(-E_r) w / 2 relative to the main term with E_r = (Im u_r)^2 - (Re u_r)^2;
 // the smallest E over the rates is at the largest rate.  At the range ends
-// the same depth serves the Phi terms of the normalisation, whose size
-// relative to the main term at T_LO is bounded with E lowered by
-// (Re u)^2 + gmax tau (e_shift); when Im u < 0 for some rate the correction is
-// the whole value and takes the full depth.
+// the same decisions serve the Phi terms of the normalisation, whose size
+// relative to the main term at T_LO is bounded with E lowered by gmax tau
+// (e_shift).  The corrections are skipped when even their own size is below
+// 2^-57 of the main term (E >= kCfSkipE); when Im u < 0 for some rate the
+// correction is the whole value and takes the full depth.
 struct TimePoint {
   double g;     // exp(-tau^2 / (2 s^2)), 0 when the correction is negligible
   bool need;    // correction evaluated
@@ -163,9 +164,9 @@ __device__ __forceinline__ TimePoint time_point(double tau, double gmax, double 
                                                 double re_u2, double e_shift) {
   TimePoint p;
   const double x = (tau - gmax * s2) * inv_r2s;  // smallest |Im u| over the rates
-  const double E = x > 0.0 ? x * x - re_u2 : -1.0;
-  p.need = !(E > kCorrSkip);
-  p.depth = cf_depth_wave(p.need ? E - e_shift : kCorrSkip);
+  const double E = (x > 0.0 ? x * x - re_u2 : -1.0) - e_shift;
+  p.need = !(E >= kCfSkipE);
+  p.depth = cf_depth_wave(p.need ? E : kCfSkipE);
   const double a = tau * inv_r2s;
   p.g = p.need ? exp(-a * a) : 0.0;
   return p;

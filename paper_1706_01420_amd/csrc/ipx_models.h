@@ -17,10 +17,6 @@ constexpr int kThreads = 256;
 constexpr int kEventsPerLane = 4;
 constexpr int kTile = kThreads * kEventsPerLane;
 
-// Skip the large-t/sigma correction when its size relative to the main term is
-// below e^{-42} (~6e-19): (Im u)^2 - (Re u)^2 > 42 with Im u < 0.
-constexpr double kCorrSkip = 42.0;
-
 // Accumulator layout (component 0 is always sum_i w_i ln P_i).
 constexpr int kAccMass = 6;       // l, dcS, dcB, dmu, dq, dlam
 constexpr int kAccMassTime = 9;   // l, dcS, dcB, dmu, dq, dlam, dgs, dgb, ds
