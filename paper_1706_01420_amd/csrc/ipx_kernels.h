@@ -166,7 +166,8 @@ __device__ __forceinline__ TimePoint time_point(double tau, double gmax, double 
   const double x = (tau - gmax * s2) * inv_r2s;  // smallest |Im u| over the rates
   const double E = (x > 0.0 ? x * x - re_u2 : -1.0) - e_shift;
   p.need = !(E >= kCfSkipE);
-  p.depth = cf_depth_wave(p.need ? E : kCfSkipE);
+  // the depth search (four wave votes) only where some lane needs it
+  p.depth = __any(p.need) ? cf_depth_wave(p.need ? E : kCfSkipE) : 1;
   const double a = tau * inv_r2s;
   p.g = p.need ? exp(-a * a) : 0.0;
   return p;

@@ -8,6 +8,7 @@ If libipx.so is missing the import fails: there is no fallback path.
 """
 import ctypes
 import os
+import threading
 
 import numpy as np
 import torch  # noqa: F401  (maps torch's HIP runtime before libipx is loaded)
@@ -56,10 +57,12 @@ _SIGNATURES = [
     ("ipx_dataset_column", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_void_pp]),
     ("ipx_dataset_read", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_int64, _c_double_p]),
+    # pointer arguments as plain addresses (the per-call marshalling below)
     ("nll_eval", ctypes.c_int,
-     [ctypes.c_void_p, ctypes.c_void_p, _c_double_p, ctypes.c_int, _c_double_p, ctypes.c_void_p]),
+     [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     ("nll_grad", ctypes.c_int,
-     [ctypes.c_void_p, ctypes.c_void_p, _c_double_p, ctypes.c_int, _c_double_p, _c_double_p, ctypes.c_void_p]),
+     [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+      ctypes.c_void_p]),
     ("ipx_plan_create", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p), _c_void_pp]),
     ("ipx_plan_destroy", None, [ctypes.c_void_p]),
     ("nll_eval_batch", ctypes.c_int,
@@ -216,28 +219,52 @@ def ipx_dataset_read(ctx, ds, col, offset=0, count=None):
     return out
 
 
+class _CallBuffers:
+    """Per-thread argument buffers of the single-dataset calls: theta is copied
+    into a fixed array whose address is taken once, so a call costs one small
+    copy instead of building ctypes pointer objects."""
+    CAP = 64
+
+    def __init__(self):
+        self.th = np.empty(self.CAP)
+        self.g = np.empty(self.CAP)
+        self.out = np.empty(1)
+        self.th_p, self.g_p, self.out_p = self.th.ctypes.data, self.g.ctypes.data, self.out.ctypes.data
+
+
+_tls = threading.local()
+
+
+def _buffers(theta):
+    b = getattr(_tls, "b", None)
+    if b is None:
+        b = _tls.b = _CallBuffers()
+    n = len(theta)
+    if n > b.CAP:
+        raise ValueError("theta has %d entries" % n)
+    b.th[:n] = theta
+    return b, n
+
+
 def nll_eval(ctx, ds, theta, stream=None):
     """-sum w ln P at theta; +inf for IPX_EDOMAIN (parameters outside the domain
     or a non-finite likelihood), an exception for any other error."""
-    th = np.ascontiguousarray(theta, dtype=np.float64)
-    out = ctypes.c_double()
-    st = _lib.nll_eval(ctx, ds, _dbl(th), th.shape[0], ctypes.byref(out), _stream_ptr(stream))
+    b, n = _buffers(theta)
+    st = _lib.nll_eval(ctx, ds, b.th_p, n, b.out_p, None if stream is None else _stream_ptr(stream))
     if st == IPX_EDOMAIN:
         return float("inf")
     _check(st)
-    return out.value
+    return float(b.out[0])
 
 
 def nll_grad(ctx, ds, theta, stream=None):
     """(NLL, dNLL/dtheta); (+inf, NaN) for IPX_EDOMAIN."""
-    th = np.ascontiguousarray(theta, dtype=np.float64)
-    out = ctypes.c_double()
-    g = np.empty(th.shape[0])
-    st = _lib.nll_grad(ctx, ds, _dbl(th), th.shape[0], ctypes.byref(out), _dbl(g), _stream_ptr(stream))
+    b, n = _buffers(theta)
+    st = _lib.nll_grad(ctx, ds, b.th_p, n, b.out_p, b.g_p, None if stream is None else _stream_ptr(stream))
     if st == IPX_EDOMAIN:
-        return float("inf"), np.full(th.shape[0], np.nan)
+        return float("inf"), np.full(n, np.nan)
     _check(st)
-    return out.value, g
+    return float(b.out[0]), b.g[:n].copy()
 
 
 class _NLL(torch.autograd.Function):

@@ -318,3 +318,26 @@ def test_torch_autograd_mirror(lib, ctx):
         assert np.array_equal(t.grad.numpy(), 2.5 * g)
     finally:
         lib.ipx_dataset_destroy(ctx, ds)
+
+
+@pytest.mark.parametrize("model", [2, 3])
+def test_resolution_extremes_match_oracle(lib, ctx, model):
+    # sigma_t log-uniform over [0.002, 0.5] ps: corrections skipped, every
+    # continued-fraction depth, the full depth, the rational-series branch
+    # (Im u < 3.4) and, for the complex rate, |u| >= 6 with E < 0
+    cols, w = small_data(model, n=20000, seed=31)
+    scol = 2 if model == 2 else 4
+    rng = np.random.default_rng(32)
+    cols = [c.copy() for c in cols]
+    cols[scol] = np.exp(rng.uniform(np.log(0.002), np.log(0.5), cols[0].shape[0]))
+    ds = lib.ipx_dataset_create(ctx, model, cols, w)
+    try:
+        for i, th in enumerate(thetas(model, 2)):
+            say("resolution extremes model", model, "theta", i)
+            f, g = lib.nll_grad(ctx, ds, th)
+            fref, gref = N.nll_grad(model, cols, th, w)
+            check_nll(f, fref)
+            check_nll(lib.nll_eval(ctx, ds, th), fref)
+            check_grad(model, cols, w, th, g, gref)
+    finally:
+        lib.ipx_dataset_destroy(ctx, ds)
