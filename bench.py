@@ -93,8 +93,8 @@ BYTES_PER_EVENT = {1: 8, 2: 24, 3: 56}
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=50)
-    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--steps", type=int, default=200)
+    p.add_argument("--warmup", type=int, default=200)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-extra", action="store_true", help="skip the secondary per-model rates")
     p.add_argument("--no-batched", action="store_true", help="skip the batched toy-fit leg")
@@ -354,7 +354,7 @@ def main():
     }
     extra = {}
     if not args.no_extra:
-        e_step, e_kern = timed_rate(ipx, ctx, ds, theta, max(args.steps // 2, 5), 2, grad=False)
+        e_step, e_kern = timed_rate(ipx, ctx, ds, theta, max(args.steps // 2, 5), max(args.warmup // 2, 2), grad=False)
         fe = algorithmic_flops(model, t_st, s_st, theta, False)
         extra["angtime_nll_eval"] = {"evals_per_s": 1 / e_step, "kernel_us": e_kern * 1e6,
                                      "flop_per_event": fe / n, "tflops": fe / e_kern / 1e12}
@@ -369,7 +369,7 @@ def main():
             if m == 2:
                 tm, sm = ipx.ipx_dataset_read(ctx, d, 1), ipx.ipx_dataset_read(ctx, d, 2)
             for grad in (False, True):
-                s, k = timed_rate(ipx, ctx, d, th, max(args.steps // 2, 5), 2, grad)
+                s, k = timed_rate(ipx, ctx, d, th, max(args.steps // 2, 5), max(args.warmup // 2, 2), grad)
                 key = ("mass" if m == 1 else "masstime") + ("_nll_grad" if grad else "_nll_eval")
                 fm = algorithmic_flops(m, tm, sm, th, grad) if m == 2 else FLOP_BASE[(m, grad)] * nm
                 extra[key] = {"n_events": nm, "evals_per_s": 1 / s, "us_per_eval": s * 1e6,
