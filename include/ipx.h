@@ -284,6 +284,31 @@ IPX_API ipx_status toy_generate_batch(ipx_ctx *ctx, int model, const double *the
 IPX_API ipx_status ipx_timing_enable(ipx_ctx *ctx, int enable);
 IPX_API ipx_status ipx_timing_read(ipx_ctx *ctx, double *total_ms, int64_t *launches, int reset);
 
+/*
+ * Self-check of the device elementary functions that the event kernels inline
+ * (exp, ln, sin/cos, erfcx and the Faddeeva function w of the resolution
+ * convolution), evaluated element by element on the context's device.
+ *   fn = IPX_FN_EXP      y = e^x
+ *        IPX_FN_LOG      y = ln x
+ *        IPX_FN_SINCOS   y = sin x, y2 = cos x
+ *        IPX_FN_ERFCX    y = e^{x^2} erfc(x), x >= 0
+ *        IPX_FN_FADDEEVA y + i y2 = w(x + i x2), x2 >= 0 (upper half plane)
+ * x, x2, y, y2: host arrays of n doubles (x2 read only for IPX_FN_FADDEEVA,
+ * y2 written only for IPX_FN_SINCOS and IPX_FN_FADDEEVA; the others may be
+ * NULL), owned by the caller; 0 <= n <= 2^28.  Synchronous; allocates and
+ * frees its own device buffers.  IPX_EINVAL for an unknown fn, n out of range
+ * or a missing buffer; IPX_EDEVICE for HIP errors.
+ */
+enum {
+  IPX_FN_EXP = 0,
+  IPX_FN_LOG = 1,
+  IPX_FN_SINCOS = 2,
+  IPX_FN_ERFCX = 3,
+  IPX_FN_FADDEEVA = 4
+};
+IPX_API ipx_status ipx_math_eval(ipx_ctx *ctx, int fn, int64_t n, const double *x, const double *x2, double *y,
+                                 double *y2);
+
 #ifdef __cplusplus
 }
 #endif

@@ -378,6 +378,66 @@ ipx_status ipx_timing_read(ipx_ctx* ctx, double* total_ms, int64_t* launches, in
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
+// Self-check of the device elementary functions (the same inline functions the
+// event kernels use), element by element.
+// ---------------------------------------------------------------------------
+__global__ void k_math_eval(int fn, int64_t n, const double* __restrict__ x, const double* __restrict__ x2,
+                            double* __restrict__ y, double* __restrict__ y2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double a = x[i];
+  switch (fn) {
+    case IPX_FN_EXP: y[i] = ipx::exp_fast(a); break;
+    case IPX_FN_LOG: y[i] = ipx::log_fast(a); break;
+    case IPX_FN_SINCOS: {
+      double s, c;
+      ipx::sincos_fast(a, &s, &c);
+      y[i] = s;
+      y2[i] = c;
+      break;
+    }
+    case IPX_FN_ERFCX: y[i] = ipx::erfcx_pos(a); break;
+    case IPX_FN_FADDEEVA: {
+      const ipx::cplx w = ipx::faddeeva_upper(ipx::cplx{a, x2[i]});
+      y[i] = w.re;
+      y2[i] = w.im;
+      break;
+    }
+    default: break;
+  }
+}
+
+extern "C" ipx_status ipx_math_eval(ipx_ctx* ctx, int fn, int64_t n, const double* x, const double* x2, double* y,
+                                    double* y2) {
+  if (!ctx) return fail(IPX_EINVAL, "ipx_math_eval: NULL ctx");
+  if (fn < IPX_FN_EXP || fn > IPX_FN_FADDEEVA) return fail(IPX_EINVAL, "ipx_math_eval: unknown function %d", fn);
+  if (n < 0 || n > (int64_t(1) << 28)) return fail(IPX_EINVAL, "ipx_math_eval: n = %lld out of [0, 2^28]", (long long)n);
+  const bool two_in = fn == IPX_FN_FADDEEVA, two_out = fn == IPX_FN_SINCOS || fn == IPX_FN_FADDEEVA;
+  if (n > 0 && (!x || !y || (two_in && !x2) || (two_out && !y2)))
+    return fail(IPX_EINVAL, "ipx_math_eval: NULL buffer");
+  if (n == 0) return IPX_OK;
+  HIP_TRY(hipSetDevice(ctx->device));
+  const size_t b = (size_t)n * sizeof(double);
+  double* d = nullptr;
+  HIP_TRY(hipMalloc(&d, 4 * b));
+  double *dx = d, *dx2 = d + n, *dy = d + 2 * n, *dy2 = d + 3 * n;
+  hipError_t e = hipMemcpyAsync(dx, x, b, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess && two_in) e = hipMemcpyAsync(dx2, x2, b, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) {
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_math_eval, dim3(blocks), dim3(256), 0, ctx->stream, fn, n, dx, dx2, dy, dy2);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(y, dy, b, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess && two_out) e = hipMemcpyAsync(y2, dy2, b, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  const hipError_t ef = hipFree(d);
+  if (e != hipSuccess) return fail(IPX_EDEVICE, "ipx_math_eval: %s", hipGetErrorString(e));
+  if (ef != hipSuccess) return fail(IPX_EDEVICE, "ipx_math_eval: hipFree: %s", hipGetErrorString(ef));
+  return IPX_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Launch helpers
 // ---------------------------------------------------------------------------
 static EventCols cols_of(const ipx_dataset* d) {

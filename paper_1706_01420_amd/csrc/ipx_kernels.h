@@ -123,10 +123,10 @@ __device__ __forceinline__ double reduce_component(const double* __restrict__ p,
 template <bool GRAD>
 __device__ __forceinline__ void event_mass(const MassConst& k, double m, double w, double* acc) {
   const double d = m - k.mu;
-  const double G = exp(-d * d * k.q);
-  const double E = exp(-k.lam * (m - kMLo));
+  const double G = exp_fast(-d * d * k.q);
+  const double E = exp_fast(-k.lam * (m - kMLo));
   const double P = k.cS * G + k.cB * E;
-  acc[0] += w * log(P);
+  acc[0] += w * log_fast(P);
   if constexpr (GRAD) {
     const double iw = w / P;
     const double ps = k.cS * G * iw;
@@ -169,7 +169,7 @@ __device__ __forceinline__ TimePoint time_point(double tau, double gmax, double 
   // the depth search (four wave votes) only where some lane needs it
   p.depth = __any(p.need) ? cf_depth_wave(p.need ? E : kCfSkipE) : 1;
   const double a = tau * inv_r2s;
-  p.g = p.need ? exp(-a * a) : 0.0;
+  p.g = p.need ? exp_fast(-a * a) : 0.0;
   return p;
 }
 
@@ -206,8 +206,8 @@ __device__ __forceinline__ RateTerms rate_terms(double t, double rate, double h2
                                                 const TimePoint& pt, const TimePoint& pa,
                                                 const TimePoint& pb, double dphi) {
   RateTerms r;
-  const double e2 = exp(h2 * s2);
-  const double Ft = conv_real(t, rate, e2 * exp(-rate * t), pt, s2, inv_r2s);
+  const double e2 = exp_fast(h2 * s2);
+  const double Ft = conv_real(t, rate, e2 * exp_fast(-rate * t), pt, s2, inv_r2s);
   const double Fa = conv_real(kTLo, rate, e2 * eA, pa, s2, inv_r2s);
   const double Fb = conv_real(kTHi, rate, e2 * eB, pb, s2, inv_r2s);
   r.F = Ft;
@@ -251,11 +251,11 @@ __device__ __forceinline__ void event_masstime(const MassTimeConst& k, double m,
   const RateTerms rs = rate_terms<GRAD>(t, k.gs, k.hs2, k.eAs, k.eBs, k.inv_gs, sig, s2, inv_r2s, pt, pa, pb, dphi);
   const RateTerms rb = rate_terms<GRAD>(t, k.gb, k.hb2, k.eAb, k.eBb, k.inv_gb, sig, s2, inv_r2s, pt, pa, pb, dphi);
   const double d = m - k.mu;
-  const double G = exp(-d * d * k.q);
-  const double E = exp(-k.lam * (m - kMLo));
+  const double G = exp_fast(-d * d * k.q);
+  const double E = exp_fast(-k.lam * (m - kMLo));
   const double hs = rs.F * rcp(rs.I), hb = rb.F * rcp(rb.I);
   const double P = k.cS * G * hs + k.cB * E * hb;
-  acc[0] += w * log(P);
+  acc[0] += w * log_fast(P);
   if constexpr (GRAD) {
     const double iw = w * rcp(P);
     const double ps = k.cS * G * hs * iw;  // w x signal posterior
@@ -304,25 +304,27 @@ __device__ __forceinline__ cplx dconv_cplx(double tau, const AngTimeConst& k, cp
   return cplx{r.re - s2 * Gt, r.im};
 }
 
-// The ten angular functions f_k(Omega).
+// The ten angular functions f_k(Omega) of the P + S wave decomposition.  The
+// terms with sin(theta_K) and sin(theta_l) (through sin 2theta = 2 sin cos)
+// need only the product sin(theta_K) sin(theta_l), one square root.
 __device__ __forceinline__ void angular_functions(double ck, double cl, double ph, double* f) {
   const double sk2 = 1.0 - ck * ck, sl2 = 1.0 - cl * cl;
-  const double sk = sqrt(sk2), sl = sqrt(sl2);
+  const double v = cl * sqrt(sk2 * sl2);  // cos(theta_l) sin(theta_K) sin(theta_l)
   double sph, cph;
-  sincos(ph, &sph, &cph);
-  const double s2k = 2.0 * sk * ck, s2l = 2.0 * sl * cl;
-  constexpr double c5 = 0.70710678118654752440;   // sqrt2/2
-  constexpr double c8 = 0.81649658092772603273;   // sqrt6/3
-  constexpr double c10 = 2.3094010767585030580;   // 4 sqrt3/3
+  sincos_fast(ph, &sph, &cph);
+  constexpr double c5 = 4.0 * 0.70710678118654752440;  // 4 x sqrt2/2 (sin 2theta_K sin 2theta_l)
+  constexpr double c8 = 2.0 * 0.81649658092772603273;  // 2 x sqrt6/3 (sin theta_K sin 2theta_l)
+  constexpr double c10 = 2.3094010767585030580;        // 4 sqrt3/3
+  const double ckv = ck * v;
   f[0] = 2.0 * ck * ck * sl2;
   f[1] = sk2 * (1.0 - sl2 * cph * cph);
   f[2] = sk2 * (1.0 - sl2 * sph * sph);
   f[3] = sk2 * sl2 * (2.0 * sph * cph);
-  f[4] = -c5 * s2k * s2l * cph;
-  f[5] = c5 * s2k * s2l * sph;
+  f[4] = -c5 * ckv * cph;
+  f[5] = c5 * ckv * sph;
   f[6] = (2.0 / 3.0) * sl2;
-  f[7] = -c8 * sk * s2l * cph;
-  f[8] = c8 * sk * s2l * sph;
+  f[7] = -c8 * v * cph;
+  f[8] = c8 * v * sph;
   f[9] = c10 * ck * sl2;
 }
 
@@ -347,15 +349,15 @@ __device__ __forceinline__ void event_angtime(const AngTimeConst& k, const doubl
   const double inv_sig = rcp(sig);
   const double inv_r2s = kInvSqrt2 * inv_sig;
   const double dmr = k.dm * sig * kInvSqrt2;
-  const double eH2 = exp_small(k.hH2 * s2), eL2 = exp_small(k.hL2 * s2), ec2 = exp(k.hc2 * s2);
+  const double eH2 = exp_small(k.hH2 * s2), eL2 = exp_small(k.hL2 * s2), ec2 = exp_fast(k.hc2 * s2);
   double sc, cc;
   sincos_small(k.gdm * s2, &sc, &cc);
   double st, ct;
-  sincos(k.dm * t, &st, &ct);
+  sincos_fast(k.dm * t, &st, &ct);
   // exp(z^2 s^2/2 - z tau) for z = Gamma - i dm has phase dm (tau - Gamma s^2);
   // e^{-Gamma_H t} = e^{-Gamma t} e^{DeltaGamma t/2}, e^{-Gamma_L t} = e^{-Gamma t} / e^{DeltaGamma t/2}
-  const double eG = exp(-k.g * t);
-  const double eD = exp(k.hdg * t);
+  const double eG = exp_fast(-k.g * t);
+  const double eD = exp_fast(k.hdg * t);
   const double mt = ec2 * eG;
   const Conv3 Xt = conv3(t, eH2 * (eG * eD), eL2 * (eG * rcp(eD)),
                          cplx{mt * (ct * cc + st * sc), mt * (st * cc - ct * sc)}, k, s2, inv_r2s, dmr, 0.0);
@@ -386,7 +388,7 @@ __device__ __forceinline__ void event_angtime(const AngTimeConst& k, const doubl
   const double num = A[0] * T[0] + A[1] * T[1] + A[2] * T[2] + A[3] * T[3];
   const double den = k.D[0] * I[0] + k.D[1] * I[1] + k.D[2] * I[2] + k.D[3] * I[3];
   const double d = m - k.mu;
-  acc[0] += w * (log(num * rcp(den)) - d * d * k.q - k.lnNG);
+  acc[0] += w * (log_fast(num * rcp(den)) - d * d * k.q - k.lnNG);
 
   if constexpr (GRAD) {
     const double inum = w * rcp(num), iden = w * rcp(den);

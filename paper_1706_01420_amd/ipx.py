@@ -36,6 +36,7 @@ IPX_COPY_DEVICE = 1
 IPX_BORROW_DEVICE = 2
 IPX_KEEP_ORDER = 4
 IPX_NO_WEIGHTS = 8
+IPX_FN_EXP, IPX_FN_LOG, IPX_FN_SINCOS, IPX_FN_ERFCX, IPX_FN_FADDEEVA = 0, 1, 2, 3, 4
 
 _c_double_p = ctypes.POINTER(ctypes.c_double)
 _c_void_pp = ctypes.POINTER(ctypes.c_void_p)
@@ -83,6 +84,9 @@ _SIGNATURES = [
     ("ipx_timing_enable", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     ("ipx_timing_read", ctypes.c_int,
      [ctypes.c_void_p, _c_double_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]),
+    ("ipx_math_eval", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+      ctypes.c_void_p]),
 ]
 EXPORTED = [s[0] for s in _SIGNATURES]
 
@@ -424,3 +428,21 @@ def ipx_timing_read(ctx, reset=False):
     n = ctypes.c_int64()
     _check(_lib.ipx_timing_read(ctx, ctypes.byref(ms), ctypes.byref(n), 1 if reset else 0))
     return ms.value, n.value
+
+
+def ipx_math_eval(ctx, fn, x, x2=None):
+    """Device elementary function fn (IPX_FN_*) on the array x (and x2 for the
+    Faddeeva function); returns y, or (y, y2) for IPX_FN_SINCOS and
+    IPX_FN_FADDEEVA."""
+    x = np.ascontiguousarray(x, np.float64).ravel()
+    n = x.size
+    two_out = fn in (IPX_FN_SINCOS, IPX_FN_FADDEEVA)
+    if fn == IPX_FN_FADDEEVA:
+        x2 = np.ascontiguousarray(x2, np.float64).ravel()
+        if x2.size != n:
+            raise ValueError("x2 must have the size of x")
+    y = np.empty(n)
+    y2 = np.empty(n) if two_out else None
+    _check(_lib.ipx_math_eval(ctx, int(fn), n, x.ctypes.data, x2.ctypes.data if x2 is not None else None,
+                              y.ctypes.data, y2.ctypes.data if two_out else None))
+    return (y, y2) if two_out else y
