@@ -28,9 +28,8 @@ PEAK_HBM_GBS = 8000.0
 FLOP_BASE = {
     (1, False): 73, (1, True): 93,
     (2, False): 193, (2, True): 348,
-    (3, False): 467, (3, True): 592,      # angular: per-event kernel
+    (3, False): 467, (3, True): 672,      # angular (gradient: with the 40 coefficient adjoints, 40 a*b+c)
 }
-FLOP_OUTER = 162                           # angular gradient: coefficient-adjoint kernel
 # A resolution correction needed at one time point costs a + b K with K the
 # continued-fraction depth of the wave (a real erfcx is 6 + 7K, the complex w
 # 25 + 21K; the levels after the first run in pairs, so K is the table's depth

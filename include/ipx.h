@@ -185,8 +185,8 @@ IPX_API ipx_status nll_eval_batch(ipx_ctx *ctx, ipx_plan *plan, const double *th
  * many concurrent clients (minimizers, MCMC chains) over resident datasets
  * (the paper's samplers and fitters each call the likelihood once per
  * parameter vector).  Requests are admitted into device slots as slots and
- * scratch memory (the request's tile partials, and the per-event scratch of
- * the angular gradient) free up, so requests arriving while others run join
+ * scratch memory (the request's tile partials: kAccMax doubles per 1024-event
+ * tile at most) free up, so requests arriving while others run join
  * the same launch; each request's result is bitwise the same as nll_eval /
  * nll_grad on its dataset alone.  The device loop ends by itself after an
  * idle period and is relaunched when work arrives.
@@ -204,7 +204,6 @@ typedef struct {
   int workgroups;          /* persistent workgroups, one of which polls the host
                               (>= 2; 0 = 2 per compute unit) */
   int idle_iterations;     /* empty scans before the device loop exits (0 = 20000) */
-  int spin_limit;          /* cap on a wait for a request's first phase (0 = 2^24) */
   int max_pending;         /* waiting requests accepted (0 = unlimited) */
 } ipx_server_cfg;
 typedef struct {

@@ -82,9 +82,7 @@ struct ipx_dataset {
   const double* cols[6] = {};
   const double* w = nullptr;
   int64_t n_tiles = 0;
-  int64_t n_tiles_outer = 0;       // tiles of the angular coefficient-adjoint kernel
   bool sorted = false;             // events stored in resolution-band order
-  double* tau = nullptr;           // 4 x n_pad per-event adjoint factors (angular gradient)
   double* partials = nullptr;      // n_tiles x kAccMax
   double* out_dev = nullptr;       // kAccMax
   double* out_host = nullptr;      // kAccMax, pinned
@@ -231,7 +229,6 @@ static void free_plan(struct ipx_plan* p);
 static void free_dataset(ipx_dataset* d) {
   if (d->self) free_plan(d->self);
   if (d->base) (void)hipFree(d->base);
-  if (d->tau) (void)hipFree(d->tau);
   if (d->partials) (void)hipFree(d->partials);
   if (d->out_dev) (void)hipFree(d->out_dev);
   if (d->out_host) (void)hipHostFree(d->out_host);
@@ -260,7 +257,6 @@ ipx_status ipx_dataset_create(ipx_ctx* ctx, int model, int64_t n, const double* 
   d->ncols = ncols;
   d->n_pad = (n + 31) / 32 * 32;  // 256-byte aligned columns
   d->n_tiles = (n + kTile - 1) / kTile;
-  d->n_tiles_outer = (n + kOuterTile - 1) / kOuterTile;
   const int64_t tiles_alloc = d->n_tiles > 0 ? d->n_tiles : 1;
   hipError_t e = hipSuccess;
   if (kind == IPX_BORROW_DEVICE) {
@@ -565,7 +561,6 @@ static hipError_t alloc_toy_dataset(int model, int64_t n, bool weighted, ipx_dat
   d->ncols = ncols;
   d->n_pad = (n + 31) / 32 * 32;
   d->n_tiles = (n + kTile - 1) / kTile;
-  d->n_tiles_outer = (n + kOuterTile - 1) / kOuterTile;
   const int nstore = ncols + (weighted ? 1 : 0);
   const size_t bytes = (size_t)nstore * (size_t)(d->n_pad > 0 ? d->n_pad : 32) * sizeof(double);
   hipError_t e = hipMalloc(&d->base, bytes);
@@ -883,8 +878,7 @@ struct ipx_plan {
   size_t const_size = 0;
   SegInfo* d_segs = nullptr;
   TileRef* d_tiles = nullptr;
-  TileRef* d_tiles_outer = nullptr;
-  int64_t n_tiles = 0, n_tiles_outer = 0;
+  int64_t n_tiles = 0;
   void* h_consts = nullptr;        // pinned [constants | active flags], written by the host
   unsigned char* h_active = nullptr;
   void* d_consts = nullptr;        // the same block's device address (read by the kernels)
@@ -902,7 +896,7 @@ static void free_plan(struct ipx_plan* p) {
     for (ipx_dataset* d : p->ds) d->plan_refs--;
   for (int i = 0; i < 2; ++i)
     if (p->exec[i]) (void)hipGraphExecDestroy(p->exec[i]);
-  (void)hipFree(p->d_segs); (void)hipFree(p->d_tiles); (void)hipFree(p->d_tiles_outer);
+  (void)hipFree(p->d_segs); (void)hipFree(p->d_tiles);
   if (p->h_consts) (void)hipHostFree(p->h_consts);
   if (p->h_out) (void)hipHostFree(p->h_out);
   delete p;
@@ -936,30 +930,19 @@ static ipx_status plan_create(ipx_ctx* ctx, int nb, ipx_dataset* const* ds, ipx_
   p->ds.assign(ds, ds + nb);
   p->const_size = const_size_of(model);
   std::vector<SegInfo> segs(nb);
-  std::vector<TileRef> tiles, outer;
+  std::vector<TileRef> tiles;
   hipError_t e = hipSuccess;
-  for (int j = 0; j < nb && e == hipSuccess; ++j) {
+  for (int j = 0; j < nb; ++j) {
     ipx_dataset* d = ds[j];
-    if (model == 3 && !d->tau && d->n > 0) {
-      e = hipMalloc(&d->tau, 4 * (size_t)d->n_pad * sizeof(double));
-      if (e != hipSuccess) d->tau = nullptr;
-      else d->bytes += 4 * (size_t)d->n_pad * sizeof(double);
-    }
     SegInfo& S = segs[j];
     S.cols = cols_of(d);
     S.partials = d->partials;
-    S.tau = d->tau;
-    S.tau_stride = d->n_pad;
     S.n_tiles = d->n_tiles;
-    S.n_tiles_outer = d->n_tiles_outer;
     for (int64_t t = 0; t < d->n_tiles; ++t) tiles.push_back(TileRef{j, (int)t});
-    for (int64_t t = 0; t < d->n_tiles_outer; ++t) outer.push_back(TileRef{j, (int)t});
   }
   p->n_tiles = (int64_t)tiles.size();
-  p->n_tiles_outer = (int64_t)outer.size();
   if (e == hipSuccess) e = hipMalloc(&p->d_segs, nb * sizeof(SegInfo));
   if (e == hipSuccess) e = hipMalloc(&p->d_tiles, std::max<size_t>(1, tiles.size()) * sizeof(TileRef));
-  if (e == hipSuccess) e = hipMalloc(&p->d_tiles_outer, std::max<size_t>(1, outer.size()) * sizeof(TileRef));
   const size_t cbytes = (nb * p->const_size + 255) / 256 * 256;
   p->stage_bytes = cbytes + (size_t)nb;
   if (e == hipSuccess) e = hipHostMalloc(&p->h_consts, p->stage_bytes, hipHostMallocDefault);
@@ -973,8 +956,6 @@ static ipx_status plan_create(ipx_ctx* ctx, int nb, ipx_dataset* const* ds, ipx_
   if (e == hipSuccess) e = hipMemcpy(p->d_segs, segs.data(), nb * sizeof(SegInfo), hipMemcpyHostToDevice);
   if (e == hipSuccess && !tiles.empty())
     e = hipMemcpy(p->d_tiles, tiles.data(), tiles.size() * sizeof(TileRef), hipMemcpyHostToDevice);
-  if (e == hipSuccess && !outer.empty())
-    e = hipMemcpy(p->d_tiles_outer, outer.data(), outer.size() * sizeof(TileRef), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     free_plan(p);
     return fail(IPX_ENOMEM, "ipx_plan_create: allocation failed: %s", hipGetErrorString(e));
@@ -1013,8 +994,7 @@ static ipx_status timing_end(ipx_ctx* ctx, hipStream_t s) {
 }
 
 // Stream operations of one (batched) evaluation: the per-event kernel (timed
-// through `timer` when given), for the angular gradient the
-// coefficient-adjoint kernel, the per-segment reductions.  The kernels read the
+// through `timer` when given), then the per-segment reductions.  The kernels read the
 // hoisted constants and active flags from pinned host memory (written by the
 // host before the launch; the few hundred bytes are cached on the device after
 // the first workgroup's read) and the reductions write the results into pinned
@@ -1022,46 +1002,32 @@ static ipx_status timing_end(ipx_ctx* ctx, hipStream_t s) {
 static ipx_status enqueue_batch(ipx_plan* p, bool grad, hipStream_t s, ipx_ctx* timer) {
   const int nb = p->nb;
   const unsigned grid = (unsigned)std::max<int64_t>(1, p->n_tiles);
-  int nacc = 1, split = 1;
+  int nacc = 1;
   {
     ipx_status st = timing_begin(timer, s);
     if (st != IPX_OK) return st;
   }
   if (p->model == 1) {
     nacc = grad ? kAccMass : 1;
-    split = nacc;
     if (grad) hipLaunchKernelGGL((k_nll_batch<1, true>), dim3(grid), dim3(kThreads), 0, s, p->d_segs, p->d_tiles, p->n_tiles, (const MassConst*)p->d_consts, p->d_active);
     else hipLaunchKernelGGL((k_nll_batch<1, false>), dim3(grid), dim3(kThreads), 0, s, p->d_segs, p->d_tiles, p->n_tiles, (const MassConst*)p->d_consts, p->d_active);
   } else if (p->model == 2) {
     nacc = grad ? kAccMassTime : 1;
-    split = nacc;
     if (grad) hipLaunchKernelGGL((k_nll_batch<2, true>), dim3(grid), dim3(kThreads), 0, s, p->d_segs, p->d_tiles, p->n_tiles, (const MassTimeConst*)p->d_consts, p->d_active);
     else hipLaunchKernelGGL((k_nll_batch<2, false>), dim3(grid), dim3(kThreads), 0, s, p->d_segs, p->d_tiles, p->n_tiles, (const MassTimeConst*)p->d_consts, p->d_active);
   } else {
     nacc = grad ? kAccAngTime : 1;
-    split = grad ? kAngInner : 1;
     if (grad) hipLaunchKernelGGL((k_angtime_batch<true>), dim3(grid), dim3(kThreads), 0, s, p->d_segs, p->d_tiles, p->n_tiles, (const AngTimeConst*)p->d_consts, p->d_active);
     else hipLaunchKernelGGL((k_angtime_batch<false>), dim3(grid), dim3(kThreads), 0, s, p->d_segs, p->d_tiles, p->n_tiles, (const AngTimeConst*)p->d_consts, p->d_active);
-    HIP_TRY(hipGetLastError());
-    {
-      ipx_status st = timing_end(timer, s);
-      if (st != IPX_OK) return st;
-    }
-    if (grad) {
-      const unsigned go = (unsigned)std::max<int64_t>(1, p->n_tiles_outer);
-      hipLaunchKernelGGL(k_angtime_outer_batch, dim3(go), dim3(kThreads), 0, s, p->d_segs, p->d_tiles_outer,
-                         p->n_tiles_outer, p->d_active);
-    }
   }
   HIP_TRY(hipGetLastError());
-  if (p->model != 3) {
+  {
     ipx_status st = timing_end(timer, s);
     if (st != IPX_OK) return st;
   }
   // the totals go straight to pinned host memory (visible once the stream
   // has synchronised)
-  hipLaunchKernelGGL(k_reduce_batch, dim3(nacc, nb), dim3(kThreads), 0, s, p->d_segs, p->d_active, split,
-                     p->h_out_dev);
+  hipLaunchKernelGGL(k_reduce_batch, dim3(nacc, nb), dim3(kThreads), 0, s, p->d_segs, p->d_active, p->h_out_dev);
   HIP_TRY(hipGetLastError());
   return IPX_OK;
 }
@@ -1230,9 +1196,7 @@ static int serve_nacc(int model, int grad) {
 }
 
 static size_t request_bytes(const ipx_dataset* d, int grad) {
-  size_t b = align256((size_t)std::max<int64_t>(1, d->n_tiles) * serve_nacc(d->model, grad) * sizeof(double));
-  if (d->model == 3 && grad) b += align256(4 * (size_t)d->n_pad * sizeof(double));
-  return b;
+  return align256((size_t)std::max<int64_t>(1, d->n_tiles) * serve_nacc(d->model, grad) * sizeof(double));
 }
 
 // Fill the descriptor of a request in its slot and publish it.
@@ -1242,23 +1206,14 @@ static void serve_publish(ipx_server* S, ServeReq* r) {
   const ipx_dataset* d = r->ds;
   D.model = r->model;
   D.grad = r->grad;
-  D.nA = (int)d->n_tiles;
-  D.nB = (r->model == 3 && r->grad) ? (int)d->n_tiles_outer : 0;
+  D.items = (int)d->n_tiles;
   D.nacc = serve_nacc(r->model, r->grad);
-  D.split = r->model == 3 && r->grad ? kAngInner : D.nacc;
   D.seg.cols = cols_of(d);
-  char* base = S->pool + r->off;
-  D.seg.partials = (double*)base;
-  D.seg.tau = r->model == 3 && r->grad
-                  ? (double*)(base + align256((size_t)std::max<int64_t>(1, d->n_tiles) * D.nacc * sizeof(double)))
-                  : nullptr;
-  D.seg.tau_stride = d->n_pad;
+  D.seg.partials = (double*)(S->pool + r->off);
   D.seg.n_tiles = d->n_tiles;
-  D.seg.n_tiles_outer = d->n_tiles_outer;
   if (r->model == 1) D.k.m1 = r->h1.k;
   else if (r->model == 2) D.k.m2 = r->h2.k;
   else D.k.m3 = r->h3.k;
-  S->hs->status[r->slot] = 0;
   r->seq = ++S->slot_seq[r->slot];
   D.seq = r->seq;
   __atomic_store_n(&S->hs->mail[r->slot], (unsigned long long)r->seq, __ATOMIC_RELEASE);
@@ -1305,8 +1260,7 @@ static void serve_worker(ipx_server* S) {
       ServeReq* r = S->slot_req[s];
       if (!r) continue;
       if (__atomic_load_n(&S->hs->fin[s], __ATOMIC_ACQUIRE) == r->seq) {
-        const int status = S->hs->status[s] ? IPX_ETIMEOUT : IPX_OK;
-        serve_finish(S, r, status, S->hs->out[s]);
+        serve_finish(S, r, IPX_OK, S->hs->out[s]);
         ++S->stats.completed;
         pool_free(S, r->off, r->bytes);
         S->slot_req[s] = nullptr;
@@ -1340,7 +1294,7 @@ static void serve_worker(ipx_server* S) {
       hipError_t e = hipMemsetD32Async((hipDeviceptr_t)&S->ctl->live, S->cfg.workgroups - 1, 1, S->stream);
       if (e == hipSuccess) {
         hipLaunchKernelGGL(k_serve, dim3((unsigned)S->cfg.workgroups), dim3(kThreads), 0, S->stream, S->hs_dev,
-                           S->ctl, S->dd, S->st, nslots, S->cfg.idle_iterations, S->cfg.spin_limit);
+                           S->ctl, S->dd, S->st, nslots, S->cfg.idle_iterations);
         e = hipGetLastError();
       }
       if (e == hipSuccess) e = hipEventRecord(S->kernel_done, S->stream);
@@ -1403,7 +1357,6 @@ extern "C" ipx_status ipx_server_start(ipx_ctx* ctx, const ipx_server_cfg* cfg, 
   if (c.workgroups == 0) c.workgroups = 2 * std::max(1, ctx->n_cu);
   if (c.workgroups < 2) return fail(IPX_EINVAL, "ipx_server_start: at least 2 workgroups (one polls the host)");
   if (c.idle_iterations <= 0) c.idle_iterations = 20000;
-  if (c.spin_limit <= 0) c.spin_limit = 1 << 24;
   HIP_TRY(hipSetDevice(ctx->device));
   ipx_server* S = new (std::nothrow) ipx_server();
   if (!S) return fail(IPX_ENOMEM, "ipx_server_start: host allocation failed");

@@ -17,10 +17,7 @@ namespace ipx {
 struct SegInfo {
   EventCols cols;
   double* partials;      // n_tiles x kAccMax, component-major
-  double* tau;           // angular gradient scratch (4 x tau_stride)
-  int64_t tau_stride;
   int64_t n_tiles;
-  int64_t n_tiles_outer;
 };
 
 struct TileRef {
@@ -49,14 +46,33 @@ __device__ __forceinline__ void tile_nll(const SegInfo& S, const typename ModelT
   tile_store<NACC, COH>(acc, S.partials, tile, S.n_tiles, red);
 }
 
-// Angular model; C is the coefficient table in LDS.
+// Make a wave's LDS writes visible to its other lanes and keep the compiler
+// from moving LDS accesses across (a wave's LDS operations complete in issue
+// order, so no wait instruction is needed).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Angular model; C is the coefficient table in LDS.  For the gradient, after
+// each round of 64 events a wave forms the 40 coefficient adjoints of those
+// events from its LDS block (lane 4k + j: the sum over the block's columns of
+// f_k tau_j, two interleaved partial sums), so the per-event factors never
+// leave the chip.  Lanes without an event write zeros to the block.  The
+// block is the wave's part of the reduction buffer (CAP x kRedPitch doubles),
+// which the tile reduction reuses afterwards.
 template <bool GRAD, bool COH, int CAP>
 __device__ __forceinline__ void tile_angtime(const SegInfo& S, const AngTimeConst& k, const double* C,
                                              int64_t tile, RedBuf<CAP>& red) {
+  static_assert(!GRAD || CAP * kRedPitch >= kOuterBlock, "the adjoint block lives in the reduction buffer");
   constexpr int NACC = GRAD ? kAngInner : 1;
   double acc[NACC];
 #pragma unroll
   for (int c = 0; c < NACC; ++c) acc[c] = 0.0;
+  double outer = 0.0;
+  const unsigned lane = threadIdx.x & 63u;
+  double* blk = &red.rows[threadIdx.x >> 6][0][0];
   const int64_t base = tile * kTile;
 #pragma unroll 1
   for (int e = 0; e < kEventsPerLane; ++e) {
@@ -69,40 +85,33 @@ __device__ __forceinline__ void tile_angtime(const SegInfo& S, const AngTimeCons
       const double w = cl.w ? ldg<COH>(cl.w + base, j) : 1.0;
       event_angtime<GRAD, COH>(k, C, ldg<COH>(cl.c[0] + base, j), ldg<COH>(cl.c[1] + base, j),
                                ldg<COH>(cl.c[2] + base, j), ldg<COH>(cl.c[3] + base, j), ldg<COH>(cl.c[4] + base, j),
-                               ldg<COH>(cl.c[5] + base, j), w, acc, S.tau + base, S.tau_stride, j);
+                               ldg<COH>(cl.c[5] + base, j), w, acc, blk + lane);
+    } else if constexpr (GRAD) {
+#pragma unroll
+      for (int r = 0; r < kOuterRows; ++r) blk[r * kOuterPitch + lane] = 0.0;
     }
-  }
-  tile_store<NACC, COH>(acc, S.partials, tile, S.n_tiles, red);
-}
-
-// Angular gradient: coefficient adjoints over one outer tile.
-template <bool COH, int CAP>
-__device__ __forceinline__ void tile_angtime_outer(const SegInfo& S, int64_t tile, RedBuf<CAP>& red) {
-  double acc[kAngOuter];
-#pragma unroll
-  for (int c = 0; c < kAngOuter; ++c) acc[c] = 0.0;
-  const int64_t base = tile * kOuterTile;
-#pragma unroll 1
-  for (int e = 0; e < kOuterEventsPerLane; ++e) {
-    const unsigned j = threadIdx.x + (unsigned)e * kThreads;
-    if (base + j < S.cols.n) {
-      double f[10];
-      angular_functions(ldg<COH>(S.cols.c[0] + base, j), ldg<COH>(S.cols.c[1] + base, j),
-                        ldg<COH>(S.cols.c[2] + base, j), f);
-      const double* tau = S.tau + base;
-      const int64_t ts = S.tau_stride;
-      const double t0 = ldg<COH>(tau, j), t1 = ldg<COH>(tau + ts, j), t2 = ldg<COH>(tau + 2 * ts, j),
-                   t3 = ldg<COH>(tau + 3 * ts, j);
-#pragma unroll
-      for (int kk = 0; kk < 10; ++kk) {
-        acc[4 * kk + 0] += f[kk] * t0;
-        acc[4 * kk + 1] += f[kk] * t1;
-        acc[4 * kk + 2] += f[kk] * t2;
-        acc[4 * kk + 3] += f[kk] * t3;
+    if constexpr (GRAD) {
+      wave_lds_sync();
+      if (lane < (unsigned)kAngOuter) {
+        const double* fr = blk + (lane >> 2) * kOuterPitch;
+        const double* tr = blk + (10 + (lane & 3u)) * kOuterPitch;
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll 8
+        for (int c = 0; c < 64; c += 2) {
+          s0 = fma(fr[c], tr[c], s0);
+          s1 = fma(fr[c + 1], tr[c + 1], s1);
+        }
+        outer += s0 + s1;
       }
+      wave_lds_sync();
     }
   }
-  tile_store<kAngOuter, COH>(acc, S.partials + kAngOuter0 * S.n_tiles, tile, S.n_tiles, red);
+  if constexpr (GRAD) {
+    if (lane < (unsigned)kAngOuter) red.wsum[threadIdx.x >> 6][kAngOuter0 + lane] = outer;
+    tile_store<NACC, COH, CAP, kAccAngTime>(acc, S.partials, tile, S.n_tiles, red);
+  } else {
+    tile_store<NACC, COH, CAP>(acc, S.partials, tile, S.n_tiles, red);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -124,17 +133,19 @@ __global__ __launch_bounds__(kThreads) void k_nll_batch(const SegInfo* __restric
   }
 }
 
-// Angular model: per-event kernel.
-// The gradient instance is held to 128 VGPRs (4 waves/SIMD; its natural
-// allocation is 129, i.e. 3 waves, and the extra wave shortens the tail of the
-// launch more than the few spilled registers cost).
+// Angular model.
+// The gradient instance is held to 128 VGPRs (4 waves/SIMD; the extra wave
+// shortens the tail of the launch more than the few spilled registers cost);
+// its LDS (adjoint blocks sharing the reduction buffer, ~33 KB) allows 4
+// workgroups per compute unit.
 template <bool GRAD>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(GRAD ? 4 : 1))) void k_angtime_batch(const SegInfo* __restrict__ segs,
                                                             const TileRef* __restrict__ tiles, int64_t n_tiles,
                                                             const AngTimeConst* __restrict__ consts,
                                                             const unsigned char* __restrict__ active) {
+  constexpr int kCap = GRAD ? (kOuterBlock + kRedPitch - 1) / kRedPitch : 1;
   __shared__ double sC[40];
-  __shared__ RedBuf<GRAD ? kAngInner : 1> red;
+  __shared__ RedBuf<kCap> red;
   for (int64_t g = blockIdx.x; g < n_tiles; g += gridDim.x) {
     const TileRef tr = tiles[g];
     if (!active[tr.seg]) continue;
@@ -145,30 +156,16 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(GRAD ?
   }
 }
 
-// Angular model: coefficient adjoints over the outer tiles of each segment.
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_angtime_outer_batch(const SegInfo* __restrict__ segs,
-                                                                  const TileRef* __restrict__ tiles,
-                                                                  int64_t n_tiles,
-                                                                  const unsigned char* __restrict__ active) {
-  __shared__ RedBuf<kAngOuter / 4> red;   // 4 passes of 10 components: 22 KB, 4 workgroups per CU
-  for (int64_t g = blockIdx.x; g < n_tiles; g += gridDim.x) {
-    const TileRef tr = tiles[g];
-    if (!active[tr.seg]) continue;
-    tile_angtime_outer<false>(segs[tr.seg], tr.tile, red);
-  }
-}
-
 // out[seg * kAccMax + c] = sum of the segment's tile partials of component c;
-// grid (nacc, n_segments).  Components >= split use the outer tile count.
+// grid (nacc, n_segments).
 __global__ __launch_bounds__(kThreads) void k_reduce_batch(const SegInfo* __restrict__ segs,
-                                                           const unsigned char* __restrict__ active, int split,
+                                                           const unsigned char* __restrict__ active,
                                                            double* __restrict__ out) {
   const int seg = blockIdx.y;
   if (!active[seg]) return;
   const int c = blockIdx.x;
   const SegInfo& S = segs[seg];
-  const int64_t nt = c < split ? S.n_tiles : S.n_tiles_outer;
-  const double total = reduce_component(S.partials + (int64_t)c * S.n_tiles, nt);
+  const double total = reduce_component(S.partials + (int64_t)c * S.n_tiles, S.n_tiles);
   if (threadIdx.x == 0) out[(int64_t)seg * kAccMax + c] = total;
 }
 

@@ -28,7 +28,7 @@ namespace ipx {
 // COH = true makes every access device-coherent (relaxed atomics at agent
 // scope: the L2 of each XCD is bypassed for stores and revalidated for loads).
 // The persistent serving kernel uses it for everything that other workgroups
-// of the same launch produce or consume (partials, per-event factors), and for
+// of the same launch produce or consume (tile partials), and for
 // the event columns (which may have been written after the launch started);
 // the kernels of one-shot launches, ordered by kernel boundaries, use plain
 // accesses.
@@ -63,7 +63,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 // combined pairwise).  Components are done in chunks of at most CAP rows (the
 // block the kernel provides: kThreads / 64 waves x CAP rows x kRedPitch).  The
 // four wave totals are combined in wave order.  Every order is a function of
-// the tile's lane layout only.
+// the tile's lane layout only.  Components NACC .. NTOT - 1 arrive as wave
+// totals that the caller has written to wsum (before the call) and are only
+// combined across the waves.
 constexpr int kRedPitch = 65;
 
 template <int CAP>
@@ -72,9 +74,10 @@ struct RedBuf {
   double wsum[kThreads / 64][kAccMax];
 };
 
-template <int NACC, bool COH, int CAP>
+template <int NACC, bool COH, int CAP, int NTOT = NACC>
 __device__ __forceinline__ void tile_store(const double (&acc)[NACC], double* __restrict__ partials,
                                            int64_t tile, int64_t n_tiles, RedBuf<CAP>& red) {
+  static_assert(NTOT >= NACC && NTOT <= kAccMax, "wave totals live in wsum");
   constexpr int kChunk = NACC < CAP ? NACC : CAP;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -98,7 +101,7 @@ __device__ __forceinline__ void tile_store(const double (&acc)[NACC], double* __
     }
     __syncthreads();
   }
-  for (int c = threadIdx.x; c < NACC; c += kThreads)
+  for (int c = threadIdx.x; c < NTOT; c += kThreads)
     stg<COH>(partials + (int64_t)c * n_tiles + tile, 0u,
              (red.wsum[0][c] + red.wsum[1][c]) + (red.wsum[2][c] + red.wsum[3][c]));
   __syncthreads();
@@ -328,22 +331,28 @@ __device__ __forceinline__ void angular_functions(double ck, double cl, double p
   f[9] = c10 * ck * sl2;
 }
 
-// Accumulator layout of the angular adjoint kernel (the 40 coefficient
-// adjoints come from k_angtime_outer at components kAngOuter0 + 4k + j).
+// Accumulator layout of the angular gradient: components 0 .. 11 are per-lane
+// sums; the 40 coefficient adjoints (component kAngOuter0 + 4k + j, the sum
+// over events of f_k tau_j) are formed per wave from the block below.
 constexpr int kAngInner = 12;   // l, dD[4], dgH, dgL, dzr, ddm, dmu, dq, sum_w
 constexpr int kAngOuter0 = 12;
 constexpr int kAngOuter = 40;
-constexpr int kOuterEventsPerLane = 16;
-constexpr int kOuterTile = kThreads * kOuterEventsPerLane;
+
+// Per-wave LDS block of the angular gradient: row k < 10 holds f_k and row
+// 10 + j holds tau_j of the wave's 64 current events (lane = column).  Rows
+// are padded to 66 doubles so that the ten f rows (and the four tau rows) that
+// one read instruction touches fall in distinct banks.
+constexpr int kOuterPitch = 66;
+constexpr int kOuterRows = 14;
+constexpr int kOuterBlock = kOuterRows * kOuterPitch;
 
 // One event.  C is the coefficient table in LDS (row-major 10 x 4).  For the
-// gradient, writes tau_j = w T_j / num to tau[j * tau_stride + i] (tau is the
-// tile's base, i the event's offset within the tile).
+// gradient, writes f_k and tau_j = w T_j / num into the wave's block at column
+// ob (ob = block + lane).
 template <bool GRAD, bool COH = false>
 __device__ __forceinline__ void event_angtime(const AngTimeConst& k, const double* __restrict__ C,
                                               double ck, double cl, double ph, double t, double sig,
-                                              double m, double w, double* acc, double* __restrict__ tau,
-                                              int64_t tau_stride, unsigned i) {
+                                              double m, double w, double* acc, double* ob) {
   // time: per-event factors shared by t, T_LO and T_HI
   const double s2 = sig * sig;
   const double inv_sig = rcp(sig);
@@ -393,7 +402,9 @@ __device__ __forceinline__ void event_angtime(const AngTimeConst& k, const doubl
   if constexpr (GRAD) {
     const double inum = w * rcp(num), iden = w * rcp(den);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) stg<COH>(tau + j * tau_stride, i, T[j] * inum);
+    for (int kk = 0; kk < 10; ++kk) ob[kk * kOuterPitch] = f[kk];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) ob[(10 + j) * kOuterPitch] = T[j] * inum;
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[1 + j] -= I[j] * iden;
     const double Gt = Xt.g * kInvSqrt2Pi * inv_sig;

@@ -20,7 +20,7 @@ constexpr int kTile = kThreads * kEventsPerLane;
 // Accumulator layout (component 0 is always sum_i w_i ln P_i).
 constexpr int kAccMass = 6;       // l, dcS, dcB, dmu, dq, dlam
 constexpr int kAccMassTime = 9;   // l, dcS, dcB, dmu, dq, dlam, dgs, dgb, ds
-constexpr int kAccAngTime = 52;   // l, dC[40], dD[4], dgH, dgL, dzr, ddm, dmu, dq, sum_w
+constexpr int kAccAngTime = 52;   // l, dD[4], dgH, dgL, dzr, ddm, dmu, dq, sum_w, dC[40]
 constexpr int kAccMax = 52;
 
 struct EventCols {

@@ -16,24 +16,20 @@
 //           item (low half).  The item is valid if lim[s] names the same
 //           request and the item is below its count; any other increment is a
 //           late claim on a finished request and is dropped, so no request
-//           can lose an item.  A (per-event) tiles come first, then the
-//           angular gradient's coefficient-adjoint tiles (B), which wait for
-//           every A tile.  The worker that takes a slot's last item clears its
-//           mask bit.  The worker that completes a request's last item sums
+//           can lose an item.  The worker that takes a slot's last item
+//           clears its mask bit.  The worker that completes a request's last item sums
 //           every component's tile partials in index order (the order of the
 //           other entry points), writes out[s], then fin[s] = seq.
 //   exit    a worker leaves after `idle_limit` consecutive scans without a
 //           claim, or when stop is set, and counts itself out of `live`; the
-//           poller leaves when no worker is left or the host sets stop.  The
-//           wait of a B item for its A items is capped by `spin_limit` (the
-//           request then finishes with status 1).
+//           poller leaves when no worker is left or the host sets stop.
 //
 // Memory ordering without cache-wide fences.  On this GPU every XCD has its
 // own L2, and an agent-scope release or acquire fence writes back or
 // invalidates that whole cache; with hundreds of workgroups fencing per item
 // the fences cost more than the tiles.  Instead, every location that one
 // workgroup writes and another reads during the launch (descriptors, lim,
-// claim, counters, tile partials, per-event factors; also the event columns,
+// claim, counters, tile partials; also the event columns,
 // which may have been written after the launch) is accessed with relaxed
 // device-coherent atomics, and a writer waits for its stores to complete
 // (s_waitcnt, then the workgroup barrier) before the atomic that publishes
@@ -41,8 +37,8 @@
 // and coherent loads see every completed coherent store.  Host memory is read
 // and written with system-coherent atomics in the same way.
 //
-// All waits are bounded, so the grid always drains; no workgroup waits on
-// work that has not been claimed by a running workgroup.
+// No workgroup waits on another's work, and every scan is bounded, so the
+// grid always drains.
 #pragma once
 
 #include "ipx_batch.h"
@@ -55,8 +51,8 @@ struct ServeDesc {
   unsigned long long seq;  // the request's sequence number in its slot
   int model;
   int grad;
-  int nA, nB;        // items: per-event tiles, coefficient-adjoint tiles
-  int nacc, split;   // reduced components; components >= split use the outer tiles
+  int items;         // tiles of the dataset
+  int nacc;          // reduced components
   SegInfo seg;       // columns of the dataset + this request's scratch
   union {
     MassConst m1;
@@ -70,8 +66,8 @@ struct ServeSlot {                 // device memory, touched by the GPU only
   unsigned long long claim;        // (seq << 32) | next item
   unsigned long long lim;          // (seq << 32) | items of the request in the slot
   unsigned long long open;         // last seq opened by the poller
-  unsigned int doneA;              // completed A items
   unsigned int done;               // completed items
+  unsigned int pad;
 };
 
 struct ServeCtl {                  // device memory
@@ -86,7 +82,6 @@ struct ServeShared {               // fine-grained host memory
   unsigned long long stop;
   unsigned long long mail[kServeMaxSlots];
   unsigned long long fin[kServeMaxSlots];
-  int status[kServeMaxSlots];
   double out[kServeMaxSlots][kAccMax];
   ServeDesc desc[kServeMaxSlots];
 };
@@ -131,9 +126,8 @@ __device__ __forceinline__ void serve_open(ServeShared* hs, ServeCtl* ctl, Serve
   wait_mem();
   __syncthreads();
   if (threadIdx.x == 0) {
-    const unsigned items = (unsigned)(load_dev(&dd[s].nA) + load_dev(&dd[s].nB));
+    const unsigned items = (unsigned)load_dev(&dd[s].items);
     store_dev(&st[s].open, seq);
-    store_dev(&st[s].doneA, 0u);
     store_dev(&st[s].done, 0u);
     store_dev(&st[s].lim, (seq << 32) | (unsigned long long)items);
     wait_mem();
@@ -186,9 +180,9 @@ __device__ __forceinline__ void serve_poll(ServeShared* hs, ServeCtl* ctl, Serve
 }
 
 __device__ __forceinline__ void serve_work(ServeShared* hs, ServeCtl* ctl, ServeDesc* __restrict__ dd,
-                                           ServeSlot* __restrict__ st, int idle_limit, int spin_limit) {
+                                           ServeSlot* __restrict__ st, int idle_limit) {
   __shared__ ServeDesc sd;          // the current item's request
-  __shared__ RedBuf<kAngOuter / 2> red;
+  __shared__ RedBuf<(kOuterBlock + kRedPitch - 1) / kRedPitch> red;
   __shared__ int cmd, cslot, citem;
   __shared__ int last;
   int idle = 0;
@@ -239,55 +233,32 @@ __device__ __forceinline__ void serve_work(ServeShared* hs, ServeCtl* ctl, Serve
     copy_dev_to_lds((unsigned long long*)&sd, (const unsigned long long*)&dd[s],
                     (int)(sizeof(ServeDesc) / sizeof(unsigned long long)));
     __syncthreads();
-    // items 0 ... nA - 1 are the A tiles, nA ... nA + nB - 1 the B tiles
-    const int item = citem;
-    const bool isA = item < sd.nA;
-    const int tile = isA ? item : item - sd.nA;
-    bool ok = true;
-    if (isA) {
-      if (sd.model == 1) {
-        if (sd.grad) tile_nll<1, true, true>(sd.seg, sd.k.m1, tile, red);
-        else tile_nll<1, false, true>(sd.seg, sd.k.m1, tile, red);
-      } else if (sd.model == 2) {
-        if (sd.grad) tile_nll<2, true, true>(sd.seg, sd.k.m2, tile, red);
-        else tile_nll<2, false, true>(sd.seg, sd.k.m2, tile, red);
-      } else {
-        if (sd.grad) tile_angtime<true, true>(sd.seg, sd.k.m3, &sd.k.m3.C[0][0], tile, red);
-        else tile_angtime<false, true>(sd.seg, sd.k.m3, &sd.k.m3.C[0][0], tile, red);
-      }
+    const int tile = citem;
+    if (sd.model == 1) {
+      if (sd.grad) tile_nll<1, true, true>(sd.seg, sd.k.m1, tile, red);
+      else tile_nll<1, false, true>(sd.seg, sd.k.m1, tile, red);
+    } else if (sd.model == 2) {
+      if (sd.grad) tile_nll<2, true, true>(sd.seg, sd.k.m2, tile, red);
+      else tile_nll<2, false, true>(sd.seg, sd.k.m2, tile, red);
     } else {
-      // phase B needs every A tile (their per-event factors); all A items were
-      // claimed before any B item, so they are held by running workgroups
-      if (threadIdx.x == 0) {
-        int spins = 0;
-        while (load_dev(&st[s].doneA) < (unsigned)sd.nA && spins < spin_limit) {
-          __builtin_amdgcn_s_sleep(2);
-          ++spins;
-        }
-        last = spins < spin_limit ? 1 : 0;
-        wait_mem();  // the per-event factors are read after doneA
-      }
-      __syncthreads();
-      ok = last != 0;
-      if (ok) tile_angtime_outer<true>(sd.seg, tile, red);
+      if (sd.grad) tile_angtime<true, true>(sd.seg, sd.k.m3, &sd.k.m3.C[0][0], tile, red);
+      else tile_angtime<false, true>(sd.seg, sd.k.m3, &sd.k.m3.C[0][0], tile, red);
     }
-    // every lane's stores of this item (tile partials, per-event factors)
-    // complete before the item is counted as done
+    // every lane's stores of this item (its tile partials) complete before
+    // the item is counted as done
     wait_mem();
     __syncthreads();
     if (threadIdx.x == 0) {
-      if (!ok) store_sys(&hs->status[s], 1);
-      if (isA) __hip_atomic_fetch_add(&st[s].doneA, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       const unsigned int prev = __hip_atomic_fetch_add(&st[s].done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      last = prev + 1 == (unsigned)(sd.nA + sd.nB) ? 1 : 0;
+      last = prev + 1 == (unsigned)sd.items ? 1 : 0;
       wait_mem();  // the partials are read after the count
     }
     __syncthreads();
     if (last) {
       // every item of the request is complete: fixed-order reduction
       for (int comp = 0; comp < sd.nacc; ++comp) {
-        const int64_t nt = comp < sd.split ? sd.seg.n_tiles : sd.seg.n_tiles_outer;
-        const double total = reduce_component<true>(sd.seg.partials + (int64_t)comp * sd.seg.n_tiles, nt);
+        const double total =
+            reduce_component<true>(sd.seg.partials + (int64_t)comp * sd.seg.n_tiles, sd.seg.n_tiles);
         if (threadIdx.x == 0) store_sys(&hs->out[s][comp], total);
         __syncthreads();
       }
@@ -302,10 +273,9 @@ __device__ __forceinline__ void serve_work(ServeShared* hs, ServeCtl* ctl, Serve
 
 // Workgroup 0 polls the host, the others evaluate; grid >= 2 workgroups.
 __global__ __launch_bounds__(kThreads) void k_serve(ServeShared* hs, ServeCtl* ctl, ServeDesc* __restrict__ dd,
-                                                    ServeSlot* __restrict__ st, int nslots, int idle_limit,
-                                                    int spin_limit) {
+                                                    ServeSlot* __restrict__ st, int nslots, int idle_limit) {
   if (blockIdx.x == 0) serve_poll(hs, ctl, dd, st, nslots);
-  else serve_work(hs, ctl, dd, st, idle_limit, spin_limit);
+  else serve_work(hs, ctl, dd, st, idle_limit);
 }
 
 }  // namespace ipx

@@ -323,7 +323,7 @@ def nll_eval_batch(ctx, plan, theta, active=None, grad=False, stream=None):
 
 class ServerCfg(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_int), ("scratch_bytes", ctypes.c_size_t), ("workgroups", ctypes.c_int),
-                ("idle_iterations", ctypes.c_int), ("spin_limit", ctypes.c_int), ("max_pending", ctypes.c_int)]
+                ("idle_iterations", ctypes.c_int), ("max_pending", ctypes.c_int)]
 
 
 class _Request(ctypes.Structure):
@@ -339,8 +339,8 @@ def _result_dict(r):
     return {"status": r.status, "nll": r.nll, "grad": np.array(r.grad[:r.np]), "latency_us": r.latency_us}
 
 
-def ipx_server_start(ctx, slots=0, scratch_bytes=0, workgroups=0, idle_iterations=0, spin_limit=0, max_pending=0):
-    cfg = ServerCfg(slots, scratch_bytes, workgroups, idle_iterations, spin_limit, max_pending)
+def ipx_server_start(ctx, slots=0, scratch_bytes=0, workgroups=0, idle_iterations=0, max_pending=0):
+    cfg = ServerCfg(slots, scratch_bytes, workgroups, idle_iterations, max_pending)
     h = ctypes.c_void_p()
     _check(_lib.ipx_server_start(ctx, ctypes.byref(cfg), ctypes.byref(h)))
     return h

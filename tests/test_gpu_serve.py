@@ -116,7 +116,7 @@ def test_mixed_concurrent_traffic_is_bitwise_equal_to_alone(lib, ctx, datasets):
 
 def test_admission_by_scratch_budget(lib, ctx, datasets):
     model, d = datasets[-1]          # angular, 100000 events
-    need = 4 * ((100000 + 31) // 32 * 32) * 8 + 52 * 98 * 8 + 4096
+    need = (52 * 98 * 8 + 255) // 256 * 256   # the tile partials of 98 tiles, 256-byte aligned
     srv = lib.ipx_server_start(ctx, slots=8, scratch_bytes=need + 1024)
     try:
         rng = np.random.default_rng(3)
