@@ -389,6 +389,11 @@ __device__ __forceinline__ void event_angtime(const AngTimeConst& k, const doubl
   // angular part: A_j = sum_k f_k C_kj
   double f[10];
   angular_functions(ck, cl, ph, f);
+  if constexpr (GRAD) {
+    // to the block at once: f dies with the contraction below
+#pragma unroll
+    for (int kk = 0; kk < 10; ++kk) ob[kk * kOuterPitch] = f[kk];
+  }
   double A[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int kk = 0; kk < 10; ++kk)
@@ -401,8 +406,6 @@ __device__ __forceinline__ void event_angtime(const AngTimeConst& k, const doubl
 
   if constexpr (GRAD) {
     const double inum = w * rcp(num), iden = w * rcp(den);
-#pragma unroll
-    for (int kk = 0; kk < 10; ++kk) ob[kk * kOuterPitch] = f[kk];
 #pragma unroll
     for (int j = 0; j < 4; ++j) ob[(10 + j) * kOuterPitch] = T[j] * inum;
 #pragma unroll
