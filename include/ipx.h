@@ -22,7 +22,7 @@
  *   - Parameters outside the model's domain return IPX_EDOMAIN with
  *     *nll = +inf and launch nothing.  An event with P <= 0 or a non-finite
  *     contribution makes the sum non-finite: the call returns IPX_EDOMAIN
- *     with *nll = +inf.
+ *     with *nll = +inf (ipx_count_bad_events counts such events).
  *   - NLL is -ln L (not -2 ln L); a minimizer uses errordef 0.5.
  */
 #ifndef IPX_H
@@ -272,6 +272,19 @@ IPX_API ipx_status toy_generate(ipx_ctx *ctx, int model, const double *theta_gen
 IPX_API ipx_status toy_generate_batch(ipx_ctx *ctx, int model, const double *theta_gen, int np, uint64_t seed,
                                       int ntoys, const uint64_t *toy_ids, const int64_t *n, unsigned flags,
                                       ipx_dataset **out, ipx_toy_stats *stats);
+
+/*
+ * Bad events: the number of events of ds whose contribution w_i ln P_i at
+ * theta is not finite (P_i <= 0, or a non-finite column value or weight), the
+ * events that make nll_eval / nll_grad return IPX_EDOMAIN with a non-finite
+ * likelihood.  A separate diagnostic pass over the dataset (the evaluation
+ * kernels only form the sum); synchronous on the context's stream; allocates
+ * and frees its own device scratch.  *count receives the number (host memory).
+ * IPX_EINVAL for NULL arguments or a wrong np, IPX_EDOMAIN for parameters
+ * outside the model's domain (no launch), IPX_EDEVICE for HIP errors.
+ */
+IPX_API ipx_status ipx_count_bad_events(ipx_ctx *ctx, const ipx_dataset *ds, const double *theta, int np,
+                                        int64_t *count);
 
 /*
  * Timing of the dominant kernel of nll_eval/nll_grad, measured with HIP events

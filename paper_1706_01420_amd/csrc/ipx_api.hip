@@ -1558,7 +1558,91 @@ static ipx_status run(ipx_ctx* ctx, const ipx_dataset* dc, const double* theta, 
   return IPX_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Bad events: the per-event contributions w_i ln P_i that are not finite (the
+// NLL kernels only see their sum).  A diagnostic pass, not part of an
+// evaluation: one count per workgroup, summed on the host.
+// ---------------------------------------------------------------------------
+template <int MODEL>
+__global__ __launch_bounds__(kThreads) void k_count_bad(EventCols cols,
+                                                        const typename ModelTraits<MODEL>::Const* __restrict__ k,
+                                                        long long* __restrict__ counts) {
+  __shared__ int wcount[kThreads / 64];
+  int bad = 0;
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < cols.n; i += stride) {
+    double acc[1] = {0.0};
+    event<MODEL, false>(*k, cols, i, 0u, acc);
+    bad += !isfinite(acc[0]);
+  }
+  for (int off = 32; off >= 1; off >>= 1) bad += __shfl_xor(bad, off, 64);
+  if ((threadIdx.x & 63) == 0) wcount[threadIdx.x >> 6] = bad;
+  __syncthreads();
+  if (threadIdx.x == 0) counts[blockIdx.x] = (long long)wcount[0] + wcount[1] + wcount[2] + wcount[3];
+}
+
+__global__ __launch_bounds__(kThreads) void k_count_bad_angtime(EventCols cols, const AngTimeConst* __restrict__ k,
+                                                                long long* __restrict__ counts) {
+  __shared__ int wcount[kThreads / 64];
+  int bad = 0;
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < cols.n; i += stride) {
+    double acc[1] = {0.0};
+    const double w = cols.w ? cols.w[i] : 1.0;
+    event_angtime<false>(*k, &k->C[0][0], cols.c[0][i], cols.c[1][i], cols.c[2][i], cols.c[3][i], cols.c[4][i],
+                         cols.c[5][i], w, acc, nullptr);
+    bad += !isfinite(acc[0]);
+  }
+  for (int off = 32; off >= 1; off >>= 1) bad += __shfl_xor(bad, off, 64);
+  if ((threadIdx.x & 63) == 0) wcount[threadIdx.x >> 6] = bad;
+  __syncthreads();
+  if (threadIdx.x == 0) counts[blockIdx.x] = (long long)wcount[0] + wcount[1] + wcount[2] + wcount[3];
+}
+
 extern "C" {
+
+ipx_status ipx_count_bad_events(ipx_ctx* ctx, const ipx_dataset* d, const double* theta, int np, int64_t* count) {
+  if (!ctx || !d || !theta || !count) return fail(IPX_EINVAL, "ipx_count_bad_events: NULL argument");
+  const int model = d->model;
+  if (np != kNParams[model])
+    return fail(IPX_EINVAL, "ipx_count_bad_events: model %d takes %d parameters, got %d", model, kNParams[model], np);
+  if (!theta_valid(model, theta)) return fail(IPX_EDOMAIN, "ipx_count_bad_events: parameters outside the domain");
+  *count = 0;
+  if (d->n == 0) return IPX_OK;
+  HIP_TRY(hipSetDevice(ctx->device));
+  const unsigned grid = (unsigned)std::min<int64_t>((d->n + kThreads - 1) / kThreads, 4096);
+  const size_t kb = 256 * 8;  // room for the largest constant block
+  static_assert(sizeof(AngTimeConst) <= 256 * 8 && sizeof(MassTimeConst) <= 256 * 8, "constant block size");
+  char* buf = nullptr;
+  HIP_TRY(hipMalloc(&buf, kb + grid * sizeof(long long)));
+  long long* counts = (long long*)(buf + kb);
+  hipError_t e = hipSuccess;
+  const EventCols cols = cols_of(d);
+  if (model == 1) {
+    const MassHoist h = hoist_mass(theta);
+    e = hipMemcpyAsync(buf, &h.k, sizeof h.k, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) hipLaunchKernelGGL(k_count_bad<1>, dim3(grid), dim3(kThreads), 0, ctx->stream, cols, (const MassConst*)buf, counts);
+  } else if (model == 2) {
+    const MassTimeHoist h = hoist_masstime(theta);
+    e = hipMemcpyAsync(buf, &h.k, sizeof h.k, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) hipLaunchKernelGGL(k_count_bad<2>, dim3(grid), dim3(kThreads), 0, ctx->stream, cols, (const MassTimeConst*)buf, counts);
+  } else {
+    const AngTimeHoist h = hoist_angtime(theta);
+    e = hipMemcpyAsync(buf, &h.k, sizeof h.k, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) hipLaunchKernelGGL(k_count_bad_angtime, dim3(grid), dim3(kThreads), 0, ctx->stream, cols, (const AngTimeConst*)buf, counts);
+  }
+  if (e == hipSuccess) e = hipGetLastError();
+  std::vector<long long> hc(grid);
+  if (e == hipSuccess) e = hipMemcpyAsync(hc.data(), counts, grid * sizeof(long long), hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  const hipError_t ef = hipFree(buf);
+  if (e != hipSuccess) return fail(IPX_EDEVICE, "ipx_count_bad_events: %s", hipGetErrorString(e));
+  if (ef != hipSuccess) return fail(IPX_EDEVICE, "ipx_count_bad_events: hipFree: %s", hipGetErrorString(ef));
+  int64_t total = 0;
+  for (long long c : hc) total += c;
+  *count = total;
+  return IPX_OK;
+}
 
 ipx_status nll_eval(ipx_ctx* ctx, const ipx_dataset* ds, const double* theta, int np, double* nll, void* stream) {
   return run(ctx, ds, theta, np, nll, nullptr, stream);

@@ -55,17 +55,23 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Reduction rows that hold a wave's adjoint block: whole 16-byte units per
+// wave, so that every wave's block starts 16-byte aligned.
+constexpr int kOuterCap = ((kOuterBlock + kRedPitch - 1) / kRedPitch + 1) & ~1;
+
 // Angular model; C is the coefficient table in LDS.  For the gradient, after
 // each round of 64 events a wave forms the 40 coefficient adjoints of those
-// events from its LDS block (lane 4k + j: the sum over the block's columns of
-// f_k tau_j, two interleaved partial sums), so the per-event factors never
-// leave the chip.  Lanes without an event write zeros to the block.  The
-// block is the wave's part of the reduction buffer (CAP x kRedPitch doubles),
-// which the tile reduction reuses afterwards.
+// events from its LDS block, so the per-event factors never leave the chip:
+// lane 8b + g (b = 4h + j) sums f_k tau_j over the events 8g .. 8g + 7 for
+// the five k = 5h .. 5h + 4 (one tau read serves five products), the eight
+// lanes of b add their sums (xor butterfly, the same total in each), and lane
+// 8b + g, g < 5, keeps the running total of coefficient (5h + g, j).  Lanes
+// without an event write zeros to the block.  The block is the wave's part of
+// the reduction buffer, which the tile reduction reuses afterwards.
 template <bool GRAD, bool COH, int CAP>
 __device__ __forceinline__ void tile_angtime(const SegInfo& S, const AngTimeConst& k, const double* C,
                                              int64_t tile, RedBuf<CAP>& red) {
-  static_assert(!GRAD || CAP * kRedPitch >= kOuterBlock, "the adjoint block lives in the reduction buffer");
+  static_assert(!GRAD || (CAP >= kOuterCap && CAP % 2 == 0), "the adjoint block lives in the reduction buffer");
   constexpr int NACC = GRAD ? kAngInner : 1;
   double acc[NACC];
 #pragma unroll
@@ -85,29 +91,36 @@ __device__ __forceinline__ void tile_angtime(const SegInfo& S, const AngTimeCons
       const double w = cl.w ? ldg<COH>(cl.w + base, j) : 1.0;
       event_angtime<GRAD, COH>(k, C, ldg<COH>(cl.c[0] + base, j), ldg<COH>(cl.c[1] + base, j),
                                ldg<COH>(cl.c[2] + base, j), ldg<COH>(cl.c[3] + base, j), ldg<COH>(cl.c[4] + base, j),
-                               ldg<COH>(cl.c[5] + base, j), w, acc, blk + lane);
+                               ldg<COH>(cl.c[5] + base, j), w, acc, blk + outer_col(lane));
     } else if constexpr (GRAD) {
 #pragma unroll
-      for (int r = 0; r < kOuterRows; ++r) blk[r * kOuterPitch + lane] = 0.0;
+      for (int r = 0; r < kOuterRows; ++r) blk[r * kOuterPitch + outer_col(lane)] = 0.0;
     }
     if constexpr (GRAD) {
       wave_lds_sync();
-      if (lane < (unsigned)kAngOuter) {
-        const double* fr = blk + (lane >> 2) * kOuterPitch;
-        const double* tr = blk + (10 + (lane & 3u)) * kOuterPitch;
-        double s0 = 0.0, s1 = 0.0;
-#pragma unroll 8
-        for (int c = 0; c < 64; c += 2) {
-          s0 = fma(fr[c], tr[c], s0);
-          s1 = fma(fr[c + 1], tr[c + 1], s1);
-        }
-        outer += s0 + s1;
+      const unsigned g = lane & 7u, b = lane >> 3;
+      const double* fr = blk + 5 * (b >> 2) * kOuterPitch;
+      const double* tr = blk + (10 + (b & 3u)) * kOuterPitch;
+      double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+      for (unsigned i = 0; i < 8; ++i) {
+        const unsigned c = outer_col(8 * g + i);
+        const double t = tr[c];
+#pragma unroll
+        for (int r = 0; r < 5; ++r) a[r] = fma(fr[r * kOuterPitch + c], t, a[r]);
       }
       wave_lds_sync();
+#pragma unroll
+      for (int off = 1; off < 8; off <<= 1)
+#pragma unroll
+        for (int r = 0; r < 5; ++r) a[r] += __shfl_xor(a[r], off, 64);
+      const double mine = g == 0 ? a[0] : g == 1 ? a[1] : g == 2 ? a[2] : g == 3 ? a[3] : a[4];
+      if (g < 5) outer += mine;
     }
   }
   if constexpr (GRAD) {
-    if (lane < (unsigned)kAngOuter) red.wsum[threadIdx.x >> 6][kAngOuter0 + lane] = outer;
+    const unsigned g = lane & 7u, b = lane >> 3;
+    if (g < 5) red.wsum[threadIdx.x >> 6][kAngOuter0 + 4 * (5 * (b >> 2) + g) + (b & 3u)] = outer;
     tile_store<NACC, COH, CAP, kAccAngTime>(acc, S.partials, tile, S.n_tiles, red);
   } else {
     tile_store<NACC, COH, CAP>(acc, S.partials, tile, S.n_tiles, red);
@@ -136,14 +149,14 @@ __global__ __launch_bounds__(kThreads) void k_nll_batch(const SegInfo* __restric
 // Angular model.
 // The gradient instance is held to 128 VGPRs (4 waves/SIMD; the extra wave
 // shortens the tail of the launch more than the few spilled registers cost);
-// its LDS (adjoint blocks sharing the reduction buffer, ~33 KB) allows 4
+// its LDS (adjoint blocks sharing the reduction buffer, ~35 KB) allows 4
 // workgroups per compute unit.
 template <bool GRAD>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(GRAD ? 4 : 1))) void k_angtime_batch(const SegInfo* __restrict__ segs,
                                                             const TileRef* __restrict__ tiles, int64_t n_tiles,
                                                             const AngTimeConst* __restrict__ consts,
                                                             const unsigned char* __restrict__ active) {
-  constexpr int kCap = GRAD ? (kOuterBlock + kRedPitch - 1) / kRedPitch : 1;
+  constexpr int kCap = GRAD ? kOuterCap : 1;
   __shared__ double sC[40];
   __shared__ RedBuf<kCap> red;
   for (int64_t g = blockIdx.x; g < n_tiles; g += gridDim.x) {

@@ -69,7 +69,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 constexpr int kRedPitch = 65;
 
 template <int CAP>
-struct RedBuf {
+struct alignas(16) RedBuf {
   double rows[kThreads / 64][CAP][kRedPitch];
   double wsum[kThreads / 64][kAccMax];
 };
@@ -339,12 +339,16 @@ constexpr int kAngOuter0 = 12;
 constexpr int kAngOuter = 40;
 
 // Per-wave LDS block of the angular gradient: row k < 10 holds f_k and row
-// 10 + j holds tau_j of the wave's 64 current events (lane = column).  Rows
-// are padded to 66 doubles so that the ten f rows (and the four tau rows) that
-// one read instruction touches fall in distinct banks.
-constexpr int kOuterPitch = 66;
+// 10 + j holds tau_j of the wave's 64 current events, event (lane) e in column
+// outer_col(e).  The block is read by lane 8b + g as the five f rows 5(b/4) ..
+// 5(b/4) + 4 and the tau row b % 4, each over the eight events 8g .. 8g + 7 in
+// pairs (16-byte reads): columns shifted by two after event 31 and a row pitch
+// of 68 doubles put the 16 distinct f pairs of one read instruction in
+// distinct banks.
+constexpr int kOuterPitch = 68;
 constexpr int kOuterRows = 14;
 constexpr int kOuterBlock = kOuterRows * kOuterPitch;
+__device__ __forceinline__ unsigned outer_col(unsigned e) { return e + ((e >> 5) << 1); }
 
 // One event.  C is the coefficient table in LDS (row-major 10 x 4).  For the
 // gradient, writes f_k and tau_j = w T_j / num into the wave's block at column

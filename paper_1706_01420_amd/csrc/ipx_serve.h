@@ -182,7 +182,7 @@ __device__ __forceinline__ void serve_poll(ServeShared* hs, ServeCtl* ctl, Serve
 __device__ __forceinline__ void serve_work(ServeShared* hs, ServeCtl* ctl, ServeDesc* __restrict__ dd,
                                            ServeSlot* __restrict__ st, int idle_limit) {
   __shared__ ServeDesc sd;          // the current item's request
-  __shared__ RedBuf<(kOuterBlock + kRedPitch - 1) / kRedPitch> red;
+  __shared__ RedBuf<kOuterCap> red;
   __shared__ int cmd, cslot, citem;
   __shared__ int last;
   int idle = 0;

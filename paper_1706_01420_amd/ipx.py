@@ -84,6 +84,8 @@ _SIGNATURES = [
     ("ipx_timing_enable", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     ("ipx_timing_read", ctypes.c_int,
      [ctypes.c_void_p, _c_double_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]),
+    ("ipx_count_bad_events", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_void_p, _c_double_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]),
     ("ipx_math_eval", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
       ctypes.c_void_p]),
@@ -446,3 +448,11 @@ def ipx_math_eval(ctx, fn, x, x2=None):
     _check(_lib.ipx_math_eval(ctx, int(fn), n, x.ctypes.data, x2.ctypes.data if x2 is not None else None,
                               y.ctypes.data, y2.ctypes.data if two_out else None))
     return (y, y2) if two_out else y
+
+
+def ipx_count_bad_events(ctx, ds, theta):
+    """Number of events of ds whose contribution w ln P at theta is not finite."""
+    th = np.ascontiguousarray(theta, np.float64)
+    n = ctypes.c_int64()
+    _check(_lib.ipx_count_bad_events(ctx, ds, _dbl(th), th.size, ctypes.byref(n)))
+    return n.value
