@@ -188,15 +188,24 @@ def bench_batched_fits(ipx, ctx, ntoys=512, plain_subset=64, seed=170601424):
     t_gen = time.perf_counter() - t0
     steps = toys.steps_for(3, sizes)
     start = theta[None, :] + 0.5 * steps
+    plan = None
     try:
+        # launch schedule: the autotuner times its candidates on this plan
+        # (the cache is per run, so the timing is always done and reported)
+        plan = ipx.ipx_plan_create(ctx, ds)
         t0 = time.perf_counter()
-        rb = toys.fit_batched(ipx, ctx, 3, ds, start, steps)
+        best, us, rows = ipx.ipx_plan_autotune(ctx, plan, start, grad=True, reps=5)
+        t_tune = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        rb = toys.fit_batched(ipx, ctx, 3, ds, start, steps, plan=plan)
         t_b = time.perf_counter() - t0
         k = plain_subset
         t0 = time.perf_counter()
         rp = toys.fit_plain(ipx, ctx, 3, ds[:k], start[:k], steps[:k])
         t_p = time.perf_counter() - t0
     finally:
+        if plan is not None:
+            ipx.ipx_plan_destroy(plan)
         for d in ds:
             ipx.ipx_dataset_destroy(ctx, d)
     same = bool(np.array_equal(rb["theta"][:k], rp["theta"]))
@@ -206,7 +215,9 @@ def bench_batched_fits(ipx, ctx, ntoys=512, plain_subset=64, seed=170601424):
             "plain_sample": "first %d toys" % k, "speedup": (ntoys / t_b) / (k / t_p),
             "rounds_batched": int(rb["rounds"]), "evals_per_fit_mean": float(rb["evals"].mean()),
             "converged_batched": float(rb["converged"].mean()), "converged_plain": float(rp["converged"].mean()),
-            "same_minima_bitwise": same}
+            "same_minima_bitwise": same,
+            "autotune": {"schedule": best, "us_per_eval": us, "tune_s": t_tune,
+                         "candidates": [[r[0]["workgroups"], r[0]["order"], round(r[1], 1)] for r in rows]}}
 
 
 def bench_served(ipx, ctx, ndatasets=64, nclients=256, nreq=600, seed=170601425):
@@ -252,6 +263,12 @@ def bench_served(ipx, ctx, ndatasets=64, nclients=256, nreq=600, seed=170601425)
                "plain_latency_us_p99": float(np.percentile(lat_plain, 99))}
         srv = ipx.ipx_server_start(ctx, slots=64)
         try:
+            # warm-up (untimed): the first launch of the device loop and every
+            # dataset's first request
+            warm = [ipx.ipx_submit(srv, ds[j], np.array(workloads.THETA_GEN[models[j]]), g)
+                    for j in range(ndatasets) for g in (False, True)]
+            for t in warm:
+                ipx.ipx_wait(srv, t, 60.0)
             for frac in (0.5, 0.8, None):
                 key = "served_at_%.1fx" % frac if frac is not None else "served_saturated"
                 # one thread submits at the paced times, then collects: latencies

@@ -181,6 +181,42 @@ IPX_API ipx_status nll_eval_batch(ipx_ctx *ctx, ipx_plan *plan, const double *th
                                   double *nll, double *grad, void *stream);
 
 /*
+ * Launch schedule of a plan's per-event kernel: how its tiles are handed to
+ * workgroups.  Every tile writes its own partials and the reduction sums them
+ * in tile order, so results are bitwise the same under every schedule; only
+ * the time changes.
+ *   workgroups: 0 = one workgroup per tile (the hardware dispatcher balances
+ *               them); > 0 = that many workgroups, each striding over the
+ *               tile table.
+ *   order:      0 = tiles segment by segment; 1 = interleaved by local tile
+ *               index (the first tile of every segment, then the second, ...).
+ * ipx_plan_set_schedule synchronises the context's stream and drops the plan's
+ * captured graphs (recaptured on the next call).  IPX_EINVAL for negative
+ * workgroups or an unknown order.
+ *
+ * ipx_plan_autotune times the candidate schedules (one workgroup per tile,
+ * 8 and 16 workgroups per compute unit; both orders when the plan has several
+ * segments) over `reps` evaluations each (after 2 untimed ones) at theta
+ * (nb x np host doubles, as for nll_eval_batch; grad != 0 times the gradient
+ * form), keeps the fastest (median wall time per call) on the plan and returns
+ * it in *best (*best_us: its median time, may be NULL).  table/ntable
+ * (optional): on entry *ntable is the capacity of table, on return the number
+ * of candidates written, each with its median time.
+ */
+typedef struct {
+  int workgroups;
+  int order;
+} ipx_schedule;
+typedef struct {
+  ipx_schedule schedule;
+  double us;
+} ipx_tune_entry;
+IPX_API ipx_status ipx_plan_set_schedule(ipx_plan *plan, const ipx_schedule *schedule);
+IPX_API ipx_status ipx_plan_get_schedule(const ipx_plan *plan, ipx_schedule *out);
+IPX_API ipx_status ipx_plan_autotune(ipx_ctx *ctx, ipx_plan *plan, const double *theta, int grad, int reps,
+                                     ipx_schedule *best, double *best_us, ipx_tune_entry *table, int *ntable);
+
+/*
  * Served likelihood: a persistent device loop that evaluates requests from
  * many concurrent clients (minimizers, MCMC chains) over resident datasets
  * (the paper's samplers and fitters each call the likelihood once per

@@ -879,6 +879,7 @@ struct ipx_plan {
   SegInfo* d_segs = nullptr;
   TileRef* d_tiles = nullptr;
   int64_t n_tiles = 0;
+  ipx_schedule sched{0, 0};        // launch schedule (results do not depend on it)
   void* h_consts = nullptr;        // pinned [constants | active flags], written by the host
   unsigned char* h_active = nullptr;
   void* d_consts = nullptr;        // the same block's device address (read by the kernels)
@@ -900,6 +901,26 @@ static void free_plan(struct ipx_plan* p) {
   if (p->h_consts) (void)hipHostFree(p->h_consts);
   if (p->h_out) (void)hipHostFree(p->h_out);
   delete p;
+}
+
+// The plan's table of (segment, local tile) pairs in the order the kernels
+// take them: segment by segment (order 0), or interleaved by local tile index
+// (order 1: the first tile of every segment, then the second, ...; within a
+// segment the tiles run in storage order, the expensive ones first).  A tile's
+// partials, and so every result, do not depend on the order.
+static std::vector<TileRef> tile_table(const ipx_plan* p, int order) {
+  std::vector<TileRef> tiles;
+  int64_t most = 0;
+  for (const ipx_dataset* d : p->ds) most = std::max(most, d->n_tiles);
+  if (order == 0) {
+    for (int j = 0; j < p->nb; ++j)
+      for (int64_t t = 0; t < p->ds[j]->n_tiles; ++t) tiles.push_back(TileRef{j, (int)t});
+  } else {
+    for (int64_t t = 0; t < most; ++t)
+      for (int j = 0; j < p->nb; ++j)
+        if (t < p->ds[j]->n_tiles) tiles.push_back(TileRef{j, (int)t});
+  }
+  return tiles;
 }
 
 static size_t const_size_of(int model) {
@@ -930,7 +951,6 @@ static ipx_status plan_create(ipx_ctx* ctx, int nb, ipx_dataset* const* ds, ipx_
   p->ds.assign(ds, ds + nb);
   p->const_size = const_size_of(model);
   std::vector<SegInfo> segs(nb);
-  std::vector<TileRef> tiles;
   hipError_t e = hipSuccess;
   for (int j = 0; j < nb; ++j) {
     ipx_dataset* d = ds[j];
@@ -938,8 +958,8 @@ static ipx_status plan_create(ipx_ctx* ctx, int nb, ipx_dataset* const* ds, ipx_
     S.cols = cols_of(d);
     S.partials = d->partials;
     S.n_tiles = d->n_tiles;
-    for (int64_t t = 0; t < d->n_tiles; ++t) tiles.push_back(TileRef{j, (int)t});
   }
+  const std::vector<TileRef> tiles = tile_table(p, 0);
   p->n_tiles = (int64_t)tiles.size();
   if (e == hipSuccess) e = hipMalloc(&p->d_segs, nb * sizeof(SegInfo));
   if (e == hipSuccess) e = hipMalloc(&p->d_tiles, std::max<size_t>(1, tiles.size()) * sizeof(TileRef));
@@ -1001,7 +1021,8 @@ static ipx_status timing_end(ipx_ctx* ctx, hipStream_t s) {
 // host memory, so an evaluation needs no copies.
 static ipx_status enqueue_batch(ipx_plan* p, bool grad, hipStream_t s, ipx_ctx* timer) {
   const int nb = p->nb;
-  const unsigned grid = (unsigned)std::max<int64_t>(1, p->n_tiles);
+  const int64_t wg = p->sched.workgroups > 0 ? std::min<int64_t>(p->sched.workgroups, p->n_tiles) : p->n_tiles;
+  const unsigned grid = (unsigned)std::max<int64_t>(1, wg);
   int nacc = 1;
   {
     ipx_status st = timing_begin(timer, s);
@@ -1110,6 +1131,77 @@ extern "C" ipx_status nll_eval_batch(ipx_ctx* ctx, ipx_plan* p, const double* th
     }
   }
   if (result != IPX_OK) return fail(result, "nll_eval_batch: some entries are outside the domain or non-finite");
+  return IPX_OK;
+}
+
+extern "C" ipx_status ipx_plan_set_schedule(ipx_plan* p, const ipx_schedule* sc) {
+  if (!p || !sc) return fail(IPX_EINVAL, "ipx_plan_set_schedule: NULL argument");
+  if (sc->workgroups < 0) return fail(IPX_EINVAL, "ipx_plan_set_schedule: workgroups %d < 0", sc->workgroups);
+  if (sc->order < 0 || sc->order > 1) return fail(IPX_EINVAL, "ipx_plan_set_schedule: unknown order %d", sc->order);
+  HIP_TRY(hipSetDevice(p->ctx->device));
+  HIP_TRY(hipStreamSynchronize(p->ctx->stream));
+  if (sc->order != p->sched.order) {
+    const std::vector<TileRef> tiles = tile_table(p, sc->order);
+    if (!tiles.empty())
+      HIP_TRY(hipMemcpy(p->d_tiles, tiles.data(), tiles.size() * sizeof(TileRef), hipMemcpyHostToDevice));
+  }
+  p->sched = *sc;
+  // the captured graphs hold the old launch dimensions
+  for (int m = 0; m < 2; ++m)
+    if (p->exec[m]) {
+      (void)hipGraphExecDestroy(p->exec[m]);
+      p->exec[m] = nullptr;
+    }
+  return IPX_OK;
+}
+
+extern "C" ipx_status ipx_plan_get_schedule(const ipx_plan* p, ipx_schedule* out) {
+  if (!p || !out) return fail(IPX_EINVAL, "ipx_plan_get_schedule: NULL argument");
+  *out = p->sched;
+  return IPX_OK;
+}
+
+extern "C" ipx_status ipx_plan_autotune(ipx_ctx* ctx, ipx_plan* p, const double* theta, int grad, int reps,
+                                        ipx_schedule* best, double* best_us, ipx_tune_entry* table, int* ntable) {
+  if (!ctx || !p || !theta || !best) return fail(IPX_EINVAL, "ipx_plan_autotune: NULL argument");
+  if (p->ctx != ctx) return fail(IPX_EINVAL, "ipx_plan_autotune: plan belongs to another context");
+  if (reps < 1) return fail(IPX_EINVAL, "ipx_plan_autotune: reps %d < 1", reps);
+  const int np = kNParams[p->model];
+  // candidates: one workgroup per tile, or a grid of 8 / 16 workgroups per
+  // compute unit striding over the tiles; tiles by segment or interleaved
+  const int cu = std::max(1, ctx->n_cu);
+  std::vector<ipx_schedule> cand;
+  for (int order = 0; order <= (p->nb > 1 ? 1 : 0); ++order)
+    for (int wg : {0, 16 * cu, 8 * cu}) cand.push_back(ipx_schedule{wg, order});
+  std::vector<double> nll(p->nb), g(grad ? (size_t)p->nb * np : 0);
+  const ipx_schedule start = p->sched;
+  double best_t = std::numeric_limits<double>::infinity();
+  ipx_schedule best_s = start;
+  int filled = 0;
+  for (const ipx_schedule& c : cand) {
+    ipx_status st = ipx_plan_set_schedule(p, &c);
+    if (st != IPX_OK) return st;
+    std::vector<double> times;
+    for (int r = 0; r < reps + 2; ++r) {
+      const auto t0 = std::chrono::steady_clock::now();
+      st = nll_eval_batch(ctx, p, theta, nullptr, nll.data(), grad ? g.data() : nullptr, nullptr);
+      const auto t1 = std::chrono::steady_clock::now();
+      if (st != IPX_OK && st != IPX_EDOMAIN) return st;
+      if (r >= 2) times.push_back(std::chrono::duration<double, std::micro>(t1 - t0).count());
+    }
+    std::sort(times.begin(), times.end());
+    const double med = times[times.size() / 2];
+    if (table && ntable && filled < *ntable) table[filled++] = ipx_tune_entry{c, med};
+    if (med < best_t) {
+      best_t = med;
+      best_s = c;
+    }
+  }
+  if (ntable) *ntable = filled;
+  ipx_status st = ipx_plan_set_schedule(p, &best_s);
+  if (st != IPX_OK) return st;
+  *best = best_s;
+  if (best_us) *best_us = best_t;
   return IPX_OK;
 }
 

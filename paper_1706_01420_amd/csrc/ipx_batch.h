@@ -88,7 +88,11 @@ __device__ __forceinline__ void tile_angtime(const SegInfo& S, const AngTimeCons
     asm volatile("" ::: "memory");
     if (base + j < S.cols.n) {
       const EventCols& cl = S.cols;
-      const double w = cl.w ? ldg<COH>(cl.w + base, j) : 1.0;
+      double w = cl.w ? ldg<COH>(cl.w + base, j) : 1.0;
+      if constexpr (GRAD) {
+        blk[kOuterWRow * kOuterPitch + outer_col(lane)] = w;
+        w = 0.0;  // the event reads its weight back from the block
+      }
       event_angtime<GRAD, COH>(k, C, ldg<COH>(cl.c[0] + base, j), ldg<COH>(cl.c[1] + base, j),
                                ldg<COH>(cl.c[2] + base, j), ldg<COH>(cl.c[3] + base, j), ldg<COH>(cl.c[4] + base, j),
                                ldg<COH>(cl.c[5] + base, j), w, acc, blk + outer_col(lane));

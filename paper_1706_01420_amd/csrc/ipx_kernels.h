@@ -347,12 +347,15 @@ constexpr int kAngOuter = 40;
 // distinct banks.
 constexpr int kOuterPitch = 68;
 constexpr int kOuterRows = 14;
-constexpr int kOuterBlock = kOuterRows * kOuterPitch;
+constexpr int kOuterWRow = 14;  // one more row: the events' weights until their last use
+constexpr int kOuterBlock = (kOuterRows + 1) * kOuterPitch;
 __device__ __forceinline__ unsigned outer_col(unsigned e) { return e + ((e >> 5) << 1); }
 
 // One event.  C is the coefficient table in LDS (row-major 10 x 4).  For the
 // gradient, writes f_k and tau_j = w T_j / num into the wave's block at column
-// ob (ob = block + lane).
+// ob, and takes the weight from the block's weight row (the caller puts it
+// there when it loads the columns), not from w: read back only where it is
+// first used, it holds no register through the event.
 template <bool GRAD, bool COH = false>
 __device__ __forceinline__ void event_angtime(const AngTimeConst& k, const double* __restrict__ C,
                                               double ck, double cl, double ph, double t, double sig,
@@ -406,6 +409,10 @@ __device__ __forceinline__ void event_angtime(const AngTimeConst& k, const doubl
   const double num = A[0] * T[0] + A[1] * T[1] + A[2] * T[2] + A[3] * T[3];
   const double den = k.D[0] * I[0] + k.D[1] * I[1] + k.D[2] * I[2] + k.D[3] * I[3];
   const double d = m - k.mu;
+  if constexpr (GRAD) {
+    asm volatile("" ::: "memory");
+    w = ob[kOuterWRow * kOuterPitch];
+  }
   acc[0] += w * (log_fast(num * rcp(den)) - d * d * k.q - k.lnNG);
 
   if constexpr (GRAD) {

@@ -84,6 +84,11 @@ _SIGNATURES = [
     ("ipx_timing_enable", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     ("ipx_timing_read", ctypes.c_int,
      [ctypes.c_void_p, _c_double_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]),
+    ("ipx_plan_set_schedule", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("ipx_plan_get_schedule", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("ipx_plan_autotune", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_void_p, _c_double_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, _c_double_p,
+      ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)]),
     ("ipx_count_bad_events", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_void_p, _c_double_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]),
     ("ipx_math_eval", ctypes.c_int,
@@ -304,6 +309,41 @@ def ipx_plan_create(ctx, datasets):
 
 def ipx_plan_destroy(plan):
     _lib.ipx_plan_destroy(plan)
+
+
+class _Schedule(ctypes.Structure):
+    _fields_ = [("workgroups", ctypes.c_int), ("order", ctypes.c_int)]
+
+
+class _TuneEntry(ctypes.Structure):
+    _fields_ = [("schedule", _Schedule), ("us", ctypes.c_double)]
+
+
+def ipx_plan_set_schedule(plan, workgroups=0, order=0):
+    """Launch schedule of the plan's per-event kernel (results do not depend on it)."""
+    sc = _Schedule(int(workgroups), int(order))
+    _check(_lib.ipx_plan_set_schedule(plan, ctypes.byref(sc)))
+
+
+def ipx_plan_get_schedule(plan):
+    sc = _Schedule()
+    _check(_lib.ipx_plan_get_schedule(plan, ctypes.byref(sc)))
+    return {"workgroups": sc.workgroups, "order": sc.order}
+
+
+def ipx_plan_autotune(ctx, plan, theta, grad=True, reps=5):
+    """Time the candidate schedules at theta (nb, np), keep the fastest on the
+    plan; returns (best schedule dict, its median us, [(schedule dict, us), ...])."""
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    best = _Schedule()
+    best_us = ctypes.c_double()
+    table = (_TuneEntry * 16)()
+    n = ctypes.c_int(16)
+    _check(_lib.ipx_plan_autotune(ctx, plan, _dbl(th), 1 if grad else 0, int(reps), ctypes.byref(best),
+                                  ctypes.byref(best_us), table, ctypes.byref(n)))
+    rows = [({"workgroups": table[i].schedule.workgroups, "order": table[i].schedule.order}, table[i].us)
+            for i in range(n.value)]
+    return {"workgroups": best.workgroups, "order": best.order}, best_us.value, rows
 
 
 def nll_eval_batch(ctx, plan, theta, active=None, grad=False, stream=None):

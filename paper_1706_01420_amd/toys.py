@@ -5,8 +5,8 @@ is Poisson-fluctuated on the host: mean mu_j log-uniform in [1e4, 2e5], drawn
 with numpy's Philox generator keyed by the study seed, then N_j ~ Poisson(mu_j).
 Events: toy_generate_batch with key (seed, toy_id = j) for toy j.
 Fits: fit.bfgs either through one nll_eval_batch per round (batched, graph
-replay) or through nll_grad per toy (plain loop); the per-toy arithmetic is the
-same, so both give the same minima.
+replay, launch schedule from the autotuner) or through nll_grad per toy (plain
+loop); the per-toy arithmetic is the same, so both give the same minima.
 """
 import numpy as np
 
@@ -63,12 +63,23 @@ def steps_for(model, sizes, scale=1.0):
     return scale * STEPS[model][None, :] * s[:, None]
 
 
-def fit_batched(ipx, ctx, model, datasets, theta0, steps, **kw):
-    plan = ipx.ipx_plan_create(ctx, datasets)
+def fit_batched(ipx, ctx, model, datasets, theta0, steps, plan=None, tune=False, **kw):
+    """Lockstep BFGS over all datasets through one batched evaluation per
+    round.  plan: an existing plan over `datasets` (kept), else one is made
+    for the fit; tune: give a new plan its launch schedule from the autotune
+    cache, timing the candidates at theta0 when the cache has none."""
+    own = plan is None
+    if own:
+        plan = ipx.ipx_plan_create(ctx, datasets)
     try:
+        if tune:
+            from . import autotune
+            sizes = [ipx.ipx_dataset_size(d) for d in datasets]
+            autotune.tune_plan(ipx, ctx, plan, model, theta0, sizes, grad=True)
         return fit.bfgs(batched_evaluator(ipx, ctx, plan), theta0, steps, **kw)
     finally:
-        ipx.ipx_plan_destroy(plan)
+        if own:
+            ipx.ipx_plan_destroy(plan)
 
 
 def fit_plain(ipx, ctx, model, datasets, theta0, steps, **kw):
