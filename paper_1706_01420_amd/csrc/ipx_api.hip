@@ -19,6 +19,7 @@
 #include <limits>
 #include <string>
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -1246,6 +1247,7 @@ struct ipx_server {
   std::vector<uint64_t> slot_seq;      // last sequence number per slot
   std::vector<ServeReq*> slot_req;     // request in the slot (nullptr = free)
   std::deque<ServeReq*> pending;
+  std::atomic<int> n_pending{0};       // pending.size(), readable without mu
   std::map<uint64_t, ServeReq*> reqs;
   ipx_server_stats stats{};
 };
@@ -1340,12 +1342,19 @@ static bool serve_kernel_live(ipx_server* S) {
   return hipEventQuery(S->kernel_done) == hipErrorNotReady;
 }
 
+// The host side of the server.  Only this thread writes slot_req, so it reads
+// it without the lock: while requests are in flight it polls their completion
+// words lock-free and takes the lock only when a request has completed, one
+// is waiting for a slot, or every 50 us (kernel liveness, stop); clients
+// submitting or waiting are never held off by the polling.
 static void serve_worker(ipx_server* S) {
   (void)hipSetDevice(S->ctx->device);
   const int nslots = S->cfg.slots;
   std::unique_lock<std::mutex> lk(S->mu);
   auto last_progress = std::chrono::steady_clock::now();
+  auto last_pass = last_progress;
   for (;;) {
+    last_pass = std::chrono::steady_clock::now();
     bool progress = false;
     int busy = 0;
     for (int s = 0; s < nslots; ++s) {
@@ -1373,6 +1382,7 @@ static void serve_worker(ipx_server* S) {
       size_t off = 0;
       if (!pool_alloc(S, r->bytes, &off)) break;  // admission by footprint: wait for memory
       S->pending.pop_front();
+      S->n_pending.fetch_sub(1, std::memory_order_relaxed);
       ++S->stats.published;
       r->slot = slot;
       r->off = off;
@@ -1403,6 +1413,7 @@ static void serve_worker(ipx_server* S) {
           }
         for (ServeReq* r : S->pending) serve_finish(S, r, IPX_EDEVICE, nullptr);
         S->pending.clear();
+        S->n_pending.store(0, std::memory_order_relaxed);
         S->kernel_launched = false;
         busy = 0;
         progress = true;
@@ -1423,15 +1434,30 @@ static void serve_worker(ipx_server* S) {
         }
       for (ServeReq* r : S->pending) serve_finish(S, r, IPX_ETIMEOUT, nullptr);
       S->pending.clear();
+      S->n_pending.store(0, std::memory_order_relaxed);
       break;
     }
     if (busy == 0 && S->pending.empty()) {
       S->cv.wait_for(lk, std::chrono::milliseconds(1));  // idle: ipx_submit notifies
     } else {
-      // requests in flight: poll the completion words without a timed sleep
-      // (a timed wait rounds up to the scheduler's timer slack, tens of us)
+      // requests in flight: poll the completion words, without the lock and
+      // without a timed sleep (a timed wait rounds up to the scheduler's timer
+      // slack, tens of us), until something needs the locked pass
       lk.unlock();
-      std::this_thread::yield();
+      for (;;) {
+        std::this_thread::yield();
+        bool done = false;
+        int used = 0;
+        for (int s = 0; s < nslots && !done; ++s) {
+          const ServeReq* r = S->slot_req[s];
+          if (!r) continue;
+          ++used;
+          done = __atomic_load_n(&S->hs->fin[s], __ATOMIC_ACQUIRE) == r->seq;
+        }
+        if (done || (S->n_pending.load(std::memory_order_relaxed) > 0 && used < nslots) ||
+            std::chrono::steady_clock::now() - last_pass > std::chrono::microseconds(50))
+          break;
+      }
       lk.lock();
     }
   }
@@ -1532,6 +1558,7 @@ extern "C" ipx_status ipx_submit(ipx_server* S, const ipx_request* q, uint64_t* 
     return IPX_OK;
   }
   S->pending.push_back(r);
+  S->n_pending.fetch_add(1, std::memory_order_relaxed);
   S->cv.notify_all();
   return IPX_OK;
 }
