@@ -217,7 +217,7 @@ def bench_batched_fits(ipx, ctx, ntoys=512, plain_subset=64, seed=170601424):
             "converged_batched": float(rb["converged"].mean()), "converged_plain": float(rp["converged"].mean()),
             "same_minima_bitwise": same,
             "autotune": {"schedule": best, "us_per_eval": us, "tune_s": t_tune,
-                         "candidates": [[r[0]["workgroups"], r[0]["order"], round(r[1], 1)] for r in rows]}}
+                         "candidates": [[r[0]["workgroups"], r[0]["order"], r[0]["graph"], round(r[1], 1)] for r in rows]}}
 
 
 def bench_served(ipx, ctx, ndatasets=64, nclients=256, nreq=600, seed=170601425):

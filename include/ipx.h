@@ -190,22 +190,26 @@ IPX_API ipx_status nll_eval_batch(ipx_ctx *ctx, ipx_plan *plan, const double *th
  *               tile table.
  *   order:      0 = tiles segment by segment; 1 = interleaved by local tile
  *               index (the first tile of every segment, then the second, ...).
- * ipx_plan_set_schedule synchronises the context's stream and drops the plan's
- * captured graphs (recaptured on the next call).  IPX_EINVAL for negative
- * workgroups or an unknown order.
+ *   graph:      1 = each evaluation replays a HIP graph of its kernels
+ *               (captured on first use); 0 = the kernels are launched directly.
+ * New plans start with {0, 0, 1}.  ipx_plan_set_schedule synchronises the
+ * context's stream and drops the plan's captured graphs (recaptured on the next
+ * call).  IPX_EINVAL for negative workgroups, an unknown order or graph not 0/1.
  *
  * ipx_plan_autotune times the candidate schedules (one workgroup per tile,
  * 8 and 16 workgroups per compute unit; both orders when the plan has several
- * segments) over `reps` evaluations each (after 2 untimed ones) at theta
- * (nb x np host doubles, as for nll_eval_batch; grad != 0 times the gradient
- * form), keeps the fastest (median wall time per call) on the plan and returns
- * it in *best (*best_us: its median time, may be NULL).  table/ntable
- * (optional): on entry *ntable is the capacity of table, on return the number
- * of candidates written, each with its median time.
+ * segments; graph replay and direct launches) at theta (nb x np host doubles,
+ * as for nll_eval_batch; grad != 0 times the gradient form) in `reps` rounds:
+ * in each round every candidate is set and evaluated twice, the second call
+ * timed.  It keeps the candidate with the smallest median wall time per call
+ * on the plan and returns it in *best (*best_us: that median, may be NULL).
+ * table/ntable (optional): on entry *ntable is the capacity of table, on return
+ * the number of candidates written, each with its median time.
  */
 typedef struct {
   int workgroups;
   int order;
+  int graph;
 } ipx_schedule;
 typedef struct {
   ipx_schedule schedule;

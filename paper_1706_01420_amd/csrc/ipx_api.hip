@@ -880,7 +880,7 @@ struct ipx_plan {
   SegInfo* d_segs = nullptr;
   TileRef* d_tiles = nullptr;
   int64_t n_tiles = 0;
-  ipx_schedule sched{0, 0};        // launch schedule (results do not depend on it)
+  ipx_schedule sched{0, 0, 1};     // launch schedule (results do not depend on it)
   void* h_consts = nullptr;        // pinned [constants | active flags], written by the host
   unsigned char* h_active = nullptr;
   void* d_consts = nullptr;        // the same block's device address (read by the kernels)
@@ -1087,7 +1087,10 @@ extern "C" ipx_status nll_eval_batch(ipx_ctx* ctx, ipx_plan* p, const double* th
   if (n_active > 0) {
     hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
     const int mode = grad ? 1 : 0;
-    if (!p->exec[mode]) {
+    if (!p->sched.graph) {
+      ipx_status st = enqueue_batch(p, grad != nullptr, s, nullptr);
+      if (st != IPX_OK) return st;
+    } else if (!p->exec[mode]) {
       hipGraph_t g = nullptr;
       HIP_TRY(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
       ipx_status st = enqueue_batch(p, grad != nullptr, ctx->stream, nullptr);
@@ -1104,7 +1107,7 @@ extern "C" ipx_status nll_eval_batch(ipx_ctx* ctx, ipx_plan* p, const double* th
         return fail(IPX_EDEVICE, "nll_eval_batch: graph instantiation failed: %s", hipGetErrorString(e));
       }
     }
-    HIP_TRY(hipGraphLaunch(p->exec[mode], s));
+    if (p->sched.graph) HIP_TRY(hipGraphLaunch(p->exec[mode], s));
     HIP_TRY(hipStreamSynchronize(s));
   }
   ipx_status result = IPX_OK;
@@ -1139,6 +1142,7 @@ extern "C" ipx_status ipx_plan_set_schedule(ipx_plan* p, const ipx_schedule* sc)
   if (!p || !sc) return fail(IPX_EINVAL, "ipx_plan_set_schedule: NULL argument");
   if (sc->workgroups < 0) return fail(IPX_EINVAL, "ipx_plan_set_schedule: workgroups %d < 0", sc->workgroups);
   if (sc->order < 0 || sc->order > 1) return fail(IPX_EINVAL, "ipx_plan_set_schedule: unknown order %d", sc->order);
+  if (sc->graph < 0 || sc->graph > 1) return fail(IPX_EINVAL, "ipx_plan_set_schedule: graph must be 0 or 1");
   HIP_TRY(hipSetDevice(p->ctx->device));
   HIP_TRY(hipStreamSynchronize(p->ctx->stream));
   if (sc->order != p->sched.order) {
@@ -1169,33 +1173,40 @@ extern "C" ipx_status ipx_plan_autotune(ipx_ctx* ctx, ipx_plan* p, const double*
   if (reps < 1) return fail(IPX_EINVAL, "ipx_plan_autotune: reps %d < 1", reps);
   const int np = kNParams[p->model];
   // candidates: one workgroup per tile, or a grid of 8 / 16 workgroups per
-  // compute unit striding over the tiles; tiles by segment or interleaved
+  // compute unit striding over the tiles; tiles by segment or interleaved;
+  // replayed as a graph or launched directly
   const int cu = std::max(1, ctx->n_cu);
   std::vector<ipx_schedule> cand;
-  for (int order = 0; order <= (p->nb > 1 ? 1 : 0); ++order)
-    for (int wg : {0, 16 * cu, 8 * cu}) cand.push_back(ipx_schedule{wg, order});
+  for (int graph = 1; graph >= 0; --graph)
+    for (int order = 0; order <= (p->nb > 1 ? 1 : 0); ++order)
+      for (int wg : {0, 16 * cu, 8 * cu}) cand.push_back(ipx_schedule{wg, order, graph});
   std::vector<double> nll(p->nb), g(grad ? (size_t)p->nb * np : 0);
-  const ipx_schedule start = p->sched;
-  double best_t = std::numeric_limits<double>::infinity();
-  ipx_schedule best_s = start;
-  int filled = 0;
-  for (const ipx_schedule& c : cand) {
-    ipx_status st = ipx_plan_set_schedule(p, &c);
-    if (st != IPX_OK) return st;
-    std::vector<double> times;
-    for (int r = 0; r < reps + 2; ++r) {
-      const auto t0 = std::chrono::steady_clock::now();
-      st = nll_eval_batch(ctx, p, theta, nullptr, nll.data(), grad ? g.data() : nullptr, nullptr);
-      const auto t1 = std::chrono::steady_clock::now();
-      if (st != IPX_OK && st != IPX_EDOMAIN) return st;
-      if (r >= 2) times.push_back(std::chrono::duration<double, std::micro>(t1 - t0).count());
+  // rounds over all candidates (so that clock drift does not favour one):
+  // in each, a candidate is set, evaluated once untimed (graph capture, first
+  // touch) and once timed; a candidate's time is its median over the rounds
+  std::vector<std::vector<double>> times(cand.size());
+  for (int r = 0; r < reps; ++r)
+    for (size_t c = 0; c < cand.size(); ++c) {
+      ipx_status st = ipx_plan_set_schedule(p, &cand[c]);
+      if (st != IPX_OK) return st;
+      for (int k = 0; k < 2; ++k) {
+        const auto t0 = std::chrono::steady_clock::now();
+        st = nll_eval_batch(ctx, p, theta, nullptr, nll.data(), grad ? g.data() : nullptr, nullptr);
+        const auto t1 = std::chrono::steady_clock::now();
+        if (st != IPX_OK && st != IPX_EDOMAIN) return st;
+        if (k == 1) times[c].push_back(std::chrono::duration<double, std::micro>(t1 - t0).count());
+      }
     }
-    std::sort(times.begin(), times.end());
-    const double med = times[times.size() / 2];
-    if (table && ntable && filled < *ntable) table[filled++] = ipx_tune_entry{c, med};
+  double best_t = std::numeric_limits<double>::infinity();
+  ipx_schedule best_s = p->sched;
+  int filled = 0;
+  for (size_t c = 0; c < cand.size(); ++c) {
+    std::sort(times[c].begin(), times[c].end());
+    const double med = times[c][times[c].size() / 2];
+    if (table && ntable && filled < *ntable) table[filled++] = ipx_tune_entry{cand[c], med};
     if (med < best_t) {
       best_t = med;
-      best_s = c;
+      best_s = cand[c];
     }
   }
   if (ntable) *ntable = filled;

@@ -312,23 +312,23 @@ def ipx_plan_destroy(plan):
 
 
 class _Schedule(ctypes.Structure):
-    _fields_ = [("workgroups", ctypes.c_int), ("order", ctypes.c_int)]
+    _fields_ = [("workgroups", ctypes.c_int), ("order", ctypes.c_int), ("graph", ctypes.c_int)]
 
 
 class _TuneEntry(ctypes.Structure):
     _fields_ = [("schedule", _Schedule), ("us", ctypes.c_double)]
 
 
-def ipx_plan_set_schedule(plan, workgroups=0, order=0):
+def ipx_plan_set_schedule(plan, workgroups=0, order=0, graph=1):
     """Launch schedule of the plan's per-event kernel (results do not depend on it)."""
-    sc = _Schedule(int(workgroups), int(order))
+    sc = _Schedule(int(workgroups), int(order), int(graph))
     _check(_lib.ipx_plan_set_schedule(plan, ctypes.byref(sc)))
 
 
 def ipx_plan_get_schedule(plan):
     sc = _Schedule()
     _check(_lib.ipx_plan_get_schedule(plan, ctypes.byref(sc)))
-    return {"workgroups": sc.workgroups, "order": sc.order}
+    return {"workgroups": sc.workgroups, "order": sc.order, "graph": sc.graph}
 
 
 def ipx_plan_autotune(ctx, plan, theta, grad=True, reps=5):
@@ -341,9 +341,9 @@ def ipx_plan_autotune(ctx, plan, theta, grad=True, reps=5):
     n = ctypes.c_int(16)
     _check(_lib.ipx_plan_autotune(ctx, plan, _dbl(th), 1 if grad else 0, int(reps), ctypes.byref(best),
                                   ctypes.byref(best_us), table, ctypes.byref(n)))
-    rows = [({"workgroups": table[i].schedule.workgroups, "order": table[i].schedule.order}, table[i].us)
-            for i in range(n.value)]
-    return {"workgroups": best.workgroups, "order": best.order}, best_us.value, rows
+    rows = [({"workgroups": table[i].schedule.workgroups, "order": table[i].schedule.order,
+              "graph": table[i].schedule.graph}, table[i].us) for i in range(n.value)]
+    return {"workgroups": best.workgroups, "order": best.order, "graph": best.graph}, best_us.value, rows
 
 
 def nll_eval_batch(ctx, plan, theta, active=None, grad=False, stream=None):
