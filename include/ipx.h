@@ -243,7 +243,10 @@ typedef struct {
   size_t scratch_bytes;    /* scratch budget for admitted requests (0 = 2 GiB) */
   int workgroups;          /* persistent workgroups, one of which polls the host
                               (>= 2; 0 = 2 per compute unit) */
-  int idle_iterations;     /* empty scans before the device loop exits (0 = 20000) */
+  int idle_iterations;     /* consecutive polls that find no new request and no
+                              claimable work before the device loop exits
+                              (0 = 20000, a few tens of ms); it is relaunched
+                              when work arrives */
   int max_pending;         /* waiting requests accepted (0 = unlimited) */
 } ipx_server_cfg;
 typedef struct {
@@ -335,6 +338,18 @@ IPX_API ipx_status ipx_count_bad_events(ipx_ctx *ctx, const ipx_dataset *ds, con
  */
 IPX_API ipx_status ipx_timing_enable(ipx_ctx *ctx, int enable);
 IPX_API ipx_status ipx_timing_read(ipx_ctx *ctx, double *total_ms, int64_t *launches, int reset);
+
+/*
+ * The device's attainable FP64 rate, for reading a kernel's fraction of peak:
+ * every lane of 8 workgroups per compute unit runs eight independent FP64
+ * fused multiply-add chains (2 FLOP each) for 10^5 iterations; the best of
+ * three launches gives *tflops, and the median over the workgroups of their
+ * shader-clock cycles per wall-clock second during that launch gives
+ * *clock_ghz.  Synchronous on the context's stream; allocates and frees its
+ * own device buffers (~4 MB).  IPX_EINVAL for NULL arguments, IPX_EDEVICE for
+ * HIP errors.
+ */
+IPX_API ipx_status ipx_fp64_peak_probe(ipx_ctx *ctx, double *tflops, double *clock_ghz);
 
 /*
  * Self-check of the device elementary functions that the event kernels inline

@@ -375,6 +375,88 @@ ipx_status ipx_timing_read(ipx_ctx* ctx, double* total_ms, int64_t* launches, in
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
+// FP64 ceiling of the device: every lane runs eight independent fused
+// multiply-add chains; each workgroup records its shader-clock cycles
+// (s_memtime) and wall-clock ticks (s_memrealtime) over the loop.
+// ---------------------------------------------------------------------------
+// (b and c arrive as arguments, in scalar registers; the loop body is 32
+// multiply-adds, so the loop's own instructions are a small fraction.)
+__global__ __launch_bounds__(256) void k_fp64_probe(double* __restrict__ out, long long* __restrict__ cyc,
+                                                    long long* __restrict__ wall, int iters, double b, double c) {
+  double x[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) x[u] = threadIdx.x * 1e-3 + u;
+  const long long t0 = clock64();
+  const long long w0 = wall_clock64();
+#pragma unroll 4
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) x[u] = fma(x[u], b, c);
+  }
+  const long long t1 = clock64();
+  const long long w1 = wall_clock64();
+  double s = 0.0;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) s += x[u];
+  out[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = s;
+  if (threadIdx.x == 0) {
+    cyc[blockIdx.x] = t1 - t0;
+    wall[blockIdx.x] = w1 - w0;
+  }
+}
+
+extern "C" ipx_status ipx_fp64_peak_probe(ipx_ctx* ctx, double* tflops, double* clock_ghz) {
+  if (!ctx || !tflops || !clock_ghz) return fail(IPX_EINVAL, "ipx_fp64_peak_probe: NULL argument");
+  HIP_TRY(hipSetDevice(ctx->device));
+  int wrate = 0;
+  HIP_TRY(hipDeviceGetAttribute(&wrate, hipDeviceAttributeWallClockRate, ctx->device));
+  if (wrate <= 0) return fail(IPX_EDEVICE, "ipx_fp64_peak_probe: no wall-clock rate");
+  const int blocks = 8 * std::max(1, ctx->n_cu), threads = 256, iters = 100000;
+  char* buf = nullptr;
+  const size_t nout = (size_t)blocks * threads;
+  HIP_TRY(hipMalloc(&buf, nout * sizeof(double) + 2 * (size_t)blocks * sizeof(long long)));
+  double* out = (double*)buf;
+  long long* cyc = (long long*)(out + nout);
+  long long* wall = cyc + blocks;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  double best = 0.0, best_ghz = 0.0;
+  std::vector<long long> c(blocks), w(blocks);
+  for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+    e = hipEventRecord(e0, ctx->stream);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(k_fp64_probe, dim3(blocks), dim3(threads), 0, ctx->stream, out, cyc, wall, iters, 1.0000001,
+                         1e-9);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess) e = hipMemcpy(c.data(), cyc, blocks * sizeof(long long), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(w.data(), wall, blocks * sizeof(long long), hipMemcpyDeviceToHost);
+    if (e != hipSuccess || ms <= 0.f) break;
+    std::vector<double> f(blocks);
+    for (int i = 0; i < blocks; ++i) f[i] = (double)c[i] * (wrate * 1e3) / std::max<double>(1.0, (double)w[i]) / 1e9;
+    std::sort(f.begin(), f.end());
+    const double tf = 2.0 * 8.0 * iters * (double)nout / (ms * 1e-3) / 1e12;
+    if (tf > best) {
+      best = tf;
+      best_ghz = f[blocks / 2];
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  const hipError_t ef = hipFree(buf);
+  if (e != hipSuccess) return fail(IPX_EDEVICE, "ipx_fp64_peak_probe: %s", hipGetErrorString(e));
+  if (ef != hipSuccess) return fail(IPX_EDEVICE, "ipx_fp64_peak_probe: hipFree: %s", hipGetErrorString(ef));
+  *tflops = best;
+  *clock_ghz = best_ghz;
+  return IPX_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Self-check of the device elementary functions (the same inline functions the
 // event kernels use), element by element.
 // ---------------------------------------------------------------------------
@@ -1405,6 +1487,7 @@ static void serve_worker(ipx_server* S) {
     if (busy > 0 && !serve_kernel_live(S)) {
       // workgroup 0 polls, the others work: the poller leaves once `live` is 0
       hipError_t e = hipMemsetD32Async((hipDeviceptr_t)&S->ctl->live, S->cfg.workgroups - 1, 1, S->stream);
+      if (e == hipSuccess) e = hipMemsetD32Async((hipDeviceptr_t)&S->ctl->quit, 0, 1, S->stream);
       if (e == hipSuccess) {
         hipLaunchKernelGGL(k_serve, dim3((unsigned)S->cfg.workgroups), dim3(kThreads), 0, S->stream, S->hs_dev,
                            S->ctl, S->dd, S->st, nslots, S->cfg.idle_iterations);

@@ -20,9 +20,14 @@
 //           clears its mask bit.  The worker that completes a request's last item sums
 //           every component's tile partials in index order (the order of the
 //           other entry points), writes out[s], then fin[s] = seq.
-//   exit    a worker leaves after `idle_limit` consecutive scans without a
-//           claim, or when stop is set, and counts itself out of `live`; the
-//           poller leaves when no worker is left or the host sets stop.
+//   exit    the poller counts its polls that find neither a new request nor
+//           a claimable item; after `idle_limit` of them in a row it sets quit
+//           and opens no more requests.  Workers leave on quit or stop (after
+//           finishing the item they hold) and count themselves out of `live`;
+//           the poller leaves when no worker is left, or at once on stop.
+//           Workers never leave on their own, so a loop that is running has
+//           all its workgroups (a request arriving after quit waits for the
+//           host to relaunch the loop).
 //
 // Memory ordering without cache-wide fences.  On this GPU every XCD has its
 // own L2, and an agent-scope release or acquire fence writes back or
@@ -74,7 +79,7 @@ struct ServeCtl {                  // device memory
   unsigned long long mask;         // slots that may have unclaimed items
   unsigned long long stop;         // mirror of the host's stop
   unsigned int live;               // worker workgroups still running (set by the host at launch)
-  unsigned int pad;
+  unsigned int quit;               // set by the poller after idle_limit idle polls (0 at launch)
 };
 
 struct ServeShared {               // fine-grained host memory
@@ -139,23 +144,30 @@ __device__ __forceinline__ void serve_open(ServeShared* hs, ServeCtl* ctl, Serve
 }
 
 __device__ __forceinline__ void serve_poll(ServeShared* hs, ServeCtl* ctl, ServeDesc* __restrict__ dd,
-                                           ServeSlot* __restrict__ st, int nslots) {
+                                           ServeSlot* __restrict__ st, int nslots, int idle_limit) {
   __shared__ int pcmd;
   __shared__ unsigned long long pseq[kServeMaxSlots];
   unsigned long long seen = 0;  // last host generation scanned (thread 0)
+  int idle = 0;                 // consecutive idle polls (thread 0)
   for (;;) {
     if (threadIdx.x == 0) {
       const unsigned long long g = load_sys(&hs->gen);
       if (load_sys(&hs->stop)) {
         pcmd = kCmdExit;
         store_dev(&ctl->stop, 1ull);
+      } else if (load_dev(&ctl->quit)) {
+        // draining: no new request is opened; leave with the last worker
+        pcmd = load_dev(&ctl->live) == 0u ? kCmdExit : kCmdIdle;
       } else if (g != seen) {
         // set before the scan: a publication during the scan bumps gen again
         seen = g;
+        idle = 0;
         pcmd = kCmdScan;
-      } else if (load_dev(&ctl->live) == 0u) {
-        pcmd = kCmdExit;
+      } else if (load_dev(&ctl->mask) != 0ull) {
+        idle = 0;
+        pcmd = kCmdIdle;
       } else {
+        if (++idle > idle_limit) store_dev(&ctl->quit, 1u);
         pcmd = kCmdIdle;
       }
       wait_mem();  // the mail words below are read after gen
@@ -180,17 +192,16 @@ __device__ __forceinline__ void serve_poll(ServeShared* hs, ServeCtl* ctl, Serve
 }
 
 __device__ __forceinline__ void serve_work(ServeShared* hs, ServeCtl* ctl, ServeDesc* __restrict__ dd,
-                                           ServeSlot* __restrict__ st, int idle_limit) {
+                                           ServeSlot* __restrict__ st) {
   __shared__ ServeDesc sd;          // the current item's request
   __shared__ RedBuf<kOuterCap> red;
   __shared__ int cmd, cslot, citem;
   __shared__ int last;
-  int idle = 0;
   const unsigned rot = blockIdx.x & 63u;  // spreads the workers' first choice over the slots
   for (;;) {
     if (threadIdx.x == 0) {
       cmd = kCmdIdle;
-      if (load_dev(&ctl->stop)) {
+      if (load_dev(&ctl->stop) || load_dev(&ctl->quit)) {
         cmd = kCmdExit;
       } else {
         unsigned long long m = load_dev(&ctl->mask);
@@ -217,7 +228,7 @@ __device__ __forceinline__ void serve_work(ServeShared* hs, ServeCtl* ctl, Serve
     }
     __syncthreads();
     const int c = cmd;
-    if (c == kCmdExit || (c == kCmdIdle && ++idle > idle_limit)) {
+    if (c == kCmdExit) {
       if (threadIdx.x == 0)
         __hip_atomic_fetch_sub(&ctl->live, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return;
@@ -227,7 +238,6 @@ __device__ __forceinline__ void serve_work(ServeShared* hs, ServeCtl* ctl, Serve
       __syncthreads();
       continue;
     }
-    idle = 0;
     const int s = cslot;
     // the request's descriptor into LDS
     copy_dev_to_lds((unsigned long long*)&sd, (const unsigned long long*)&dd[s],
@@ -274,8 +284,8 @@ __device__ __forceinline__ void serve_work(ServeShared* hs, ServeCtl* ctl, Serve
 // Workgroup 0 polls the host, the others evaluate; grid >= 2 workgroups.
 __global__ __launch_bounds__(kThreads) void k_serve(ServeShared* hs, ServeCtl* ctl, ServeDesc* __restrict__ dd,
                                                     ServeSlot* __restrict__ st, int nslots, int idle_limit) {
-  if (blockIdx.x == 0) serve_poll(hs, ctl, dd, st, nslots);
-  else serve_work(hs, ctl, dd, st, idle_limit);
+  if (blockIdx.x == 0) serve_poll(hs, ctl, dd, st, nslots, idle_limit);
+  else serve_work(hs, ctl, dd, st);
 }
 
 }  // namespace ipx

@@ -91,6 +91,7 @@ _SIGNATURES = [
       ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)]),
     ("ipx_count_bad_events", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_void_p, _c_double_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]),
+    ("ipx_fp64_peak_probe", ctypes.c_int, [ctypes.c_void_p, _c_double_p, _c_double_p]),
     ("ipx_math_eval", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
       ctypes.c_void_p]),
@@ -496,3 +497,11 @@ def ipx_count_bad_events(ctx, ds, theta):
     n = ctypes.c_int64()
     _check(_lib.ipx_count_bad_events(ctx, ds, _dbl(th), th.size, ctypes.byref(n)))
     return n.value
+
+
+def ipx_fp64_peak_probe(ctx):
+    """Attainable FP64 rate of the device: (TFLOP/s of an FMA loop, its median shader clock in GHz)."""
+    tf = ctypes.c_double()
+    ghz = ctypes.c_double()
+    _check(_lib.ipx_fp64_peak_probe(ctx, ctypes.byref(tf), ctypes.byref(ghz)))
+    return tf.value, ghz.value
