@@ -342,7 +342,7 @@ IPX_API ipx_status ipx_timing_read(ipx_ctx *ctx, double *total_ms, int64_t *laun
 /*
  * The device's attainable FP64 rate, for reading a kernel's fraction of peak:
  * every lane of 8 workgroups per compute unit runs eight independent FP64
- * fused multiply-add chains (2 FLOP each) for 10^5 iterations; the best of
+ * fused multiply-add chains (2 FLOP each) for 2 x 10^5 iterations; the best of
  * three launches gives *tflops, and the median over the workgroups of their
  * shader-clock cycles per wall-clock second during that launch gives
  * *clock_ghz.  Synchronous on the context's stream; allocates and frees its

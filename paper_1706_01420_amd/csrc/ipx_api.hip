@@ -379,19 +379,22 @@ ipx_status ipx_timing_read(ipx_ctx* ctx, double* total_ms, int64_t* launches, in
 // multiply-add chains; each workgroup records its shader-clock cycles
 // (s_memtime) and wall-clock ticks (s_memrealtime) over the loop.
 // ---------------------------------------------------------------------------
-// (b and c arrive as arguments, in scalar registers; the loop body is 32
-// multiply-adds, so the loop's own instructions are a small fraction.)
-__global__ __launch_bounds__(256) void k_fp64_probe(double* __restrict__ out, long long* __restrict__ cyc,
-                                                    long long* __restrict__ wall, int iters, double b, double c) {
+// (The factor is a literal, built in scalar registers, and the addend 0.5 an
+// inline constant, so the loop is the multiply-adds and a few scalar
+// instructions; a factor passed as an argument is reloaded from the argument
+// block in every iteration, as the device code is built without machine
+// loop-invariant code motion.)
+__global__ void k_fp64_probe(double* __restrict__ out, long long* __restrict__ cyc, long long* __restrict__ wall,
+                             int iters) {
+  constexpr double b = 1.0000001;
   double x[8];
 #pragma unroll
   for (int u = 0; u < 8; ++u) x[u] = threadIdx.x * 1e-3 + u;
   const long long t0 = clock64();
   const long long w0 = wall_clock64();
-#pragma unroll 4
   for (int i = 0; i < iters; ++i) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) x[u] = fma(x[u], b, c);
+    for (int u = 0; u < 8; ++u) x[u] = fma(x[u], b, 0.5);
   }
   const long long t1 = clock64();
   const long long w1 = wall_clock64();
@@ -411,7 +414,7 @@ extern "C" ipx_status ipx_fp64_peak_probe(ipx_ctx* ctx, double* tflops, double* 
   int wrate = 0;
   HIP_TRY(hipDeviceGetAttribute(&wrate, hipDeviceAttributeWallClockRate, ctx->device));
   if (wrate <= 0) return fail(IPX_EDEVICE, "ipx_fp64_peak_probe: no wall-clock rate");
-  const int blocks = 8 * std::max(1, ctx->n_cu), threads = 256, iters = 100000;
+  const int blocks = 8 * std::max(1, ctx->n_cu), threads = 256, iters = 200000;
   char* buf = nullptr;
   const size_t nout = (size_t)blocks * threads;
   HIP_TRY(hipMalloc(&buf, nout * sizeof(double) + 2 * (size_t)blocks * sizeof(long long)));
@@ -426,8 +429,7 @@ extern "C" ipx_status ipx_fp64_peak_probe(ipx_ctx* ctx, double* tflops, double* 
   for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
     e = hipEventRecord(e0, ctx->stream);
     if (e == hipSuccess) {
-      hipLaunchKernelGGL(k_fp64_probe, dim3(blocks), dim3(threads), 0, ctx->stream, out, cyc, wall, iters, 1.0000001,
-                         1e-9);
+      hipLaunchKernelGGL(k_fp64_probe, dim3(blocks), dim3(threads), 0, ctx->stream, out, cyc, wall, iters);
       e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
