@@ -10,6 +10,7 @@ Prints one JSON line.  Usage:
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
 import argparse
+import gc
 import json
 import os
 import sys
@@ -278,6 +279,11 @@ def bench_served(ipx, ctx, ndatasets=64, nclients=256, nreq=600, seed=170601425)
                 results = []
                 errors = []
                 t_end = time.perf_counter() + 60.0   # the whole rate step is bounded
+                # the arrival process is paced by this Python loop: a collection of
+                # the interpreter's garbage (tens of ms with the objects of the
+                # earlier legs) would stall it and release a burst
+                gc.collect()
+                gc.disable()
                 t0 = time.perf_counter()
                 nxt = t0
                 t_sub = []
@@ -293,6 +299,8 @@ def bench_served(ipx, ctx, ndatasets=64, nclients=256, nreq=600, seed=170601425)
                         results.append(ipx.ipx_wait(srv, t, max(t_end - time.perf_counter(), 0.0)))
                 except ipx.IpxError as e:
                     errors.append(str(e))
+                finally:
+                    gc.enable()
                 # from the first submission to the last completion (submission
                 # time + the library's latency stamp), not to the end of the
                 # collection loop
