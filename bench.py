@@ -411,7 +411,7 @@ def main():
     if args.profile:
         out["calibration"] = calibration_copy()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cols, w, theta, n, 150_000)
+        out["cpu_baseline"] = cpu_baseline(cols, w, theta, n, 3_000_000)
     print(json.dumps(out), flush=True)
 
 
