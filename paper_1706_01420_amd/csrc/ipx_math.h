@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include "cf_depth.h"
+#include "minimax_coeffs.h"
 #include "weideman_coeffs.h"
 
 namespace ipx {
@@ -65,9 +66,10 @@ __device__ __forceinline__ cplx cdiv(cplx a, cplx b) {
 // Elementary functions of the event loops.  The library versions carry
 // double-double steps and argument ranges the likelihood does not need; these
 // take the textbook route (an additive reduction with the constant split in
-// two, Cody and Waite's method, then a Taylor polynomial on the reduced
-// interval) and are within about 2 ulp over their stated domains (measured
-// against correctly rounded values by the math self-check entry point).
+// two, Cody and Waite's method, then a near-minimax polynomial on the reduced
+// interval, with coefficients from gen_minimax.py) and are within about 2 ulp
+// over their stated domains (measured against correctly rounded values by the
+// math self-check entry point).
 // ---------------------------------------------------------------------------
 constexpr double kLn2Hi = 0x1.62e42fefa39efp-1;   // ln 2 rounded to double
 constexpr double kLn2Lo = 0x1.abc9e3b39803fp-56;  // ln 2 - kLn2Hi
@@ -79,24 +81,18 @@ constexpr double kSqrtHalf = 0x1.6a09e667f3bcdp-1;
 
 // e^x.  x = k ln2 + r with k = rint(x / ln2): x - k kLn2Hi is exact under the
 // fused multiply-add (both are multiples of 2^-53 and the difference is below
-// 1/2), so |r| <= ln2/2 up to rounding; e^r from its Taylor polynomial of
-// degree 13 (truncation below 1e-17 relative), then scaled by 2^k.  Arguments
-// are clamped to [-1100, 710] (results 0 and +inf beyond); NaN propagates.
+// 1/2), so |r| <= ln2/2 up to rounding; e^r = 1 + r + r^2/2 + r^3 E(r) with
+// the degree-8 near-minimax E of minimax_coeffs.h (approximation error below
+// 4e-17 relative), then scaled by 2^k.  Arguments are clamped to [-1100, 710]
+// (results 0 and +inf beyond); NaN propagates.
 __device__ __forceinline__ double exp_fast(double x) {
   const double xc = fmin(fmax(x, -1100.0), 710.0);
   const double k = rint(xc * kLog2E);
   const double r = fma(-k, kLn2Lo, fma(-k, kLn2Hi, xc));
-  double p = 1.0 / 6227020800.0;  // 1/13!
-  p = fma(p, r, 1.0 / 479001600.0);
-  p = fma(p, r, 1.0 / 39916800.0);
-  p = fma(p, r, 1.0 / 3628800.0);
-  p = fma(p, r, 1.0 / 362880.0);
-  p = fma(p, r, 1.0 / 40320.0);
-  p = fma(p, r, 1.0 / 5040.0);
-  p = fma(p, r, 1.0 / 720.0);
-  p = fma(p, r, 1.0 / 120.0);
-  p = fma(p, r, 1.0 / 24.0);
-  p = fma(p, r, 1.0 / 6.0);
+  constexpr int n = sizeof(kExpPoly) / sizeof(double);
+  double p = kExpPoly[n - 1];
+#pragma unroll
+  for (int i = n - 2; i >= 0; --i) p = fma(p, r, kExpPoly[i]);
   p = fma(p, r, 0.5);
   p = fma(p, r, 1.0);
   p = fma(p, r, 1.0);
@@ -106,10 +102,10 @@ __device__ __forceinline__ double exp_fast(double x) {
 
 // ln x for x > 0 (positive normal or subnormal; other arguments go to the
 // library log, so 0 gives -inf and negative x NaN).  x = 2^e m with m in
-// [sqrt(1/2), sqrt 2), ln m = 2 atanh(s), s = (m - 1)/(m + 1), |s| <= 0.172,
-// by the odd series of atanh through s^21 (truncation below 1e-18 relative);
-// ln x = e ln2 + ln m with the product e kLn2Hi exact inside the fused
-// multiply-add.
+// [sqrt(1/2), sqrt 2), ln m = 2 atanh(s) = 2s + 2s s^2 L(s^2),
+// s = (m - 1)/(m + 1), |s| <= 0.172, with the degree-6 near-minimax L of
+// minimax_coeffs.h (approximation error below 5e-18 relative); ln x =
+// e ln2 + ln m with the product e kLn2Hi exact inside the fused multiply-add.
 __device__ __forceinline__ double log_fast(double x) {
   if (!__builtin_amdgcn_class(x, 0x180)) return log(x);  // not positive normal/subnormal
   double m = __builtin_amdgcn_frexp_mant(x);  // [1/2, 1)
@@ -120,16 +116,10 @@ __device__ __forceinline__ double log_fast(double x) {
   }
   const double s = (m - 1.0) * rcp(m + 1.0);
   const double s2 = s * s;
-  double q = 1.0 / 21.0;
-  q = fma(q, s2, 1.0 / 19.0);
-  q = fma(q, s2, 1.0 / 17.0);
-  q = fma(q, s2, 1.0 / 15.0);
-  q = fma(q, s2, 1.0 / 13.0);
-  q = fma(q, s2, 1.0 / 11.0);
-  q = fma(q, s2, 1.0 / 9.0);
-  q = fma(q, s2, 1.0 / 7.0);
-  q = fma(q, s2, 1.0 / 5.0);
-  q = fma(q, s2, 1.0 / 3.0);
+  constexpr int n = sizeof(kLogPoly) / sizeof(double);
+  double q = kLogPoly[n - 1];
+#pragma unroll
+  for (int i = n - 2; i >= 0; --i) q = fma(q, s2, kLogPoly[i]);
   const double s2x = 2.0 * s;
   const double lm = fma(s2x * s2, q, s2x);
   const double ef = static_cast<double>(e);
@@ -138,8 +128,10 @@ __device__ __forceinline__ double log_fast(double x) {
 
 // sin x and cos x for |x| <= 2^19 (the library sincos beyond): x = k pi/2 + r
 // with x - k kPio2Hi exact under the fused multiply-add (|r| <= pi/4; absolute
-// error of r below 2e-27), Taylor polynomials of sin through r^17 and of cos
-// through r^16 (truncation below 3e-18 relative), then the quadrant k mod 4.
+// error of r below 2e-27), sin r = r - r^3 S(r^2) and cos r =
+// 1 + r^2 (-1/2 + r^2 C(r^2)) with the degree-5 near-minimax S and C of
+// minimax_coeffs.h (approximation errors below 3e-17 relative), then the
+// quadrant k mod 4.
 __device__ __forceinline__ void sincos_fast(double x, double* sn, double* cs) {
   if (fabs(x) > 0x1p19) {
     sincos(x, sn, cs);
@@ -148,22 +140,15 @@ __device__ __forceinline__ void sincos_fast(double x, double* sn, double* cs) {
   const double k = rint(x * kTwoOverPi);
   const double r = fma(-k, kPio2Lo, fma(-k, kPio2Hi, x));
   const double r2 = r * r;
-  double ps = -1.0 / 355687428096000.0;  // -1/17!
-  ps = fma(ps, r2, 1.0 / 1307674368000.0);
-  ps = fma(ps, r2, -1.0 / 6227020800.0);
-  ps = fma(ps, r2, 1.0 / 39916800.0);
-  ps = fma(ps, r2, -1.0 / 362880.0);
-  ps = fma(ps, r2, 1.0 / 5040.0);
-  ps = fma(ps, r2, -1.0 / 120.0);
-  ps = fma(ps, r2, 1.0 / 6.0);
+  constexpr int ns = sizeof(kSinPoly) / sizeof(double);
+  double ps = kSinPoly[ns - 1];
+#pragma unroll
+  for (int i = ns - 2; i >= 0; --i) ps = fma(ps, r2, kSinPoly[i]);
   const double s = fma(-(r * r2), ps, r);
-  double pc = 1.0 / 20922789888000.0;  // 1/16!
-  pc = fma(pc, r2, -1.0 / 87178291200.0);
-  pc = fma(pc, r2, 1.0 / 479001600.0);
-  pc = fma(pc, r2, -1.0 / 3628800.0);
-  pc = fma(pc, r2, 1.0 / 40320.0);
-  pc = fma(pc, r2, -1.0 / 720.0);
-  pc = fma(pc, r2, 1.0 / 24.0);
+  constexpr int nc = sizeof(kCosPoly) / sizeof(double);
+  double pc = kCosPoly[nc - 1];
+#pragma unroll
+  for (int i = nc - 2; i >= 0; --i) pc = fma(pc, r2, kCosPoly[i]);
   pc = fma(pc, r2, -0.5);
   const double c = fma(r2, pc, 1.0);
   const int q = static_cast<int>(k);
@@ -173,15 +158,15 @@ __device__ __forceinline__ void sincos_fast(double x, double* sn, double* cs) {
   *cs = ((q + 1) & 2) ? -b : b;
 }
 
-// e^x with a short Taylor polynomial when |x| <= 2^-9 (truncation below
-// 1e-22 relative), exp_fast otherwise.
+// e^x with a short Taylor polynomial when |x| <= 2^-9 (through x^5:
+// truncation below 1e-19 relative), exp_fast otherwise.
 __device__ __forceinline__ double exp_small(double x) {
   if (fabs(x) > 0x1p-9) return exp_fast(x);
-  return 1.0 + x * (1.0 + x * (0.5 + x * (1.0 / 6.0 + x * (1.0 / 24.0 + x * (1.0 / 120.0 + x * (1.0 / 720.0))))));
+  return 1.0 + x * (1.0 + x * (0.5 + x * (1.0 / 6.0 + x * (1.0 / 24.0 + x * (1.0 / 120.0)))));
 }
 
-// sin and cos with Taylor polynomials when |x| <= 0.05 (truncation below
-// 1e-21), sincos_fast otherwise.
+// sin and cos with Taylor polynomials when |x| <= 0.05 (sin through x^9, cos
+// through x^8: truncation below 3e-20 relative), sincos_fast otherwise.
 __device__ __forceinline__ void sincos_small(double x, double* s, double* c) {
   if (fabs(x) > 0.05) {
     sincos_fast(x, s, c);
@@ -189,7 +174,7 @@ __device__ __forceinline__ void sincos_small(double x, double* s, double* c) {
   }
   const double x2 = x * x;
   *s = x * (1.0 - x2 * (1.0 / 6.0 - x2 * (1.0 / 120.0 - x2 * (1.0 / 5040.0 - x2 * (1.0 / 362880.0)))));
-  *c = 1.0 - x2 * (0.5 - x2 * (1.0 / 24.0 - x2 * (1.0 / 720.0 - x2 * (1.0 / 40320.0 - x2 * (1.0 / 3628800.0)))));
+  *c = 1.0 - x2 * (0.5 - x2 * (1.0 / 24.0 - x2 * (1.0 / 720.0 - x2 * (1.0 / 40320.0))));
 }
 
 // Depth of the continued fraction for correction terms whose exponent
