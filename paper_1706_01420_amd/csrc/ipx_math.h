@@ -177,20 +177,50 @@ __device__ __forceinline__ void sincos_small(double x, double* s, double* c) {
   *c = 1.0 - x2 * (0.5 - x2 * (1.0 / 24.0 - x2 * (1.0 / 720.0 - x2 * (1.0 / 40320.0))));
 }
 
+// The depth thresholds of cf_depth.h are multiples of 1/8 in [1/8, 32): as
+// integers 8 E_min[K] they pack into one 64-bit word (K = 1 .. 8) and one
+// byte (K = 9), so that the depth search below reads no memory (a table in
+// memory costs a dependent scalar load and its wait per search step).
+constexpr unsigned long long cf_pack_thresholds() {
+  unsigned long long v = 0;
+  for (int i = 0; i < 8; ++i) v |= static_cast<unsigned long long>(kCfDepthE[i] * 8.0) << (8 * i);
+  return v;
+}
+constexpr bool cf_thresholds_pack() {
+  for (int i = 0; i < kCfMaxDepth - 1; ++i) {
+    const double t = kCfDepthE[i] * 8.0;
+    if (!(t >= 1.0 && t <= 255.0 && t == static_cast<double>(static_cast<int>(t)))) return false;
+  }
+  return true;
+}
+static_assert(kCfMaxDepth == 10 && cf_thresholds_pack(), "depth thresholds must be multiples of 1/8 in [1/8, 32)");
+constexpr unsigned long long kCfTh8 = cf_pack_thresholds();
+constexpr int kCfTh9 = static_cast<int>(kCfDepthE[8] * 8.0);
+
 // Depth of the continued fraction for correction terms whose exponent
 // E = (Im z)^2 - (Re z)^2 is at least the given value on every active lane of
 // the wave (the table in cf_depth.h bounds the truncation error of a K-level
 // fraction times the correction's size by 2^-57 of the main term).  The result
-// is the same on all lanes: a binary search with wave votes.
+// is the same on all lanes: a binary search with wave votes on n = trunc(8 E),
+// for which n < 8 E_min[K] exactly when E < E_min[K] (a NaN or negative E
+// asks for the full depth).
 __device__ __forceinline__ int cf_depth_wave(double E) {
+  const int n = static_cast<int>(fmin(fmax(E * 8.0, -1.0), 1e9));
   int lo = 1, hi = kCfMaxDepth;
 #pragma unroll
   for (int it = 0; it < 4; ++it) {
     const int mid = (lo + hi) >> 1;
-    if (__any(E < kCfDepthE[mid - 1])) lo = mid + 1;
+    const int th = mid <= 8 ? static_cast<int>((kCfTh8 >> (8 * (mid - 1))) & 255u) : kCfTh9;
+    if (__any(n < th)) lo = mid + 1;
     else hi = mid;
   }
   return hi;
+}
+
+// d a - c b for complex d, a, b and real c, the products fused (three
+// operations per component).
+__device__ __forceinline__ cplx cmul_sub(cplx d, cplx a, cplx b, double c) {
+  return cplx{fma(d.re, a.re, fma(-d.im, a.im, -c * b.re)), fma(d.re, a.im, fma(d.im, a.re, -c * b.im))};
 }
 
 // One level K of the Jacobi fraction's Wallis recurrences, constants folded at
@@ -204,11 +234,11 @@ __device__ __forceinline__ void cf_level(const cplx& z2, cplx& p, cplx& q, cplx&
   constexpr double c = (2.0 * K - 1.0) * (2.0 * K) * 0.25;
   const cplx d{z2.re - a, z2.im};
   if constexpr (K % 2 == 1) {
-    pm = csub(cmul(d, p), cscale(pm, c));
-    qm = csub(cmul(d, q), cscale(qm, c));
+    pm = cmul_sub(d, p, pm, c);
+    qm = cmul_sub(d, q, qm, c);
   } else {
-    p = csub(cmul(d, pm), cscale(p, c));
-    q = csub(cmul(d, qm), cscale(q, c));
+    p = cmul_sub(d, pm, p, c);
+    q = cmul_sub(d, qm, q, c);
   }
 }
 
@@ -265,9 +295,11 @@ __device__ __forceinline__ cplx faddeeva_cf(cplx z, int depth) {
   cplx pm{1.0, 0.0}, qm{0.0, 0.0};          // P_{-1}, Q_{-1}
   cplx p{z2.re - 0.5, z2.im}, q{1.0, 0.0};  // P_0, Q_0
   cf_levels(z2, p, q, pm, qm, depth);
-  // w = i z Q / (sqrt(pi) P)
+  // w = i z Q / (sqrt(pi) P) = i z Q conj(P) / (sqrt(pi) |P|^2): for
+  // |z| <= 1e6 and at most 10 levels |P|^2 stays far inside the double range
   const cplx izq = cmul(cplx{-z.im, z.re}, q);
-  return cdiv(cscale(izq, kInvSqrtPi), p);
+  const double inv = kInvSqrtPi * rcp(fma(p.re, p.re, p.im * p.im));
+  return cplx{fma(izq.re, p.re, izq.im * p.im) * inv, fma(izq.im, p.re, -izq.re * p.im) * inv};
 }
 
 // Weideman N = 40 rational series, used for |z| < 6 and Im z < 3.4.
