@@ -107,8 +107,9 @@ def parse():
 # HBM traffic of the dominant kernel from the rocprofv3 FETCH_SIZE / WRITE_SIZE
 # runs (scaled by the calibration copy), valid for the kernel sources whose
 # hash is recorded with it; reported as null once those sources change.
-TRAFFIC = {"sources_sha256": "bd8d6cdaf7b8cde7ad59af76e6ff6e0e81c3d47771102ab98b40d47327593af0", "bytes_per_launch": 251426916}
-KERNEL_SOURCES = ["ipx_kernels.h", "ipx_batch.h", "ipx_math.h", "ipx_models.h", "weideman_coeffs.h", "cf_depth.h"]
+TRAFFIC = {"sources_sha256": "a67ab6fa9567d0d4d11928309da956008810dc45d5a129f101d87f86acfb65ea", "bytes_per_launch": 251365916}
+KERNEL_SOURCES = ["ipx_kernels.h", "ipx_batch.h", "ipx_math.h", "ipx_models.h", "weideman_coeffs.h", "cf_depth.h",
+                  "minimax_coeffs.h"]
 
 
 def kernel_sources_hash():
