@@ -112,16 +112,17 @@ __device__ __forceinline__ void tile_store(const double (&acc)[NACC], double* __
 template <bool COH = false>
 __device__ __forceinline__ double reduce_component(const double* __restrict__ p, int64_t nt) {
   double s = 0.0;
-  int64_t i = threadIdx.x;
-  // eight loads in flight, added in the order of the plain loop below
-  for (; i + 7 * kThreads < nt; i += 8 * kThreads) {
-    double v[8];
+  // sixteen loads in flight per round (the ragged end masked), added in index
+  // order: s = ((p[t] + p[t + 256]) + p[t + 512]) + ... for lane t
+  constexpr int kFlight = 16;
+  for (int64_t i0 = threadIdx.x; i0 < nt; i0 += kFlight * kThreads) {
+    double v[kFlight];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = ldg<COH>(p + i + u * kThreads, 0u);
+    for (int u = 0; u < kFlight; ++u) v[u] = i0 + u * kThreads < nt ? ldg<COH>(p + i0 + u * kThreads, 0u) : 0.0;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) s += v[u];
+    for (int u = 0; u < kFlight; ++u)
+      if (i0 + u * kThreads < nt) s += v[u];
   }
-  for (; i < nt; i += kThreads) s += ldg<COH>(p + i, 0u);
   __shared__ double lds[kThreads / 64];
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
