@@ -217,48 +217,57 @@ __device__ __forceinline__ int cf_depth_wave(double E) {
   return hi;
 }
 
-// d a - c b for complex d, a, b and real c, the products fused (three
-// operations per component).
-__device__ __forceinline__ cplx cmul_sub(cplx d, cplx a, cplx b, double c) {
-  return cplx{fma(d.re, a.re, fma(-d.im, a.im, -c * b.re)), fma(d.re, a.im, fma(d.im, a.re, -c * b.im))};
+// One level K of the Jacobi fraction's Wallis recurrences, in scaled form.
+// The plain recurrence is P_K = (z^2 - a_K) P_{K-1} - c_K P_{K-2} with
+// a_K = 2K + 1/2 and c_K = (2K - 1)(2K)/4, the same for Q.  Dividing by
+// alpha_K = c_K alpha_{K-2} (alpha_{-1} = alpha_0 = 1) gives
+// P'_K = d_K P'_{K-1} - P'_{K-2}, d_K = (z^2 - a_K) r_K, r_K = alpha_{K-1} /
+// alpha_K, and the same for Q'; the fraction only needs Q/P = Q'/P', and the
+// scaled level has no product with c_K (one fused operation per real
+// component and step).  The constants are folded at compile time.  The two
+// newest numerators live in p and pm and are updated in place, alternating
+// (odd K writes pm, even K writes p), so that every early exit leaves them in
+// the same registers.
+constexpr double cf_c(int K) { return (2.0 * K - 1.0) * (2.0 * K) * 0.25; }
+constexpr double cf_alpha(int K) { return K <= 0 ? 1.0 : cf_c(K) * cf_alpha(K - 2); }
+
+// d a - b for complex d, a, b (two fused operations per component)
+__device__ __forceinline__ cplx cmul_sub1(cplx d, cplx a, cplx b) {
+  return cplx{fma(d.re, a.re, fma(-d.im, a.im, -b.re)), fma(d.re, a.im, fma(d.im, a.re, -b.im))};
 }
 
-// One level K of the Jacobi fraction's Wallis recurrences, constants folded at
-// compile time: P_K = (z^2 - (2K + 1/2)) P_{K-1} - c_K P_{K-2}, the same for
-// Q, c_K = (2K - 1)(2K)/4.  The two newest numerators live in p and pm and are
-// updated in place, alternating (odd K writes pm, even K writes p), so that
-// every early exit leaves them in the same registers.
 template <int K>
 __device__ __forceinline__ void cf_level(const cplx& z2, cplx& p, cplx& q, cplx& pm, cplx& qm) {
   constexpr double a = 2.0 * K + 0.5;
-  constexpr double c = (2.0 * K - 1.0) * (2.0 * K) * 0.25;
-  const cplx d{z2.re - a, z2.im};
+  constexpr double r = cf_alpha(K - 1) / cf_alpha(K);
+  const cplx d{(z2.re - a) * r, z2.im * r};
   if constexpr (K % 2 == 1) {
-    pm = cmul_sub(d, p, pm, c);
-    qm = cmul_sub(d, q, qm, c);
+    pm = cmul_sub1(d, p, pm);
+    qm = cmul_sub1(d, q, qm);
   } else {
-    p = cmul_sub(d, pm, p, c);
-    q = cmul_sub(d, qm, q, c);
+    p = cmul_sub1(d, pm, p);
+    q = cmul_sub1(d, qm, q);
   }
 }
 
 template <int K>
 __device__ __forceinline__ void cf_level(const double& z2, double& p, double& q, double& pm, double& qm) {
   constexpr double a = 2.0 * K + 0.5;
-  constexpr double c = (2.0 * K - 1.0) * (2.0 * K) * 0.25;
-  const double d = z2 - a;
+  constexpr double r = cf_alpha(K - 1) / cf_alpha(K);
+  const double d = (z2 - a) * r;
   if constexpr (K % 2 == 1) {
-    pm = d * p - c * pm;
-    qm = d * q - c * qm;
+    pm = fma(d, p, -pm);
+    qm = fma(d, q, -qm);
   } else {
-    p = d * pm - c * p;
-    q = d * qm - c * q;
+    p = fma(d, pm, -p);
+    q = fma(d, qm, -q);
   }
 }
 
 // Levels 1 .. depth' with depth' = depth rounded up to odd, at most 10 (depth
 // wave-uniform, 1 .. kCfMaxDepth): uniform branches around pairs of
-// straight-line levels.  On return (p, q) hold P_depth', Q_depth'.
+// straight-line levels.  On return (p, q) hold the scaled numerators P', Q'
+// of level depth'.
 template <typename T>
 __device__ __forceinline__ void cf_levels(const T& z2, T& p, T& q, T& pm, T& qm, int depth) {
   static_assert(kCfMaxDepth == 10, "the level calls below spell out 10 levels");
@@ -295,8 +304,9 @@ __device__ __forceinline__ cplx faddeeva_cf(cplx z, int depth) {
   cplx pm{1.0, 0.0}, qm{0.0, 0.0};          // P_{-1}, Q_{-1}
   cplx p{z2.re - 0.5, z2.im}, q{1.0, 0.0};  // P_0, Q_0
   cf_levels(z2, p, q, pm, qm, depth);
-  // w = i z Q / (sqrt(pi) P) = i z Q conj(P) / (sqrt(pi) |P|^2): for
-  // |z| <= 1e6 and at most 10 levels |P|^2 stays far inside the double range
+  // w = i z Q / (sqrt(pi) P) = i z Q conj(P) / (sqrt(pi) |P|^2) with the
+  // scaled P', Q': for |z| <= 1e6 and at most 10 levels |P'|^2 stays far
+  // inside the double range
   const cplx izq = cmul(cplx{-z.im, z.re}, q);
   const double inv = kInvSqrtPi * rcp(fma(p.re, p.re, p.im * p.im));
   return cplx{fma(izq.re, p.re, izq.im * p.im) * inv, fma(izq.im, p.re, -izq.re * p.im) * inv};
