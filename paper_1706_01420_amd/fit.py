@@ -32,14 +32,32 @@ def fd_hessian(evaluate, theta, steps, active=None):
     return 0.5 * (H + np.transpose(H, (0, 2, 1)))
 
 
-def _inverse_or_diag(H, fallback):
+def _positive_definite(H):
+    """Cholesky succeeds: H (symmetric, finite) is positive definite."""
     try:
-        w = np.linalg.eigvalsh(H)
-        if np.all(np.isfinite(w)) and w.min() > 0:
-            return np.linalg.inv(H)
+        np.linalg.cholesky(H)
+        return True
     except np.linalg.LinAlgError:
-        pass
-    return np.diag(fallback ** 2)
+        return False
+
+
+def _inverse_or_diag(H, fallback):
+    """Inverses of the stacked (nb, np, np) H where positive definite, else
+    diag(fallback^2) per problem.  The stacked LAPACK calls work matrix by
+    matrix, and a stack that fails the test as a whole is decided matrix by
+    matrix, so each problem's result does not depend on nb."""
+    nb, npar, _ = H.shape
+    out = np.empty_like(H)
+    good = np.zeros(nb, bool)
+    cand = np.nonzero(np.all(np.isfinite(H), axis=(1, 2)))[0]
+    if cand.size and not _positive_definite(H[cand]):
+        cand = np.array([j for j in cand if _positive_definite(H[j])], dtype=np.int64)
+    if cand.size:
+        out[cand] = np.linalg.inv(H[cand])
+        good[cand] = True
+    for j in np.nonzero(~good)[0]:
+        out[j] = np.diag(fallback[j] ** 2)
+    return out
 
 
 def bfgs(evaluate, theta0, steps, edm_tol=1e-6, max_rounds=400, c1=1e-4, init_hessian=True):
@@ -59,15 +77,12 @@ def bfgs(evaluate, theta0, steps, edm_tol=1e-6, max_rounds=400, c1=1e-4, init_he
     everyone = np.ones(nb, bool)
     f, g = evaluate(x, everyone)
     evals += 1
-    Hinv = np.empty((nb, npar, npar))
     if init_hessian:
         H = fd_hessian(evaluate, x, steps, everyone)
         evals += 2 * npar
-        for j in range(nb):
-            Hinv[j] = _inverse_or_diag(H[j], steps[j])
+        Hinv = _inverse_or_diag(H, steps)
     else:
-        for j in range(nb):
-            Hinv[j] = np.diag(steps[j] ** 2)
+        Hinv = steps[:, :, None] ** 2 * np.eye(npar)
     converged = np.zeros(nb, bool)
     failed = ~np.isfinite(f)
     edm = 0.5 * np.einsum("ni,nij,nj->n", g, Hinv, g)
@@ -89,22 +104,27 @@ def bfgs(evaluate, theta0, steps, edm_tol=1e-6, max_rounds=400, c1=1e-4, init_he
         # rejected: halve the step; give up after many halvings
         alpha[bad] *= 0.5
         failed |= bad & (alpha < 1e-12)
-        for j in np.nonzero(ok)[0]:
-            s = trial[j] - x[j]
-            y = gt[j] - g[j]
-            sy = s @ y
-            if sy > 1e-300:
-                rho = 1.0 / sy
-                I = np.eye(npar)
-                V = I - rho * np.outer(s, y)
-                Hinv[j] = V @ Hinv[j] @ V.T + rho * np.outer(s, s)
-            x[j], f[j], g[j] = trial[j], ft[j], gt[j]
-            edm[j] = 0.5 * g[j] @ Hinv[j] @ g[j]
-            if edm[j] < edm_tol:
-                converged[j] = True
-            else:
-                p[j] = -Hinv[j] @ g[j]
-                alpha[j] = 1.0
+        # accepted: BFGS update of the inverse Hessian, all such problems at
+        # once (row-wise arithmetic, independent of how many there are)
+        acc = np.nonzero(ok)[0]
+        if acc.size:
+            s = trial[acc] - x[acc]
+            y = gt[acc] - g[acc]
+            sy = np.einsum("ni,ni->n", s, y)
+            upd = sy > 1e-300
+            if upd.any():
+                u = acc[upd]
+                su, yu = s[upd], y[upd]
+                rho = (1.0 / sy[upd])[:, None, None]
+                V = np.eye(npar) - rho * (su[:, :, None] * yu[:, None, :])
+                Hinv[u] = V @ Hinv[u] @ np.transpose(V, (0, 2, 1)) + rho * (su[:, :, None] * su[:, None, :])
+            x[acc], f[acc], g[acc] = trial[acc], ft[acc], gt[acc]
+            edm[acc] = 0.5 * np.einsum("ni,nij,nj->n", g[acc], Hinv[acc], g[acc])
+            done = edm[acc] < edm_tol
+            converged[acc[done]] = True
+            go = acc[~done]
+            p[go] = -np.einsum("nij,nj->ni", Hinv[go], g[go])
+            alpha[go] = 1.0
     return {"theta": x, "f": f, "grad": g, "edm": edm, "converged": converged, "failed": failed,
             "rounds": rounds, "evals": evals}
 

@@ -73,3 +73,23 @@ def test_restrict_holds_fixed_parameters():
         Af1 = A[j][free, 1]
         ref = xstar[j, free] - np.linalg.solve(Aff, Af1 * (c - xstar[j, 1]))
         assert np.allclose(r["theta"][j], ref, atol=1e-6)
+
+
+def test_inverse_or_diag_same_for_stack_and_single():
+    # half positive definite, half indefinite, one with a NaN: the stacked call
+    # decides every problem as a call on that problem alone would
+    rng = np.random.default_rng(3)
+    nb, npar = 64, 6
+    H = rng.standard_normal((nb, npar, npar))
+    H = 0.5 * (H + np.transpose(H, (0, 2, 1)))
+    H[:32] += 8 * np.eye(npar)
+    H[5, 0, 0] = np.nan
+    fb = np.full((nb, npar), 0.1)
+    a = fit._inverse_or_diag(H, fb)
+    b = np.array([fit._inverse_or_diag(H[j:j + 1], fb[j:j + 1])[0] for j in range(nb)])
+    assert np.array_equal(a, b)
+    for j in range(nb):
+        if j < 32 and j != 5:
+            assert np.allclose(a[j] @ H[j], np.eye(npar), atol=1e-10)
+        else:
+            assert np.array_equal(a[j], np.diag(fb[j] ** 2))
