@@ -975,6 +975,7 @@ struct ipx_plan {
   hipGraphExec_t exec[2] = {nullptr, nullptr};  // [eval, grad]
   bool counted = false;            // holds a reference on each dataset
   hipStream_t exec_stream[2] = {nullptr, nullptr};
+  std::vector<AngTimeHoist> h3;    // angular model: per-dataset hoists, kept between calls
 };
 
 static void free_plan(struct ipx_plan* p) {
@@ -1146,10 +1147,10 @@ extern "C" ipx_status nll_eval_batch(ipx_ctx* ctx, ipx_plan* p, const double* th
   const int model = p->model, nb = p->nb, np = kNParams[model];
   std::vector<MassHoist> h1;
   std::vector<MassTimeHoist> h2;
-  std::vector<AngTimeHoist> h3;
   if (model == 1) h1.resize(nb);
   else if (model == 2) h2.resize(nb);
-  else h3.resize(nb);
+  else if ((int)p->h3.size() != nb) p->h3.resize(nb);
+  std::vector<AngTimeHoist>& h3 = p->h3;
   int n_active = 0;
   for (int j = 0; j < nb; ++j) {
     const double* th = theta + (size_t)j * np;
@@ -1166,7 +1167,7 @@ extern "C" ipx_status nll_eval_batch(ipx_ctx* ctx, ipx_plan* p, const double* th
     char* dst = (char*)p->h_consts + (size_t)j * p->const_size;
     if (model == 1) { h1[j] = hoist_mass(th); std::memcpy(dst, &h1[j].k, sizeof(MassConst)); }
     else if (model == 2) { h2[j] = hoist_masstime(th); std::memcpy(dst, &h2[j].k, sizeof(MassTimeConst)); }
-    else { h3[j] = hoist_angtime(th); std::memcpy(dst, &h3[j].k, sizeof(AngTimeConst)); }
+    else { hoist_angtime_values(th, h3[j].k, h3[j].ng); std::memcpy(dst, &h3[j].k, sizeof(AngTimeConst)); }
   }
   if (n_active > 0) {
     hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
@@ -1192,6 +1193,11 @@ extern "C" ipx_status nll_eval_batch(ipx_ctx* ctx, ipx_plan* p, const double* th
       }
     }
     if (p->sched.graph) HIP_TRY(hipGraphLaunch(p->exec[mode], s));
+    // the derivative tables of the angular coefficients serve only the
+    // gradient's Jacobian: computed while the kernels run
+    if (model == 3 && grad)
+      for (int j = 0; j < nb; ++j)
+        if (p->h_active[j]) angtime_derivatives(theta + (size_t)j * np, h3[j]);
     HIP_TRY(hipStreamSynchronize(s));
   }
   ipx_status result = IPX_OK;
@@ -1752,10 +1758,11 @@ static ipx_status run(ipx_ctx* ctx, const ipx_dataset* dc, const double* theta, 
   AngTimeHoist h3;
   if (model == 1) { h1 = hoist_mass(theta); std::memcpy(p->h_consts, &h1.k, sizeof h1.k); }
   else if (model == 2) { h2 = hoist_masstime(theta); std::memcpy(p->h_consts, &h2.k, sizeof h2.k); }
-  else { h3 = hoist_angtime(theta); std::memcpy(p->h_consts, &h3.k, sizeof h3.k); }
+  else { hoist_angtime_values(theta, h3.k, h3.ng); std::memcpy(p->h_consts, &h3.k, sizeof h3.k); }
   p->h_active[0] = 1;
   ipx_status st = enqueue_batch(p, grad != nullptr, s, ctx);
   if (st != IPX_OK) return st;
+  if (model == 3 && grad) angtime_derivatives(theta, h3);  // while the kernels run
   HIP_TRY(hipStreamSynchronize(s));
   const double* a = p->h_out;
   if (!std::isfinite(a[0])) {

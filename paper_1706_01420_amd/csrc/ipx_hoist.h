@@ -29,6 +29,16 @@ template <int N> inline HD<N> hsin(const HD<N>& a) { HD<N> r; r.v = std::sin(a.v
 template <int N> inline HD<N> hcos(const HD<N>& a) { HD<N> r; r.v = std::cos(a.v); const double s = -std::sin(a.v); for (int i = 0; i < N; ++i) r.d[i] = s * a.d[i]; return r; }
 // sqrt with a zero derivative at 0 (the amplitude moduli enter squared there)
 template <int N> inline HD<N> hsqrt(const HD<N>& a) { HD<N> r; r.v = std::sqrt(a.v); const double h = r.v > 0.0 ? 0.5 / r.v : 0.0; for (int i = 0; i < N; ++i) r.d[i] = h * a.d[i]; return r; }
+// The same operations on plain values: code written for HD<N> computes, with
+// double, exactly the values (.v) of its dual-number run.
+inline double hsin(double a) { return std::sin(a); }
+inline double hcos(double a) { return std::cos(a); }
+inline double hsqrt(double a) { return std::sqrt(a); }
+template <typename T> inline T hvar(double x, int j);
+template <> inline double hvar<double>(double x, int) { return x; }
+template <> inline HD<7> hvar<HD<7>>(double x, int j) { return HD<7>::var(x, j); }
+inline double hval(double x) { return x; }
+template <int N> inline double hval(const HD<N>& x) { return x.v; }
 
 // ---------------------------------------------------------------------------
 // Mass normalisations and their derivatives
@@ -169,26 +179,28 @@ constexpr double kXi[10] = {32.0 * M_PI / 9.0, 32.0 * M_PI / 9.0, 32.0 * M_PI / 
 
 using HD7 = HD<7>;  // directions: fL, fperp, Fs, dpa, dpe, dS, phis
 
-// C[k][j] = N_k (a_k, b_k, c_k, d_k), |lambda| = 1, C_SP = 1, delta_0 = 0.
-inline void angular_coefficients(const double* th, HD7 C[10][4]) {
-  const HD7 fL = HD7::var(th[0], 0), fpe = HD7::var(th[1], 1), Fs = HD7::var(th[2], 2);
-  const HD7 dpa = HD7::var(th[3], 3), dpe = HD7::var(th[4], 4), dS = HD7::var(th[5], 5);
-  const HD7 phis = HD7::var(th[9], 6);
-  const HD7 one(1.0), zero(0.0);
-  const HD7 Cc = zero;            // (1 - |lambda|^2)/(1 + |lambda|^2)
-  const HD7 S = -hsin(phis);      // -2|lambda| sin(phis)/(1 + |lambda|^2)
-  const HD7 Dd = -hcos(phis);     // -2|lambda| cos(phis)/(1 + |lambda|^2)
-  const HD7 a0 = (one - Fs) * fL, ape = (one - Fs) * fpe, apa = (one - Fs) * (one - fL - fpe), aS = Fs;
-  const HD7 r0 = hsqrt(a0), rpe = hsqrt(ape), rpa = hsqrt(apa), rS = hsqrt(aS);
-  const HD7 d0 = zero;
-  const HD7 spp = hsin(dpe - dpa), cpp = hcos(dpe - dpa);
-  const HD7 cp0 = hcos(dpa - d0);
-  const HD7 se0 = hsin(dpe - d0), ce0 = hcos(dpe - d0);
-  const HD7 cpS = hcos(dpa - dS), spS = hsin(dpa - dS);
-  const HD7 seS = hsin(dpe - dS);
-  const HD7 c0S = hcos(d0 - dS), s0S = hsin(d0 - dS);
-  const HD7 N[10] = {a0, apa, ape, rpa * rpe, r0 * rpa, r0 * rpe, aS, rS * rpa, rS * rpe, rS * r0};
-  const HD7 abcd[10][4] = {
+// C[k][j] = N_k (a_k, b_k, c_k, d_k), |lambda| = 1, C_SP = 1, delta_0 = 0;
+// T = double for the values, HD7 for values and derivatives.
+template <typename T>
+inline void angular_coefficients(const double* th, T C[10][4]) {
+  const T fL = hvar<T>(th[0], 0), fpe = hvar<T>(th[1], 1), Fs = hvar<T>(th[2], 2);
+  const T dpa = hvar<T>(th[3], 3), dpe = hvar<T>(th[4], 4), dS = hvar<T>(th[5], 5);
+  const T phis = hvar<T>(th[9], 6);
+  const T one(1.0), zero(0.0);
+  const T Cc = zero;            // (1 - |lambda|^2)/(1 + |lambda|^2)
+  const T S = -hsin(phis);      // -2|lambda| sin(phis)/(1 + |lambda|^2)
+  const T Dd = -hcos(phis);     // -2|lambda| cos(phis)/(1 + |lambda|^2)
+  const T a0 = (one - Fs) * fL, ape = (one - Fs) * fpe, apa = (one - Fs) * (one - fL - fpe), aS = Fs;
+  const T r0 = hsqrt(a0), rpe = hsqrt(ape), rpa = hsqrt(apa), rS = hsqrt(aS);
+  const T d0 = zero;
+  const T spp = hsin(dpe - dpa), cpp = hcos(dpe - dpa);
+  const T cp0 = hcos(dpa - d0);
+  const T se0 = hsin(dpe - d0), ce0 = hcos(dpe - d0);
+  const T cpS = hcos(dpa - dS), spS = hsin(dpa - dS);
+  const T seS = hsin(dpe - dS);
+  const T c0S = hcos(d0 - dS), s0S = hsin(d0 - dS);
+  const T N[10] = {a0, apa, ape, rpa * rpe, r0 * rpa, r0 * rpe, aS, rS * rpa, rS * rpe, rS * r0};
+  const T abcd[10][4] = {
       {one, Dd, Cc, -S},
       {one, Dd, Cc, -S},
       {one, -Dd, Cc, S},
@@ -206,18 +218,19 @@ inline void angular_coefficients(const double* th, HD7 C[10][4]) {
 
 struct AngTimeHoist {
   AngTimeConst k;
-  HD7 C[10][4];
+  HD7 C[10][4];   // the coefficient table with its derivatives (for the gradient only)
   GaussNorm ng;
 };
-inline AngTimeHoist hoist_angtime(const double* th) {
-  AngTimeHoist h;
-  angular_coefficients(th, h.C);
-  AngTimeConst& k = h.k;
+// The kernel constants alone (what a launch needs); the derivative table can
+// follow while the kernel runs (angtime_derivatives).
+inline void hoist_angtime_values(const double* th, AngTimeConst& k, GaussNorm& ng) {
+  double Cv[10][4];
+  angular_coefficients(th, Cv);
   for (int j = 0; j < 4; ++j) {
     double s = 0.0;
     for (int kk = 0; kk < 10; ++kk) {
-      k.C[kk][j] = h.C[kk][j].v;
-      s += kXi[kk] * h.C[kk][j].v;
+      k.C[kk][j] = Cv[kk][j];
+      s += kXi[kk] * Cv[kk][j];
     }
     k.D[j] = s;
   }
@@ -243,10 +256,16 @@ inline AngTimeHoist hoist_angtime(const double* th) {
   k.izr = G / den;
   k.izi = DM / den;
   const double mu = th[10], sig = th[11];
-  h.ng = gauss_norm(mu, sig);
+  ng = gauss_norm(mu, sig);
   k.mu = mu;
   k.q = 1.0 / (2.0 * sig * sig);
-  k.lnNG = std::log(h.ng.N);
+  k.lnNG = std::log(ng.N);
+}
+inline void angtime_derivatives(const double* th, AngTimeHoist& h) { angular_coefficients(th, h.C); }
+inline AngTimeHoist hoist_angtime(const double* th) {
+  AngTimeHoist h;
+  hoist_angtime_values(th, h.k, h.ng);
+  angtime_derivatives(th, h);
   return h;
 }
 inline void grad_angtime(const AngTimeHoist& h, const double* th, const double* a, double* g) {
