@@ -1627,6 +1627,17 @@ extern "C" ipx_status ipx_submit(ipx_server* S, const ipx_request* q, uint64_t* 
   std::memcpy(r->theta, q->theta, np * sizeof(double));
   r->t_submit = std::chrono::steady_clock::now();
   r->bytes = request_bytes(d, r->grad);
+  // hoisting outside the server's lock (the derivative table only for a
+  // gradient request)
+  const bool valid = theta_valid(model, r->theta);
+  if (valid) {
+    if (model == 1) r->h1 = hoist_mass(r->theta);
+    else if (model == 2) r->h2 = hoist_masstime(r->theta);
+    else {
+      hoist_angtime_values(r->theta, r->h3.k, r->h3.ng);
+      if (r->grad) angtime_derivatives(r->theta, r->h3);
+    }
+  }
   std::lock_guard<std::mutex> lk(S->mu);
   if (S->stopping) {
     delete r;
@@ -1643,16 +1654,13 @@ extern "C" ipx_status ipx_submit(ipx_server* S, const ipx_request* q, uint64_t* 
   r->ticket = S->next_ticket++;
   S->reqs[r->ticket] = r;
   *ticket = r->ticket;
-  if (!theta_valid(model, r->theta)) {
+  if (!valid) {
     serve_finish(S, r, IPX_EDOMAIN, nullptr);
     r->res.nll = std::numeric_limits<double>::infinity();
     for (int i = 0; i < np; ++i) r->res.grad[i] = std::numeric_limits<double>::quiet_NaN();
     S->cv.notify_all();
     return IPX_OK;
   }
-  if (model == 1) r->h1 = hoist_mass(r->theta);
-  else if (model == 2) r->h2 = hoist_masstime(r->theta);
-  else r->h3 = hoist_angtime(r->theta);
   if (d->n == 0) {  // nothing to evaluate: the empty sum
     double zeros[kAccMax] = {};
     serve_finish(S, r, IPX_OK, zeros);
