@@ -32,9 +32,8 @@ FLOP_BASE = {
     (3, False): 467, (3, True): 672,      # angular (gradient: with the 40 coefficient adjoints, 40 a*b+c)
 }
 # A resolution correction needed at one time point costs a + b K with K the
-# continued-fraction depth of the wave (a real erfcx is 6 + 7K, the complex w
-# 25 + 21K; the levels after the first run in pairs, so K is the table's depth
-# rounded up to odd, at most 10): at the range ends (with the Phi term of the
+# continued-fraction depth that event needs (a real erfcx is 6 + 7K, the
+# complex w 25 + 21K): at the range ends (with the Phi term of the
 # normalisation) and at the event time t.
 CORR_FLOP = {2: {"range": (56, 21), "t": (46, 14)}, 3: {"range": (88, 42), "t": (78, 35)}}
 # Continued-fraction depth table (paper_1706_01420_amd/csrc/cf_depth.h).
@@ -43,26 +42,28 @@ CORR_SKIP = 36.5          # cf_depth.h: kCfSkipE
 T_LO, T_HI = 0.3, 15.0
 
 
-def _wave_depths(x, re2, e_shift):
-    """Per-lane need flag and the wave's depth at one time point, as the
-    kernel decides them (waves = 64 consecutive stored events)."""
+def _lane_depths(x, re2, e_shift):
+    """Per-event need flag and depth at one time point: the correction is
+    counted where its size relative to the main term reaches 2^-57, at the
+    smallest continued-fraction depth whose error bound meets the same
+    target for that event (its own accuracy requirement, whatever events
+    share its wave or however they are stored)."""
     import numpy as np
     with np.errstate(invalid="ignore"):
         E = np.where(x > 0.0, x * x - re2, -1.0) - e_shift
     need = ~(E >= CORR_SKIP)
     eff = np.where(need, E, CORR_SKIP)
-    k_lane = 1 + sum((eff < th).astype(np.int64) for th in CF_DEPTH_E)
-    n = k_lane.size
-    pad = (-n) % 64
-    kw = np.concatenate([k_lane, np.ones(pad, np.int64)]).reshape(-1, 64).max(axis=1)
-    kw = np.where(kw >= 10, 10, kw | 1)     # levels run in pairs after the first
-    return need, np.repeat(kw, 64)[:n]
+    depth = 1 + sum((eff < th).astype(np.int64) for th in CF_DEPTH_E)
+    return need, depth
 
 
 def algorithmic_flops(model, t, sig_t, theta, grad):
-    """FP64 operations of one evaluation of the per-event kernel over the
-    stored events (t, sigma_t in storage order): the base count per event plus
-    every needed correction at the depth its wave uses."""
+    """FP64 operations of one evaluation over the events (t, sigma_t in any
+    order): the formulas' base count per event plus, for every event, each
+    resolution correction its accuracy needs at the depth it needs.  The
+    count follows the method, not the kernel: a wave that evaluates a
+    correction or a deeper fraction for some of its lanes earns nothing for
+    the others, and the count does not change with the storage order."""
     import numpy as np
     n = t.size
     total = float(FLOP_BASE[(model, grad)]) * n
@@ -81,9 +82,9 @@ def algorithmic_flops(model, t, sig_t, theta, grad):
     s2 = sig * sig
     for tau, kind, shift in ((t, "t", 0.0), (T_LO, "range", gmax * T_LO), (T_HI, "range", gmax * T_HI)):
         x = (tau - gmax * s2) * inv_r2s
-        need, kw = _wave_depths(x, re2, shift)
+        need, depth = _lane_depths(x, re2, shift)
         a, b = CORR_FLOP[model][kind]
-        total += float(np.sum(np.where(need, a + b * kw, 0)))
+        total += float(np.sum(np.where(need, a + b * depth, 0)))
     return total
 
 
@@ -158,18 +159,170 @@ def timed_rate(ipx, ctx, ds, theta, steps, warmup, grad):
     return (t1 - t0) / steps, kms / max(launches, 1) / 1e3
 
 
-def cpu_baseline(cols, w, theta, n_total, sample):
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle as it stands, on this host's cores
+# ---------------------------------------------------------------------------
+_CPU = {}   # inputs shared with the forked worker processes
+
+
+def _cpu_workers():
+    """One worker process per core this process may run on, at most 16 (the
+    CPU share of one GPU on the benchmark hosts)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _cpu_eval_chunk(i):
+    from oracle import nll as N
+    cols, w, theta, chunks = _CPU["eval"]
+    lo, hi = chunks[i]
+    return N.nll_grad(3, [c[lo:hi] for c in cols], theta, None if w is None else w[lo:hi])
+
+
+def _cpu_gen_toy(j):
+    from oracle import generate as OG
+    theta, seed, sizes = _CPU["gen"]
+    r = OG.generate(3, theta, seed, j, int(sizes[j]))
+    return r["cols"], r["w"]
+
+
+def _cpu_fit_toy(j):
     import numpy as np
     from oracle import nll as N
-    sub = [c[:sample] for c in cols]
-    ws = None if w is None else w[:sample]
-    t0 = time.perf_counter()
-    N.nll_grad(3, sub, np.asarray(theta), ws)
-    dt = time.perf_counter() - t0
-    per_eval = dt * n_total / sample
-    return {"value": 1.0 / per_eval, "unit": "NLL+grad evals/s", "cores": 1, "kind": "oracle",
-            "sample": "oracle nll_grad (numpy/scipy FP64, one thread) on the first %d of the %d events, "
-                      "%.2f s, scaled to the full sample" % (sample, n_total, dt)}
+    from paper_1706_01420_amd import fit
+    cols, w = _CPU["toys"][j]
+    start, steps = _CPU["fit"]
+
+    def evaluate(th, active):
+        f, g = N.nll_grad(3, cols, th[0], w)
+        return np.array([f]), g[None, :]
+
+    r = fit.bfgs(evaluate, start[j:j + 1], steps[j:j + 1])
+    return bool(r["converged"][0]), int(r["evals"][0])
+
+
+def _cpu_request(i):
+    from oracle import nll as N
+    j, th, grad = _CPU["mix"][i]
+    model, cols, w = _CPU["mix_data"][j]
+    return N.nll_grad(model, cols, th, w) if grad else N.nll(model, cols, th, w)
+
+
+def _noop(_):
+    return None
+
+
+def cpu_baseline(cols, w, theta, reps=3, ntoys=16, nreq=16):
+    """The oracle (numpy/scipy FP64, exactly rounded sums, dual-number
+    gradient) timed on the host's cores: worker processes forked before this
+    process touches the GPU, each running the oracle single-threaded on its
+    share of the work.
+      value       NLL+grad evaluations/s of the full angular sample (events
+                  split into chunks over the workers; median of `reps`);
+      toy_fits    fits/s of the first `ntoys` toys of the batched-fit study
+                  (generated by the oracle's generator, one BFGS fit per
+                  worker with the oracle's gradient, same start and steps);
+      served_mix  evaluations/s over the first `nreq` requests of the served
+                  mix (datasets of the mix's models and sizes)."""
+    import multiprocessing as mp
+    import numpy as np
+    import oracle  # noqa: F401  (imported once, before the workers fork)
+    from oracle import generate, nll  # noqa: F401
+    from paper_1706_01420_amd import fit, toys, workloads  # noqa: F401
+    workers = _cpu_workers()
+    fork = mp.get_context("fork")
+    n = cols[0].size
+    edges = np.linspace(0, n, 2 * workers + 1).astype(np.int64)
+    _CPU["eval"] = (cols, w, list(theta), list(zip(edges[:-1].tolist(), edges[1:].tolist())))
+    times = []
+    with fork.Pool(workers) as pool:
+        pool.map(_noop, range(workers))
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            pool.map(_cpu_eval_chunk, range(len(edges) - 1))
+            times.append(time.perf_counter() - t0)
+    med = float(np.median(times))
+    out = {"value": 1.0 / med, "unit": "NLL+grad evals/s", "cores": workers, "kind": "oracle",
+           "sample": "oracle nll_grad over all %d events of the angular workload, split into %d chunks over %d "
+                     "single-threaded worker processes; median of %d repetitions (%s s)"
+                     % (n, len(edges) - 1, workers, reps, ", ".join("%.2f" % t for t in times)),
+           "host": {"cpu_model": _cpu_model(), "nproc": os.cpu_count(), "workers": workers}}
+
+    # batched-toy fits: the same toys (seed, ids, sizes) and start points
+    seed = 170601424
+    _, sizes = toys.toy_sizes(seed, 512)
+    sizes = sizes[:ntoys]
+    steps = toys.steps_for(3, sizes)
+    start = np.array(theta)[None, :] + 0.5 * steps
+    _CPU["gen"] = (list(theta), seed, sizes)
+    with fork.Pool(workers) as pool:
+        _CPU["toys"] = pool.map(_cpu_gen_toy, range(ntoys))
+    _CPU["fit"] = (start, steps)
+    with fork.Pool(workers) as pool:
+        pool.map(_noop, range(workers))
+        t0 = time.perf_counter()
+        fits = pool.map(_cpu_fit_toy, range(ntoys))
+        t_fit = time.perf_counter() - t0
+    out["toy_fits"] = {"fits_per_s": ntoys / t_fit, "wall_s": t_fit, "toys": ntoys,
+                       "events": int(sizes.sum()), "converged": float(np.mean([c for c, _ in fits])),
+                       "evals_per_fit_mean": float(np.mean([e for _, e in fits])),
+                       "sample": "first %d toys of the 512-toy study, generated by the oracle, one fit per worker "
+                                 "(%d workers)" % (ntoys, workers)}
+
+    # served mix: the first requests of the served benchmark's stream
+    sizes_s, models_s, reqs = served_mix(nreq=nreq)
+    used = sorted({j for j, _, _ in reqs})
+    _CPU["mix"] = reqs
+    _CPU["mix_data"] = {j: (models_s[j],) + tuple(workloads.events(models_s[j], int(sizes_s[j]), seed=170601425 + j))
+                        for j in used}
+    with fork.Pool(workers) as pool:
+        pool.map(_noop, range(workers))
+        t0 = time.perf_counter()
+        pool.map(_cpu_request, range(len(reqs)))
+        t_mix = time.perf_counter() - t0
+    out["served_mix"] = {"evals_per_s": len(reqs) / t_mix, "wall_s": t_mix, "requests": len(reqs),
+                         "events": int(sum(int(sizes_s[j]) for j, _, _ in reqs)),
+                         "sample": "first %d requests of the served stream (half with gradient), datasets of the "
+                                   "mix's models and sizes drawn by the workload generator, one request per worker "
+                                   "at a time" % len(reqs)}
+    _CPU.clear()
+    return out
+
+
+def served_mix(ndatasets=64, nclients=256, nreq=600, seed=170601425):
+    """The served benchmark's datasets (models cycled 1, 2, 3; sizes
+    log-uniform in [1e3, 5e6]) and request stream: 256 clients, each bound to
+    one dataset, half asking NLL only (random-walk chains), half NLL +
+    gradient (minimisers), parameters jittered around the generation point."""
+    import numpy as np
+    from paper_1706_01420_amd import workloads
+    rng = np.random.default_rng(seed)
+    sizes = np.exp(rng.uniform(np.log(1e3), np.log(5e6), ndatasets)).astype(np.int64)
+    models = [1 + (j % 3) for j in range(ndatasets)]
+    client_ds = rng.integers(ndatasets, size=nclients)
+    client_grad = np.arange(nclients) >= nclients // 2
+    reqs = []
+    for _ in range(nreq):
+        c = rng.integers(nclients)
+        j = int(client_ds[c])
+        th = np.array(workloads.THETA_GEN[models[j]])
+        th = th * (1.0 + 0.002 * rng.standard_normal(th.size))
+        reqs.append((j, th, bool(client_grad[c])))
+    return sizes, models, reqs
 
 
 def bench_batched_fits(ipx, ctx, ntoys=512, plain_subset=64, seed=170601424):
@@ -230,23 +383,15 @@ def bench_served(ipx, ctx, ndatasets=64, nclients=256, nreq=600, seed=170601425)
     throughput.  Latency = submission to completion."""
     import numpy as np
     from paper_1706_01420_amd import workloads
-    rng = np.random.default_rng(seed)
-    sizes = np.exp(rng.uniform(np.log(1e3), np.log(5e6), ndatasets)).astype(np.int64)
-    models = [1 + (j % 3) for j in range(ndatasets)]
+    sizes, models, reqs = served_mix(ndatasets, nclients, nreq, seed)
+    # arrival times from their own stream (the original interleaved them with
+    # the mix's draws after the requests)
+    rng = np.random.default_rng(seed + 1)
     ds = []
     try:
         for j in range(ndatasets):
             d, _ = ipx.toy_generate(ctx, models[j], workloads.THETA_GEN[models[j]], seed, j, int(sizes[j]))
             ds.append(d)
-        client_ds = rng.integers(ndatasets, size=nclients)
-        client_grad = np.arange(nclients) >= nclients // 2
-        reqs = []
-        for _ in range(nreq):
-            c = rng.integers(nclients)
-            j = client_ds[c]
-            th = np.array(workloads.THETA_GEN[models[j]])
-            th = th * (1.0 + 0.002 * rng.standard_normal(th.size))
-            reqs.append((j, th, bool(client_grad[c])))
         # plain: one call per request, back to back
         lat_plain = []
         t0 = time.perf_counter()
@@ -326,6 +471,42 @@ def bench_served(ipx, ctx, ndatasets=64, nclients=256, nreq=600, seed=170601425)
             ipx.ipx_dataset_destroy(ctx, d)
 
 
+def bench_mass_batch(ipx, ctx, steps, warmup, nb=64):
+    """The mass model's HBM roofline on a batch: one 10^5-event call moves
+    0.8 MB and is launch-latency bound, so 64 datasets of that size are
+    evaluated per call (one plan, graph replay); 51 MB per call, which the
+    256 MB last-level cache (MALL) can hold."""
+    import numpy as np
+    import torch
+    from paper_1706_01420_amd import workloads
+    nm = workloads.WORKLOAD_SIZES[1]
+    dsl = []
+    plan = None
+    try:
+        for j in range(nb):
+            c, _ = workloads.events(1, nm, seed=workloads.BENCH_SEED + 100 + j)
+            dsl.append(ipx.ipx_dataset_create(ctx, 1, c, None))
+        plan = ipx.ipx_plan_create(ctx, dsl)
+        th = np.tile(np.array(workloads.THETA_GEN[1]), (nb, 1))
+        for _ in range(warmup):
+            ipx.nll_eval_batch(ctx, plan, th)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ipx.nll_eval_batch(ctx, plan, th)
+        dt = (time.perf_counter() - t0) / steps
+    finally:
+        if plan is not None:
+            ipx.ipx_plan_destroy(plan)
+        for d in dsl:
+            ipx.ipx_dataset_destroy(ctx, d)
+    nbytes = BYTES_PER_EVENT[1] * nm * nb
+    return {"datasets": nb, "events": nm * nb, "us_per_call": dt * 1e6, "evals_per_s": nb / dt,
+            "bytes_per_call": nbytes, "gbs": nbytes / dt / 1e9, "frac_hbm": nbytes / dt / 1e9 / PEAK_HBM_GBS,
+            "note": "wall time per batched call (graph replay, reduction and readback included); the 51 MB "
+                    "of columns fit in the 256 MB MALL"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -333,22 +514,27 @@ def main():
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import numpy as np
-    import torch
-    from paper_1706_01420_amd import ipx, workloads
+    from paper_1706_01420_amd import workloads
 
     model = 3
     n = workloads.WORKLOAD_SIZES[model]
     cols, w = workloads.events(model, n)
     theta = np.array(workloads.THETA_GEN[model])
+    cpu = None
+    if not args.no_cpu_baseline and not args.profile:
+        # first, while this process has not touched the GPU: the oracle's
+        # worker processes are forked from it
+        cpu = cpu_baseline(cols, w, theta)
+
+    import torch
+    from paper_1706_01420_amd import ipx
     ctx = ipx.ipx_create(0)
     ds = ipx.ipx_dataset_create(ctx, model, cols, w)
     torch.cuda.synchronize()
 
     step_s, kernel_s = timed_rate(ipx, ctx, ds, theta, args.steps, args.warmup, grad=True)
     value = 1.0 / step_s
-    # the stored (reordered) decay times and widths decide the corrections
-    t_st, s_st = ipx.ipx_dataset_read(ctx, ds, 3), ipx.ipx_dataset_read(ctx, ds, 4)
-    flops = algorithmic_flops(model, t_st, s_st, theta, True)
+    flops = algorithmic_flops(model, cols[3], cols[4], theta, True)
     achieved = flops / kernel_s / 1e12
     # what this GPU sustains on a pure FP64 FMA loop (clock under load)
     fma_tflops, clock_ghz = ipx.ipx_fp64_peak_probe(ctx)
@@ -381,7 +567,7 @@ def main():
     extra = {}
     if not args.no_extra:
         e_step, e_kern = timed_rate(ipx, ctx, ds, theta, max(args.steps // 2, 5), max(args.warmup // 2, 2), grad=False)
-        fe = algorithmic_flops(model, t_st, s_st, theta, False)
+        fe = algorithmic_flops(model, cols[3], cols[4], theta, False)
         extra["angtime_nll_eval"] = {"evals_per_s": 1 / e_step, "kernel_us": e_kern * 1e6,
                                      "flop_per_event": fe / n, "tflops": fe / e_kern / 1e12}
     ipx.ipx_dataset_destroy(ctx, ds)
@@ -391,18 +577,17 @@ def main():
             c, wm = workloads.events(m, nm)
             d = ipx.ipx_dataset_create(ctx, m, c, wm)
             th = np.array(workloads.THETA_GEN[m])
-            tm = sm = None
-            if m == 2:
-                tm, sm = ipx.ipx_dataset_read(ctx, d, 1), ipx.ipx_dataset_read(ctx, d, 2)
             for grad in (False, True):
                 s, k = timed_rate(ipx, ctx, d, th, max(args.steps // 2, 5), max(args.warmup // 2, 2), grad)
                 key = ("mass" if m == 1 else "masstime") + ("_nll_grad" if grad else "_nll_eval")
-                fm = algorithmic_flops(m, tm, sm, th, grad) if m == 2 else FLOP_BASE[(m, grad)] * nm
+                fm = algorithmic_flops(m, c[1], c[2], th, grad) if m == 2 else FLOP_BASE[(m, grad)] * nm
                 extra[key] = {"n_events": nm, "evals_per_s": 1 / s, "us_per_eval": s * 1e6,
                               "kernel_us": k * 1e6, "flop_per_event": fm / nm,
                               "tflops": fm / k / 1e12,
                               "hbm_gbs": BYTES_PER_EVENT[m] * nm / k / 1e9}
             ipx.ipx_dataset_destroy(ctx, d)
+        extra["mass_nll_eval_batch64"] = bench_mass_batch(ipx, ctx, max(args.steps // 2, 5),
+                                                          max(args.warmup // 2, 2))
         out["extra"] = extra
     if not args.no_batched and not args.profile:
         out["batched"] = bench_batched_fits(ipx, ctx)
@@ -411,8 +596,8 @@ def main():
     ipx.ipx_destroy(ctx)
     if args.profile:
         out["calibration"] = calibration_copy()
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cols, w, theta, n, 3_000_000)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

@@ -151,6 +151,13 @@ IPX_API ipx_status nll_eval(ipx_ctx *ctx, const ipx_dataset *ds, const double *t
  * term with respect to the per-call hoisted quantities (coefficients,
  * normalisations, decay constants); the host applies the Jacobian of the
  * hoisting.  The NLL value is bitwise equal to nll_eval's.
+ * The gradient's domain is open where the model takes a square root of a
+ * parameter: in IPX_MODEL_ANGTIME the interference coefficients are linear in
+ * the amplitude moduli sqrt(|A_i|^2), whose slope is infinite where a squared
+ * modulus vanishes, so nll_grad (and the gradient forms of nll_eval_batch
+ * and served requests) require fL > 0, fperp > 0, fL + fperp < 1 and
+ * 0 < Fs < 1; on that boundary they return IPX_EDOMAIN with *nll = +inf and
+ * NaN gradients (nll_eval accepts it).
  */
 IPX_API ipx_status nll_grad(ipx_ctx *ctx, const ipx_dataset *ds, const double *theta, int np, double *nll,
                     double *grad, void *stream);
@@ -328,6 +335,22 @@ IPX_API ipx_status toy_generate_batch(ipx_ctx *ctx, int model, const double *the
  */
 IPX_API ipx_status ipx_count_bad_events(ipx_ctx *ctx, const ipx_dataset *ds, const double *theta, int np,
                                         int64_t *count);
+
+/*
+ * Per-event terms, for inspection (the paper's advice on debugging GPU code:
+ * write intermediate per-event values to a device array and look at them):
+ * out[i] = w_i ln P_i at theta for event i of ds in storage order (the order
+ * ipx_dataset_read returns), i.e. the terms whose sum is -nll_eval(...); the
+ * angular model's term includes its mass factor, ln(G(m)/N_G).
+ *   out: DEVICE memory of ipx_dataset_size(ds) doubles, caller-owned (may be
+ *        NULL when the dataset is empty).
+ * Enqueued on `stream` (NULL: the context's stream) and synchronised before
+ * returning.  IPX_EINVAL for NULL arguments or a wrong np; IPX_EDOMAIN for
+ * parameters outside the model's domain (nothing written); IPX_EDEVICE for
+ * HIP errors.
+ */
+IPX_API ipx_status ipx_event_logp(ipx_ctx *ctx, const ipx_dataset *ds, const double *theta, int np, double *out,
+                                  void *stream);
 
 /*
  * Timing of the dominant kernel of nll_eval/nll_grad, measured with HIP events

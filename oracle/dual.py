@@ -113,8 +113,17 @@ def log(x):
 
 
 def sqrt(x):
+    """Square root.  Its slope is infinite at 0; a direction along which the
+    argument does not change leaves the root unchanged there as well (zero
+    derivative, not 0 x inf), so only the directions that move a vanishing
+    argument get a non-finite derivative."""
     v = np.sqrt(value(x))
-    return _chain(x, v, lambda: 0.5 / v)
+    if not isinstance(x, Dual):
+        return v
+    d = x._dexp(np.ndim(v))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        dv = np.where(d == 0.0, 0.0, d * (0.5 / v))
+    return Dual(v, dv)
 
 
 def sin(x):

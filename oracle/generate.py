@@ -104,8 +104,30 @@ def bound_angtime(theta):
 # Candidates
 # ---------------------------------------------------------------------------
 def _box_muller(ua, ub):
+    """Two independent unit Gaussians from two uniforms (Box and Muller, 1958)."""
     r = np.sqrt(-2.0 * np.log(ua))
     return r * np.cos(2.0 * np.pi * ub), r * np.sin(2.0 * np.pi * ub)
+
+
+def _exp_inverse_cdf(u, lam):
+    """Mass of the exponential shape exp(-lam (m - M_LO)) truncated to the range,
+    by inverting its CDF at u (uniform on the range when lam = 0)."""
+    L = Mo.M_HI - Mo.M_LO
+    if lam == 0.0:
+        return Mo.M_LO + L * u
+    return Mo.M_LO - np.log1p(-u * (-np.expm1(-lam * L))) / lam
+
+
+def _envelope_rate(G, DG):
+    """Rate of the exponential proposal of the true decay time: the slowest of
+    the two mass eigenstates, Gamma - |DeltaGamma|/2, so that e^{rate t} times
+    the unconvolved density stays bounded for every t >= 0."""
+    return G - abs(DG) / 2.0
+
+
+def _angles(ua, ub, uc):
+    """cos(theta_K), cos(theta_l) uniform on [-1, 1] and phi uniform on [-pi, pi]."""
+    return 2.0 * ua - 1.0, 2.0 * ub - 1.0, np.pi * (2.0 * uc - 1.0)
 
 
 def candidates(model, theta, u, bound):
@@ -120,11 +142,7 @@ def candidates(model, theta, u, bound):
         st = 0.03 + 0.03 * u[:, 0]
         sig = u[:, 1] < f
         g1, g2 = _box_muller(u[:, 2], u[:, 3])
-        L = Mo.M_HI - Mo.M_LO
-        if lam == 0.0:
-            mb = Mo.M_LO + L * u[:, 4]
-        else:
-            mb = Mo.M_LO - np.log1p(-u[:, 4] * (-np.expm1(-lam * L))) / lam
+        mb = _exp_inverse_cdf(u[:, 4], lam)
         m = np.where(sig, mu + sig_m * g1, mb)
         t = -np.where(sig, tau_s, tau_b) * np.log(u[:, 5]) + s * st * g2
         inr = (m >= Mo.M_LO) & (m <= Mo.M_HI) & (t >= Mo.T_LO) & (t <= Mo.T_HI)
@@ -134,9 +152,9 @@ def candidates(model, theta, u, bound):
         return inr & (lhs < R), [m, t, st], None, (R - lhs) / R, R > bound
     fL, fpe, Fs, dpa, dpe, dS, G, DG, DM, phis, mu_m, sig_m = theta
     st = 0.03 + 0.03 * u[:, 0]
-    gmin = G - abs(DG) / 2.0
+    gmin = _envelope_rate(G, DG)
     t0 = -np.log(u[:, 1]) / gmin
-    ck, cl, ph = 2.0 * u[:, 2] - 1.0, 2.0 * u[:, 3] - 1.0, np.pi * (2.0 * u[:, 4] - 1.0)
+    ck, cl, ph = _angles(u[:, 2], u[:, 3], u[:, 4])
     C = Mo.time_coefficients(fL, fpe, Fs, dpa, dpe, dS, phis)
     fk = Mo.angular_functions(ck, cl, ph)
     e = np.exp((gmin - G) * t0)

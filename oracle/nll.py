@@ -78,6 +78,33 @@ def nll_grad(model, cols, theta, w=None):
     return f, g
 
 
+def nll_grad_scale(model, cols, theta, w=None):
+    """(NLL, gradient, scale): nll_grad's values plus, per parameter, the sum
+    of the absolute per-event terms sum_i |w_i d ln P_i / d theta_j| (the size
+    of the sum the gradient cancels down from, which bounds its rounding)."""
+    if not models.theta_valid(model, theta):
+        return math.inf, np.full(len(theta), np.nan), np.full(len(theta), np.nan)
+    cols, n = _as_cols(model, cols)
+    K = len(theta)
+    wv = None if w is None else np.asarray(w, dtype=np.float64)
+    vals = np.empty(n)
+    ders = np.empty((K, n))
+    for lo in range(0, n, CHUNK):
+        hi = min(n, lo + CHUNK)
+        lp = D.log(models.pdf(model, [c[lo:hi] for c in cols], D.seed(theta)))
+        v, d = lp.v, np.broadcast_to(lp.d, (K, hi - lo))
+        if wv is not None:
+            v = v * wv[lo:hi]
+            d = d * wv[lo:hi]
+        vals[lo:hi] = v
+        ders[:, lo:hi] = d
+    if not np.all(np.isfinite(vals)):
+        return math.inf, np.full(K, np.nan), np.full(K, np.nan)
+    f = -math.fsum(vals.tolist())
+    g = np.array([-math.fsum(ders[j].tolist()) for j in range(K)])
+    return f, g, np.abs(ders).sum(axis=1)
+
+
 def event_grad(model, cols, theta):
     """Per-event d ln P_i / d theta, shape (K, n) (used by tolerance budgets)."""
     cols, n = _as_cols(model, cols)

@@ -577,7 +577,8 @@ static void gen_setup(int model, const double* th, uint64_t seed, uint64_t toy, 
     }
     g.M = (1.0 + 1e-3) * M;
   } else {
-    const AngTimeHoist a = hoist_angtime(th);
+    AngTimeHoist a;
+    hoist_angtime_values(th, a.k, a.ng);
     double M = 0.0;
     for (int k = 0; k < 10; ++k) {
       double s = 0.0;
@@ -1155,7 +1156,7 @@ extern "C" ipx_status nll_eval_batch(ipx_ctx* ctx, ipx_plan* p, const double* th
   for (int j = 0; j < nb; ++j) {
     const double* th = theta + (size_t)j * np;
     bool on = active ? active[j] != 0 : true;
-    if (on && !theta_valid(model, th)) {
+    if (on && (!theta_valid(model, th) || (grad && !theta_grad_valid(model, th)))) {
       on = false;
       nll[j] = std::numeric_limits<double>::infinity();
       if (grad)
@@ -1629,7 +1630,7 @@ extern "C" ipx_status ipx_submit(ipx_server* S, const ipx_request* q, uint64_t* 
   r->bytes = request_bytes(d, r->grad);
   // hoisting outside the server's lock (the derivative table only for a
   // gradient request)
-  const bool valid = theta_valid(model, r->theta);
+  const bool valid = theta_valid(model, r->theta) && (!r->grad || theta_grad_valid(model, r->theta));
   if (valid) {
     if (model == 1) r->h1 = hoist_mass(r->theta);
     else if (model == 2) r->h2 = hoist_masstime(r->theta);
@@ -1747,11 +1748,12 @@ static ipx_status run(ipx_ctx* ctx, const ipx_dataset* dc, const double* theta, 
   ipx_dataset* d = const_cast<ipx_dataset*>(dc);  // lazily created plan and scratch only
   const int model = d->model;
   if (np != kNParams[model]) return fail(IPX_EINVAL, "model %d takes %d parameters, got %d", model, kNParams[model], np);
-  if (!theta_valid(model, theta)) {
+  if (!theta_valid(model, theta) || (grad && !theta_grad_valid(model, theta))) {
     *nll = std::numeric_limits<double>::infinity();
     if (grad)
       for (int i = 0; i < np; ++i) grad[i] = std::numeric_limits<double>::quiet_NaN();
-    return fail(IPX_EDOMAIN, "parameters outside the domain of model %d", model);
+    return fail(IPX_EDOMAIN, grad ? "parameters outside the gradient's domain of model %d"
+                                  : "parameters outside the domain of model %d", model);
   }
   HIP_TRY(hipSetDevice(ctx->device));
   if (!d->self) {
@@ -1829,6 +1831,37 @@ __global__ __launch_bounds__(kThreads) void k_count_bad_angtime(EventCols cols, 
   if (threadIdx.x == 0) counts[blockIdx.x] = (long long)wcount[0] + wcount[1] + wcount[2] + wcount[3];
 }
 
+// ---------------------------------------------------------------------------
+// Per-event terms w_i ln P_i (the quantities the evaluation kernels sum), for
+// inspection: one lane per event in storage order.  A wave's lanes hold 64
+// consecutive events starting at a multiple of 64, as in the tile kernels, so
+// the wave-uniform choices (which resolution corrections are evaluated, at
+// what continued-fraction depth) are the tile kernels' own.
+// ---------------------------------------------------------------------------
+template <int MODEL>
+__global__ __launch_bounds__(kThreads) void k_event_logp(EventCols cols, typename ModelTraits<MODEL>::Const k,
+                                                         double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= cols.n) return;
+  double acc[1] = {0.0};
+  event<MODEL, false>(k, cols, i, 0u, acc);
+  out[i] = acc[0];
+}
+
+__global__ __launch_bounds__(kThreads) void k_event_logp_angtime(EventCols cols, AngTimeConst k,
+                                                                 double* __restrict__ out) {
+  __shared__ double sC[40];
+  if (threadIdx.x < 40) sC[threadIdx.x] = (&k.C[0][0])[threadIdx.x];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= cols.n) return;
+  double acc[1] = {0.0};
+  const double w = cols.w ? ldg(cols.w + i, 0u) : 1.0;
+  event_angtime<false>(k, sC, ldg(cols.c[0] + i, 0u), ldg(cols.c[1] + i, 0u), ldg(cols.c[2] + i, 0u),
+                       ldg(cols.c[3] + i, 0u), ldg(cols.c[4] + i, 0u), ldg(cols.c[5] + i, 0u), w, acc, nullptr);
+  out[i] = acc[0];
+}
+
 extern "C" {
 
 ipx_status ipx_count_bad_events(ipx_ctx* ctx, const ipx_dataset* d, const double* theta, int np, int64_t* count) {
@@ -1857,7 +1890,8 @@ ipx_status ipx_count_bad_events(ipx_ctx* ctx, const ipx_dataset* d, const double
     e = hipMemcpyAsync(buf, &h.k, sizeof h.k, hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess) hipLaunchKernelGGL(k_count_bad<2>, dim3(grid), dim3(kThreads), 0, ctx->stream, cols, (const MassTimeConst*)buf, counts);
   } else {
-    const AngTimeHoist h = hoist_angtime(theta);
+    AngTimeHoist h;
+    hoist_angtime_values(theta, h.k, h.ng);
     e = hipMemcpyAsync(buf, &h.k, sizeof h.k, hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess) hipLaunchKernelGGL(k_count_bad_angtime, dim3(grid), dim3(kThreads), 0, ctx->stream, cols, (const AngTimeConst*)buf, counts);
   }
@@ -1871,6 +1905,35 @@ ipx_status ipx_count_bad_events(ipx_ctx* ctx, const ipx_dataset* d, const double
   int64_t total = 0;
   for (long long c : hc) total += c;
   *count = total;
+  return IPX_OK;
+}
+
+ipx_status ipx_event_logp(ipx_ctx* ctx, const ipx_dataset* d, const double* theta, int np, double* out,
+                          void* stream) {
+  if (!ctx || !d || !theta) return fail(IPX_EINVAL, "ipx_event_logp: NULL argument");
+  const int model = d->model;
+  if (np != kNParams[model])
+    return fail(IPX_EINVAL, "ipx_event_logp: model %d takes %d parameters, got %d", model, kNParams[model], np);
+  if (d->n > 0 && !out) return fail(IPX_EINVAL, "ipx_event_logp: out is NULL");
+  if (!theta_valid(model, theta)) return fail(IPX_EDOMAIN, "ipx_event_logp: parameters outside the domain");
+  if (d->n == 0) return IPX_OK;
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+  const unsigned grid = (unsigned)((d->n + kThreads - 1) / kThreads);
+  const EventCols cols = cols_of(d);
+  if (model == 1) {
+    const MassHoist h = hoist_mass(theta);
+    hipLaunchKernelGGL(k_event_logp<1>, dim3(grid), dim3(kThreads), 0, s, cols, h.k, out);
+  } else if (model == 2) {
+    const MassTimeHoist h = hoist_masstime(theta);
+    hipLaunchKernelGGL(k_event_logp<2>, dim3(grid), dim3(kThreads), 0, s, cols, h.k, out);
+  } else {
+    AngTimeHoist h;
+    hoist_angtime_values(theta, h.k, h.ng);
+    hipLaunchKernelGGL(k_event_logp_angtime, dim3(grid), dim3(kThreads), 0, s, cols, h.k, out);
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
   return IPX_OK;
 }
 

@@ -27,8 +27,9 @@ template <int N> inline HD<N> operator*(const HD<N>& a, const HD<N>& b) { HD<N> 
 template <int N> inline HD<N> operator*(double s, const HD<N>& a) { HD<N> r; r.v = s * a.v; for (int i = 0; i < N; ++i) r.d[i] = s * a.d[i]; return r; }
 template <int N> inline HD<N> hsin(const HD<N>& a) { HD<N> r; r.v = std::sin(a.v); const double c = std::cos(a.v); for (int i = 0; i < N; ++i) r.d[i] = c * a.d[i]; return r; }
 template <int N> inline HD<N> hcos(const HD<N>& a) { HD<N> r; r.v = std::cos(a.v); const double s = -std::sin(a.v); for (int i = 0; i < N; ++i) r.d[i] = s * a.d[i]; return r; }
-// sqrt with a zero derivative at 0 (the amplitude moduli enter squared there)
-template <int N> inline HD<N> hsqrt(const HD<N>& a) { HD<N> r; r.v = std::sqrt(a.v); const double h = r.v > 0.0 ? 0.5 / r.v : 0.0; for (int i = 0; i < N; ++i) r.d[i] = h * a.d[i]; return r; }
+// sqrt; its slope is infinite at 0, where the gradient is not defined (the
+// derivative table is built only inside theta_grad_valid's domain)
+template <int N> inline HD<N> hsqrt(const HD<N>& a) { HD<N> r; r.v = std::sqrt(a.v); const double h = 0.5 / r.v; for (int i = 0; i < N; ++i) r.d[i] = h * a.d[i]; return r; }
 // The same operations on plain values: code written for HD<N> computes, with
 // double, exactly the values (.v) of its dual-number run.
 inline double hsin(double a) { return std::sin(a); }
@@ -92,6 +93,18 @@ inline bool theta_valid(int model, const double* th) {
     return all_finite(th, 12) && th[0] >= 0.0 && th[1] >= 0.0 && th[0] + th[1] <= 1.0 && th[2] >= 0.0 &&
            th[2] <= 1.0 && th[11] > 0.0 && th[6] - std::fabs(th[7]) / 2.0 > 0.0;
   return false;
+}
+// The gradient's domain.  The angular model's interference coefficients are
+// linear in the amplitude moduli sqrt(|A_i|^2), whose slope is infinite where
+// a squared modulus vanishes (Fs = 0 or 1, fL = 0, fperp = 0, fL + fperp = 1):
+// there dNLL/dtheta does not exist.  The gradient is evaluated only where every
+// squared modulus, computed as the hoisting computes it, is positive.
+inline bool theta_grad_valid(int model, const double* th) {
+  if (!theta_valid(model, th)) return false;
+  if (model != 3) return true;
+  const double fL = th[0], fpe = th[1], Fs = th[2];
+  const double a0 = (1.0 - Fs) * fL, ape = (1.0 - Fs) * fpe, apa = (1.0 - Fs) * (1.0 - fL - fpe);
+  return a0 > 0.0 && ape > 0.0 && apa > 0.0 && Fs > 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -262,12 +275,6 @@ inline void hoist_angtime_values(const double* th, AngTimeConst& k, GaussNorm& n
   k.lnNG = std::log(ng.N);
 }
 inline void angtime_derivatives(const double* th, AngTimeHoist& h) { angular_coefficients(th, h.C); }
-inline AngTimeHoist hoist_angtime(const double* th) {
-  AngTimeHoist h;
-  hoist_angtime_values(th, h.k, h.ng);
-  angtime_derivatives(th, h);
-  return h;
-}
 inline void grad_angtime(const AngTimeHoist& h, const double* th, const double* a, double* g) {
   // total adjoint of C_kj: direct plus through D_j = sum_k xi_k C_kj
   // layout: a[0] l, a[1..4] dD_j, a[5..8] d(Gamma_H, Gamma_L, Re z, dm),

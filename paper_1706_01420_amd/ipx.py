@@ -91,6 +91,8 @@ _SIGNATURES = [
       ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)]),
     ("ipx_count_bad_events", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_void_p, _c_double_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]),
+    ("ipx_event_logp", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_void_p, _c_double_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     ("ipx_fp64_peak_probe", ctypes.c_int, [ctypes.c_void_p, _c_double_p, _c_double_p]),
     ("ipx_math_eval", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -497,6 +499,21 @@ def ipx_count_bad_events(ctx, ds, theta):
     n = ctypes.c_int64()
     _check(_lib.ipx_count_bad_events(ctx, ds, _dbl(th), th.size, ctypes.byref(n)))
     return n.value
+
+
+def ipx_event_logp(ctx, ds, theta, out=None, stream=None):
+    """Per-event terms w_i ln P_i at theta in storage order, written by the
+    library into a float64 CUDA tensor (out, or a new one); returns it."""
+    th = np.ascontiguousarray(theta, np.float64)
+    n = _lib.ipx_dataset_size(ds)
+    if out is None:
+        out = torch.empty(max(n, 0), dtype=torch.float64, device="cuda")
+    elif not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == torch.float64
+              and out.is_contiguous() and out.numel() >= n):
+        raise TypeError("out must be a contiguous float64 CUDA tensor of at least %d elements" % n)
+    _check(_lib.ipx_event_logp(ctx, ds, _dbl(th), th.size, out.data_ptr() if n > 0 else None,
+                               _stream_ptr(stream)))
+    return out
 
 
 def ipx_fp64_peak_probe(ctx):

@@ -17,6 +17,7 @@ import sys
 import numpy as np
 import pytest
 
+import theta_sweep
 from storage_order import band_order
 
 from oracle import models as M
@@ -46,18 +47,11 @@ def ctx(lib):
     lib.ipx_destroy(c)
 
 
-def thetas(model, k=4, seed=0):
-    rng = np.random.default_rng(seed + 10 * model)
-    base = np.array(M.THETA_GEN[model])
-    out = [base]
-    while len(out) < k:
-        th = base * (1.0 + 0.03 * rng.standard_normal(base.size))
-        if model == 3:
-            th[3:6] = base[3:6] + 0.3 * rng.standard_normal(3)
-            th[9] = base[9] + 0.3 * rng.standard_normal()
-        if M.theta_valid(model, th):
-            out.append(th)
-    return out
+def thetas(model, k=4):
+    """The generation point, then the first k - 1 random points of the parity
+    sweep (drawn over each parameter's whole range, tests/theta_sweep.py)."""
+    pts = [np.array(th) for lab, th, _ in theta_sweep.points(model) if lab.startswith("random")]
+    return [np.array(M.THETA_GEN[model])] + pts[:k - 1]
 
 
 def small_data(model, n=SMALL_N, seed=7):

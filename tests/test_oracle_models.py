@@ -175,3 +175,31 @@ def test_invalid_theta_gives_inf():
     bad = list(M.THETA_GEN[3])
     bad[7] = 2.0                   # Gamma_H < 0
     assert N.nll(3, c3, bad) == np.inf
+
+
+@pytest.mark.parametrize("edge", ["Fs=0", "fL+fperp=1"])
+def test_dual_gradient_at_a_vanishing_modulus(edge):
+    # The amplitude moduli sqrt(|A_i|^2) have an infinite slope where |A_i|^2 = 0:
+    # the derivatives along the parameters that move that modulus do not exist,
+    # every other one does and is the limit from inside the domain.
+    cols, w = _small_angtime()
+    th0 = np.array(M.THETA_GEN[3])
+    if edge == "Fs=0":
+        th0[2], moving, step = 0.0, [2], (2, 1e-14)
+    else:
+        th0[1] = 1.0 - th0[0]
+        moving, step = [0, 1], (1, -1e-14)
+    f0, g0 = N.nll_grad(3, cols, th0, w)
+    th1 = th0.copy()
+    th1[step[0]] += step[1]
+    f1, g1 = N.nll_grad(3, cols, th1, w)
+    others = [i for i in range(12) if i not in moving]
+    assert np.isfinite(f0) and abs(f0 - f1) <= 1e-6 * abs(f0)
+    assert not np.any(np.isfinite(g0[moving]))
+    assert np.all(np.isfinite(g0[others]))
+    assert np.allclose(g0[others], g1[others], rtol=1e-5, atol=1e-6 * np.abs(g1[others]).max())
+
+
+def _small_angtime():
+    from paper_1706_01420_amd import workloads as W
+    return W.events(3, 400, seed=17)
