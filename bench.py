@@ -91,6 +91,11 @@ def algorithmic_flops(model, t, sig_t, theta, grad):
 BYTES_PER_EVENT = {1: 8, 2: 24, 3: 56}
 
 
+def progress(msg):
+    """One line per finished leg on stderr (the JSON line stays alone on stdout)."""
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -256,6 +261,7 @@ def cpu_baseline(cols, w, theta, reps=3, ntoys=16, nreq=16):
             pool.map(_cpu_eval_chunk, range(len(edges) - 1))
             times.append(time.perf_counter() - t0)
     med = float(np.median(times))
+    progress("cpu baseline: full-sample evaluations %s s" % ", ".join("%.2f" % t for t in times))
     out = {"value": 1.0 / med, "unit": "NLL+grad evals/s", "cores": workers, "kind": "oracle",
            "sample": "oracle nll_grad over all %d events of the angular workload, split into %d chunks over %d "
                      "single-threaded worker processes; median of %d repetitions (%s s)"
@@ -277,6 +283,7 @@ def cpu_baseline(cols, w, theta, reps=3, ntoys=16, nreq=16):
         t0 = time.perf_counter()
         fits = pool.map(_cpu_fit_toy, range(ntoys))
         t_fit = time.perf_counter() - t0
+    progress("cpu baseline: %d toy fits in %.2f s" % (ntoys, t_fit))
     out["toy_fits"] = {"fits_per_s": ntoys / t_fit, "wall_s": t_fit, "toys": ntoys,
                        "events": int(sizes.sum()), "converged": float(np.mean([c for c, _ in fits])),
                        "evals_per_fit_mean": float(np.mean([e for _, e in fits])),
@@ -525,6 +532,7 @@ def main():
         # first, while this process has not touched the GPU: the oracle's
         # worker processes are forked from it
         cpu = cpu_baseline(cols, w, theta)
+        progress("cpu baseline done: %.4g evals/s on %d workers" % (cpu["value"], cpu["cores"]))
 
     import torch
     from paper_1706_01420_amd import ipx
@@ -534,6 +542,7 @@ def main():
 
     step_s, kernel_s = timed_rate(ipx, ctx, ds, theta, args.steps, args.warmup, grad=True)
     value = 1.0 / step_s
+    progress("angular nll_grad: %.4f ms per call, kernel %.1f us" % (step_s * 1e3, kernel_s * 1e6))
     flops = algorithmic_flops(model, cols[3], cols[4], theta, True)
     achieved = flops / kernel_s / 1e12
     # what this GPU sustains on a pure FP64 FMA loop (clock under load)
@@ -589,10 +598,13 @@ def main():
         extra["mass_nll_eval_batch64"] = bench_mass_batch(ipx, ctx, max(args.steps // 2, 5),
                                                           max(args.warmup // 2, 2))
         out["extra"] = extra
+        progress("secondary rates done")
     if not args.no_batched and not args.profile:
         out["batched"] = bench_batched_fits(ipx, ctx)
+        progress("batched fits done")
     if not args.no_served and not args.profile:
         out["served"] = bench_served(ipx, ctx)
+        progress("served leg done")
     ipx.ipx_destroy(ctx)
     if args.profile:
         out["calibration"] = calibration_copy()
