@@ -29,23 +29,28 @@ T_LO, T_HI = 0.3, 15.0           # ps
 
 SQRT2 = np.sqrt(2.0)
 
-NPARAMS = {1: 4, 2: 7, 3: 12}
-NCOLS = {1: 1, 2: 3, 3: 6}
+NPARAMS = {1: 4, 2: 7, 3: 12, 4: 12}
+NCOLS = {1: 1, 2: 3, 3: 6, 4: 7}
 PARAM_NAMES = {
     1: ("f", "mu", "sigma", "lam"),
     2: ("f", "mu", "sigma_m", "lam", "tau_s", "tau_b", "s"),
     3: ("fL", "fpe", "Fs", "dpa", "dpe", "dS", "G", "DG", "DM", "phis", "mu_m", "sigma_m"),
 }
+PARAM_NAMES[4] = PARAM_NAMES[3]
 COL_NAMES = {
     1: ("m",),
     2: ("m", "t", "sigma_t"),
     3: ("cos_k", "cos_l", "phi", "t", "sigma_t", "m"),
+    # model 4: model 3 with a flavour tag per event, qd = q (1 - 2 omega):
+    # q = +1 (B_s) / -1 (anti-B_s) the tag decision, omega its mistag probability
+    4: ("cos_k", "cos_l", "phi", "t", "sigma_t", "m", "qd"),
 }
 THETA_GEN = {
     1: (0.3, 5367.0, 15.0, 0.002),
     2: (0.3, 5367.0, 15.0, 0.002, 1.5, 0.7, 1.0),
     3: (0.52, 0.25, 0.05, 3.26, 3.08, 0.35, 0.66, 0.08, 17.8, -0.03, 5367.0, 15.0),
 }
+THETA_GEN[4] = THETA_GEN[3]
 
 # Fixed physics constants of the angular model: |lambda| = 1, C_SP = 1, delta_0 = 0.
 LAMBDA_ABS = 1.0
@@ -170,9 +175,13 @@ def angular_functions(cos_k, cos_l, phi):
 ANGULAR_INTEGRALS = np.array([32.0 * np.pi / 9.0] * 3 + [0.0] * 3 + [32.0 * np.pi / 9.0] + [0.0] * 3)
 
 
-def time_coefficients(fL, fpe, Fs, dpa, dpe, dS, phis):
+def time_coefficients(fL, fpe, Fs, dpa, dpe, dS, phis, c_sp=None):
     """C[k][j] = N_k (a_k, b_k, c_k, d_k): the weights of the cosh, sinh, cos and
-    sin time terms in term k, for a B_s at production."""
+    sin time terms in term k, for a B_s at production.  c_sp: the S-P
+    interference factor of the KK-mass bin (Example 2 fits one per bin; the
+    module constant C_SP when None)."""
+    if c_sp is None:
+        c_sp = C_SP
     l2 = LAMBDA_ABS * LAMBDA_ABS
     C = (1.0 - l2) / (1.0 + l2)
     S = -2.0 * LAMBDA_ABS * D.sin(phis) / (1.0 + l2)
@@ -197,9 +206,9 @@ def time_coefficients(fL, fpe, Fs, dpa, dpe, dS, phis):
         (r0 * rpa, (c_pa_0, Dd * c_pa_0, C * c_pa_0, -S * c_pa_0)),
         (r0 * rpe, (C * s_pe_0, S * c_pe_0, s_pe_0, Dd * c_pe_0)),
         (aS, (1.0, -Dd, C, S)),
-        (C_SP * rS * rpa, (C * c_pa_S, S * s_pa_S, c_pa_S, Dd * s_pa_S)),
-        (C_SP * rS * rpe, (s_pe_S, -Dd * s_pe_S, C * s_pe_S, S * s_pe_S)),
-        (C_SP * rS * r0, (C * c_0_S, S * s_0_S, c_0_S, Dd * s_0_S)),
+        (c_sp * rS * rpa, (C * c_pa_S, S * s_pa_S, c_pa_S, Dd * s_pa_S)),
+        (c_sp * rS * rpe, (s_pe_S, -Dd * s_pe_S, C * s_pe_S, S * s_pe_S)),
+        (c_sp * rS * r0, (C * c_0_S, S * s_0_S, c_0_S, Dd * s_0_S)),
     ]
     return [[nk * x for x in abcd] for nk, abcd in rows]
 
@@ -227,13 +236,29 @@ def time_integrals(G, DG, DM, sigma):
 
 
 def pdf_angtime(cos_k, cos_l, phi, t, sigma_t, m,
-                fL, fpe, Fs, dpa, dpe, dS, G, DG, DM, phis, mu_m, sigma_m):
+                fL, fpe, Fs, dpa, dpe, dS, G, DG, DM, phis, mu_m, sigma_m,
+                qd=1.0, xi=None, c_sp=None):
     """Model 3: [sum_k f_k(Omega) sum_j C_kj T_j(t|sigma)] / [sum_j D_j I_j(sigma)]
-    x G(m)/N_G, with D_j = sum_k xi_k C_kj and xi_k = integral f_k dOmega."""
-    Cm = time_coefficients(fL, fpe, Fs, dpa, dpe, dS, phis)
+    x G(m)/N_G, with D_j = sum_k xi_k C_kj and xi_k = integral f_k dOmega.
+
+    Model 4 (tagged) passes qd = q (1 - 2 omega) per event: an event tagged q
+    with mistag probability omega is a B_s with probability 1 - omega when
+    q = +1, and the anti-B_s PDF has the cos and sin weights (c_k, d_k) of
+    the opposite sign, so the mixture (1 - omega) |A|^2 + omega |Abar|^2 has
+    the cos and sin terms scaled by qd in the numerator and in the
+    normalisation alike (qd = +1: B_s, qd = -1: anti-B_s, qd = 0: untagged).
+
+    xi: the ten normalisation weights xi_k = integral eps(Omega) f_k dOmega of
+    an angular efficiency eps (flat efficiency: the analytic integrals); the
+    PDF is then normalised against eps, the efficiency itself being a
+    constant factor per event that the likelihood drops."""
+    Cm = time_coefficients(fL, fpe, Fs, dpa, dpe, dS, phis, c_sp)
     fk = angular_functions(cos_k, cos_l, phi)
     T = time_functions(t, G, DG, DM, sigma_t)
     I = time_integrals(G, DG, DM, sigma_t)
+    T = [T[0], T[1], qd * T[2], qd * T[3]]
+    I = [I[0], I[1], qd * I[2], qd * I[3]]
+    xk = ANGULAR_INTEGRALS if xi is None else xi
     num = 0.0
     for k in range(10):
         for j in range(4):
@@ -242,8 +267,8 @@ def pdf_angtime(cos_k, cos_l, phi, t, sigma_t, m,
     for j in range(4):
         Dj = 0.0
         for k in range(10):
-            if ANGULAR_INTEGRALS[k] != 0.0:
-                Dj = Dj + ANGULAR_INTEGRALS[k] * Cm[k][j]
+            if xk[k] != 0.0:
+                Dj = Dj + xk[k] * Cm[k][j]
         den = den + Dj * I[j]
     return num / den * gauss_shape(m, mu_m, sigma_m) / gauss_norm(mu_m, sigma_m)
 
@@ -266,12 +291,18 @@ def theta_valid(model, theta):
             and sig > 0.0 and G - abs(DG) / 2.0 > 0.0)
 
 
-def pdf(model, cols, theta):
-    """Per-event PDF values; cols in COL_NAMES order, theta in PARAM_NAMES order."""
+def pdf(model, cols, theta, settings=None):
+    """Per-event PDF values; cols in COL_NAMES order, theta in PARAM_NAMES order.
+    settings (models 3 and 4): a dict with the dataset's normalisation weights
+    "xi" (ten values) and S-P factor "c_sp"; absent keys take the flat
+    efficiency and the module's C_SP."""
+    st = settings or {}
     if model == 1:
         return pdf_mass(cols[0], *theta)
     if model == 2:
         return pdf_masstime(cols[0], cols[1], cols[2], *theta)
     if model == 3:
-        return pdf_angtime(*cols, *theta)
+        return pdf_angtime(*cols, *theta, xi=st.get("xi"), c_sp=st.get("c_sp"))
+    if model == 4:
+        return pdf_angtime(*cols[:6], *theta, qd=cols[6], xi=st.get("xi"), c_sp=st.get("c_sp"))
     raise ValueError("unknown model %r" % (model,))

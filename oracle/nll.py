@@ -28,23 +28,23 @@ def _as_cols(model, cols):
     return cols, n
 
 
-def log_pdf(model, cols, theta):
-    """Per-event ln P as an array (value only)."""
+def log_pdf(model, cols, theta, settings=None):
+    """Per-event ln P as an array (value only); settings as models.pdf."""
     cols, n = _as_cols(model, cols)
     out = np.empty(n)
     th = [float(x) for x in theta]
     for lo in range(0, n, CHUNK):
         hi = min(n, lo + CHUNK)
-        out[lo:hi] = np.log(models.pdf(model, [c[lo:hi] for c in cols], th))
+        out[lo:hi] = np.log(models.pdf(model, [c[lo:hi] for c in cols], th, settings))
     return out
 
 
-def nll(model, cols, theta, w=None):
+def nll(model, cols, theta, w=None, settings=None):
     """-sum_i w_i ln P_i, exactly summed; +inf outside the parameter domain or
     when any event has P <= 0 or a non-finite P."""
     if not models.theta_valid(model, theta):
         return math.inf
-    lp = log_pdf(model, cols, theta)
+    lp = log_pdf(model, cols, theta, settings)
     if w is not None:
         lp = lp * np.asarray(w, dtype=np.float64)
     if not np.all(np.isfinite(lp)):
@@ -52,7 +52,7 @@ def nll(model, cols, theta, w=None):
     return -math.fsum(lp.tolist())
 
 
-def nll_grad(model, cols, theta, w=None):
+def nll_grad(model, cols, theta, w=None, settings=None):
     """(NLL, dNLL/dtheta) with the gradient from forward-mode dual numbers."""
     if not models.theta_valid(model, theta):
         return math.inf, np.full(len(theta), np.nan)
@@ -64,7 +64,7 @@ def nll_grad(model, cols, theta, w=None):
     for lo in range(0, n, CHUNK):
         hi = min(n, lo + CHUNK)
         th = D.seed(theta)
-        lp = D.log(models.pdf(model, [c[lo:hi] for c in cols], th))
+        lp = D.log(models.pdf(model, [c[lo:hi] for c in cols], th, settings))
         v, d = lp.v, np.broadcast_to(lp.d, (K, hi - lo))
         if wv is not None:
             v = v * wv[lo:hi]
@@ -78,7 +78,7 @@ def nll_grad(model, cols, theta, w=None):
     return f, g
 
 
-def nll_grad_scale(model, cols, theta, w=None):
+def nll_grad_scale(model, cols, theta, w=None, settings=None):
     """(NLL, gradient, scale): nll_grad's values plus, per parameter, the sum
     of the absolute per-event terms sum_i |w_i d ln P_i / d theta_j| (the size
     of the sum the gradient cancels down from, which bounds its rounding)."""
@@ -91,7 +91,7 @@ def nll_grad_scale(model, cols, theta, w=None):
     ders = np.empty((K, n))
     for lo in range(0, n, CHUNK):
         hi = min(n, lo + CHUNK)
-        lp = D.log(models.pdf(model, [c[lo:hi] for c in cols], D.seed(theta)))
+        lp = D.log(models.pdf(model, [c[lo:hi] for c in cols], D.seed(theta), settings))
         v, d = lp.v, np.broadcast_to(lp.d, (K, hi - lo))
         if wv is not None:
             v = v * wv[lo:hi]
@@ -105,13 +105,13 @@ def nll_grad_scale(model, cols, theta, w=None):
     return f, g, np.abs(ders).sum(axis=1)
 
 
-def event_grad(model, cols, theta):
+def event_grad(model, cols, theta, settings=None):
     """Per-event d ln P_i / d theta, shape (K, n) (used by tolerance budgets)."""
     cols, n = _as_cols(model, cols)
     K = len(theta)
     out = np.empty((K, n))
     for lo in range(0, n, CHUNK):
         hi = min(n, lo + CHUNK)
-        lp = D.log(models.pdf(model, [c[lo:hi] for c in cols], D.seed(theta)))
+        lp = D.log(models.pdf(model, [c[lo:hi] for c in cols], D.seed(theta), settings))
         out[:, lo:hi] = np.broadcast_to(lp.d, (K, hi - lo))
     return out

@@ -110,3 +110,39 @@ def mixing_amplitudes(fL, fpe, Fs, dpa, dpe, dS, G, DG, DM, phis, lam_abs, t, de
     eL = np.exp(+1j * (DM / 2) * t - (G + DG / 2) * t / 2)
     gp, gm = (eL + eH) / 2, (eL - eH) / 2
     return {k: a[k] * (gp + eta[k] * lam * gm) for k in a}
+
+
+def mixing_amplitudes_bar(fL, fpe, Fs, dpa, dpe, dS, G, DG, DM, phis, lam_abs, t, delta0=0.0):
+    """The same amplitudes for an anti-B_s at t = 0:
+    Abar_i(t) = A_i [eta_i lambda g+(t) + g-(t)] up to the common phase p/q
+    (|p/q| = 1), from |Bbar(t)> = g+ |Bbar> + (p/q) g- |B> and
+    Abar_f = (p/q) lambda_f A_f, lambda_f = eta_f lambda."""
+    a = {"0": np.sqrt((1 - Fs) * fL) * np.exp(1j * delta0),
+         "pa": np.sqrt((1 - Fs) * (1 - fL - fpe)) * np.exp(1j * dpa),
+         "pe": np.sqrt((1 - Fs) * fpe) * np.exp(1j * dpe),
+         "S": np.sqrt(Fs) * np.exp(1j * dS)}
+    eta = {"0": 1.0, "pa": 1.0, "pe": -1.0, "S": -1.0}
+    lam = lam_abs * np.exp(-1j * phis)
+    eH = np.exp(-1j * (DM / 2) * t - (G - DG / 2) * t / 2)
+    eL = np.exp(+1j * (DM / 2) * t - (G + DG / 2) * t / 2)
+    gp, gm = (eL + eH) / 2, (eL - eH) / 2
+    return {k: a[k] * (eta[k] * lam * gp + gm) for k in a}
+
+
+def helicity_density_csp(A0, Apa, Ape, AS, cos_k, cos_l, phi, c_sp):
+    """helicity_density with the S-P interference terms scaled by c_sp: the
+    P-wave part, the S-wave part and c_sp times what the two add when summed
+    coherently."""
+    z = 0.0 * AS
+    full = helicity_density(A0, Apa, Ape, AS, cos_k, cos_l, phi)
+    p = helicity_density(A0, Apa, Ape, z, cos_k, cos_l, phi)
+    s = helicity_density(z, z, z, AS, cos_k, cos_l, phi)
+    return p + s + c_sp * (full - p - s)
+
+
+def acceptance(cos_k, cos_l, phi):
+    """A smooth, positive angular efficiency of the kind a detector imposes:
+    polynomial in the cosines, trigonometric in phi (integrated exactly by
+    angular_grid(8, 16))."""
+    return (1.0 + 0.3 * cos_k ** 2 - 0.2 * cos_l + 0.15 * cos_l ** 2 * np.cos(2.0 * phi)
+            - 0.1 * cos_k * np.sin(phi))
