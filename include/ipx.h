@@ -163,6 +163,33 @@ IPX_API ipx_status nll_grad(ipx_ctx *ctx, const ipx_dataset *ds, const double *t
                     double *grad, void *stream);
 
 /*
+ * Allocation-free evaluation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): nll_eval (grad == NULL) or nll_grad (grad != NULL) over
+ * caller-owned device columns, with every per-call buffer (segment record,
+ * hoisted constants, tile table, tile partials, reduced totals) in a fixed
+ * device array of the library (about 6.9 MB per device, held from the first
+ * ipx_create on that device until the process ends).  The call allocates
+ * nothing, on the device or in pinned host memory.
+ *   model, n, cols, ncols, w: as ipx_dataset_create with IPX_BORROW_DEVICE
+ *          (device pointers, events in the given order, w NULL for unit
+ *          weights); the results are bitwise those of nll_eval / nll_grad
+ *          on such a dataset.
+ *   n:     0 <= n <= 16,777,216 (2^24); larger n returns IPX_EINVAL.
+ *   theta, np, nll, grad, stream: as nll_eval / nll_grad (synchronous).
+ * All calls on one device share the array, which keeps the last call's
+ * contents (every value a call reads was written earlier by the same call).
+ * Within a process the library serialises the calls on a device with a lock;
+ * callers that bypass it (another copy of the library in the same process)
+ * must not overlap their calls on one device.
+ * IPX_EINVAL for NULL arguments, a wrong model, column count or np, or n out
+ * of range; IPX_EDOMAIN as nll_eval / nll_grad; IPX_EDEVICE for HIP errors.
+ */
+IPX_API ipx_status nll_eval_noalloc(ipx_ctx *ctx, int model, int64_t n, const double *const *cols, int ncols,
+                                    const double *w, const double *theta, int np, double *nll, double *grad,
+                                    void *stream);
+
+/*
  * Batched evaluation (many datasets of one model, each at its own theta, in
  * one fused launch; the paper's pseudo-experiment studies fit hundreds of toys
  * with the same likelihood).  A plan fixes the list of datasets (all of the

@@ -183,6 +183,8 @@ extern "C" {
 
 const char* ipx_last_error(void) { return g_last_error.c_str(); }
 
+static ipx_status noalloc_setup(int device);
+
 int ipx_model_nparams(int model) { return (model >= 1 && model <= 3) ? kNParams[model] : -1; }
 int ipx_model_ncols(int model) { return (model >= 1 && model <= 3) ? kNCols[model] : -1; }
 
@@ -193,6 +195,11 @@ ipx_status ipx_create(int device, ipx_ctx** out) {
   HIP_TRY(hipGetDeviceCount(&count));
   if (device < 0 || device >= count) return fail(IPX_EINVAL, "ipx_create: device %d of %d", device, count);
   HIP_TRY(hipSetDevice(device));
+  {
+    // the allocation-free entry point's scratch address on this device
+    ipx_status st = noalloc_setup(device);
+    if (st != IPX_OK) return st;
+  }
   ipx_ctx* c = new (std::nothrow) ipx_ctx();
   if (!c) return fail(IPX_ENOMEM, "ipx_create: host allocation failed");
   c->device = device;
@@ -1100,44 +1107,52 @@ static ipx_status timing_end(ipx_ctx* ctx, hipStream_t s) {
   return IPX_OK;
 }
 
-// Stream operations of one (batched) evaluation: the per-event kernel (timed
-// through `timer` when given), then the per-segment reductions.  The kernels read the
-// hoisted constants and active flags from pinned host memory (written by the
-// host before the launch; the few hundred bytes are cached on the device after
-// the first workgroup's read) and the reductions write the results into pinned
-// host memory, so an evaluation needs no copies.
-static ipx_status enqueue_batch(ipx_plan* p, bool grad, hipStream_t s, ipx_ctx* timer) {
-  const int nb = p->nb;
-  const int64_t wg = p->sched.workgroups > 0 ? std::min<int64_t>(p->sched.workgroups, p->n_tiles) : p->n_tiles;
-  const unsigned grid = (unsigned)std::max<int64_t>(1, wg);
+// The per-event kernel over a tile table (timed through `timer` when given),
+// then the per-segment reductions writing nacc totals per segment to `out`.
+// Shared by plans and the allocation-free entry point, so a dataset's tiles
+// run the same instructions whichever way it is evaluated.
+static ipx_status launch_eval(int model, bool grad, unsigned grid, const SegInfo* segs, const TileRef* tiles,
+                              int64_t n_tiles, const void* consts, const unsigned char* active, int nb, double* out,
+                              hipStream_t s, ipx_ctx* timer) {
   int nacc = 1;
   {
     ipx_status st = timing_begin(timer, s);
     if (st != IPX_OK) return st;
   }
-  if (p->model == 1) {
+  if (model == 1) {
     nacc = grad ? kAccMass : 1;
-    if (grad) hipLaunchKernelGGL((k_nll_batch<1, true>), dim3(grid), dim3(kThreads), 0, s, p->d_segs, p->d_tiles, p->n_tiles, (const MassConst*)p->d_consts, p->d_active);
-    else hipLaunchKernelGGL((k_nll_batch<1, false>), dim3(grid), dim3(kThreads), 0, s, p->d_segs, p->d_tiles, p->n_tiles, (const MassConst*)p->d_consts, p->d_active);
-  } else if (p->model == 2) {
+    if (grad) hipLaunchKernelGGL((k_nll_batch<1, true>), dim3(grid), dim3(kThreads), 0, s, segs, tiles, n_tiles, (const MassConst*)consts, active);
+    else hipLaunchKernelGGL((k_nll_batch<1, false>), dim3(grid), dim3(kThreads), 0, s, segs, tiles, n_tiles, (const MassConst*)consts, active);
+  } else if (model == 2) {
     nacc = grad ? kAccMassTime : 1;
-    if (grad) hipLaunchKernelGGL((k_nll_batch<2, true>), dim3(grid), dim3(kThreads), 0, s, p->d_segs, p->d_tiles, p->n_tiles, (const MassTimeConst*)p->d_consts, p->d_active);
-    else hipLaunchKernelGGL((k_nll_batch<2, false>), dim3(grid), dim3(kThreads), 0, s, p->d_segs, p->d_tiles, p->n_tiles, (const MassTimeConst*)p->d_consts, p->d_active);
+    if (grad) hipLaunchKernelGGL((k_nll_batch<2, true>), dim3(grid), dim3(kThreads), 0, s, segs, tiles, n_tiles, (const MassTimeConst*)consts, active);
+    else hipLaunchKernelGGL((k_nll_batch<2, false>), dim3(grid), dim3(kThreads), 0, s, segs, tiles, n_tiles, (const MassTimeConst*)consts, active);
   } else {
     nacc = grad ? kAccAngTime : 1;
-    if (grad) hipLaunchKernelGGL((k_angtime_batch<true>), dim3(grid), dim3(kThreads), 0, s, p->d_segs, p->d_tiles, p->n_tiles, (const AngTimeConst*)p->d_consts, p->d_active);
-    else hipLaunchKernelGGL((k_angtime_batch<false>), dim3(grid), dim3(kThreads), 0, s, p->d_segs, p->d_tiles, p->n_tiles, (const AngTimeConst*)p->d_consts, p->d_active);
+    if (grad) hipLaunchKernelGGL((k_angtime_batch<true>), dim3(grid), dim3(kThreads), 0, s, segs, tiles, n_tiles, (const AngTimeConst*)consts, active);
+    else hipLaunchKernelGGL((k_angtime_batch<false>), dim3(grid), dim3(kThreads), 0, s, segs, tiles, n_tiles, (const AngTimeConst*)consts, active);
   }
   HIP_TRY(hipGetLastError());
   {
     ipx_status st = timing_end(timer, s);
     if (st != IPX_OK) return st;
   }
-  // the totals go straight to pinned host memory (visible once the stream
-  // has synchronised)
-  hipLaunchKernelGGL(k_reduce_batch, dim3(nacc, nb), dim3(kThreads), 0, s, p->d_segs, p->d_active, p->h_out_dev);
+  hipLaunchKernelGGL(k_reduce_batch, dim3(nacc, nb), dim3(kThreads), 0, s, segs, active, out);
   HIP_TRY(hipGetLastError());
   return IPX_OK;
+}
+
+// Stream operations of one (batched) evaluation.  The kernels read the
+// hoisted constants and active flags from pinned host memory (written by the
+// host before the launch; the few hundred bytes are cached on the device after
+// the first workgroup's read) and the reductions write the results into pinned
+// host memory (visible once the stream has synchronised), so an evaluation
+// needs no copies.
+static ipx_status enqueue_batch(ipx_plan* p, bool grad, hipStream_t s, ipx_ctx* timer) {
+  const int64_t wg = p->sched.workgroups > 0 ? std::min<int64_t>(p->sched.workgroups, p->n_tiles) : p->n_tiles;
+  const unsigned grid = (unsigned)std::max<int64_t>(1, wg);
+  return launch_eval(p->model, grad, grid, p->d_segs, p->d_tiles, p->n_tiles, p->d_consts, p->d_active, p->nb,
+                     p->h_out_dev, s, timer);
 }
 
 extern "C" ipx_status nll_eval_batch(ipx_ctx* ctx, ipx_plan* p, const double* theta, const unsigned char* active,
@@ -1742,18 +1757,60 @@ extern "C" ipx_status ipx_server_stop(ipx_server* S) {
   return IPX_OK;
 }
 
+// Per-call host state of one evaluation: the hoisted constants of the model
+// in use and, for the angular gradient, the derivative table of the hoisting.
+struct EvalHoist {
+  MassHoist h1;
+  MassTimeHoist h2;
+  AngTimeHoist h3;
+  const void* consts = nullptr;
+  size_t bytes = 0;
+};
+
+// Domain check shared by the evaluation entry points: outside the model's
+// domain (or the gradient's) the outputs are +inf / NaN and nothing runs.
+static ipx_status check_theta(int model, const double* theta, int np, double* nll, double* grad) {
+  if (theta_valid(model, theta) && (!grad || theta_grad_valid(model, theta))) return IPX_OK;
+  *nll = std::numeric_limits<double>::infinity();
+  if (grad)
+    for (int i = 0; i < np; ++i) grad[i] = std::numeric_limits<double>::quiet_NaN();
+  return fail(IPX_EDOMAIN, grad ? "parameters outside the gradient's domain of model %d"
+                                : "parameters outside the domain of model %d", model);
+}
+
+static void hoist_eval(int model, const double* theta, EvalHoist& h) {
+  if (model == 1) { h.h1 = hoist_mass(theta); h.consts = &h.h1.k; h.bytes = sizeof h.h1.k; }
+  else if (model == 2) { h.h2 = hoist_masstime(theta); h.consts = &h.h2.k; h.bytes = sizeof h.h2.k; }
+  else { hoist_angtime_values(theta, h.h3.k, h.h3.ng); h.consts = &h.h3.k; h.bytes = sizeof h.h3.k; }
+}
+
+// NLL and gradient from the reduced totals a[] (a[0] = sum of w ln P).
+static ipx_status finish_eval(int model, const EvalHoist& h, const double* theta, int np, const double* a,
+                              double* nll, double* grad) {
+  if (!std::isfinite(a[0])) {
+    *nll = std::numeric_limits<double>::infinity();
+    if (grad)
+      for (int i = 0; i < np; ++i) grad[i] = std::numeric_limits<double>::quiet_NaN();
+    return fail(IPX_EDOMAIN, "non-finite likelihood (an event has P <= 0 or a non-finite term)");
+  }
+  *nll = -a[0];
+  if (grad) {
+    if (model == 1) grad_mass(h.h1, theta, a, grad);
+    else if (model == 2) grad_masstime(h.h2, theta, a, grad);
+    else grad_angtime(h.h3, theta, a, grad);
+  }
+  return IPX_OK;
+}
+
 static ipx_status run(ipx_ctx* ctx, const ipx_dataset* dc, const double* theta, int np, double* nll,
                       double* grad, void* stream) {
   if (!ctx || !dc || !theta || !nll) return fail(IPX_EINVAL, "NULL argument");
   ipx_dataset* d = const_cast<ipx_dataset*>(dc);  // lazily created plan and scratch only
   const int model = d->model;
   if (np != kNParams[model]) return fail(IPX_EINVAL, "model %d takes %d parameters, got %d", model, kNParams[model], np);
-  if (!theta_valid(model, theta) || (grad && !theta_grad_valid(model, theta))) {
-    *nll = std::numeric_limits<double>::infinity();
-    if (grad)
-      for (int i = 0; i < np; ++i) grad[i] = std::numeric_limits<double>::quiet_NaN();
-    return fail(IPX_EDOMAIN, grad ? "parameters outside the gradient's domain of model %d"
-                                  : "parameters outside the domain of model %d", model);
+  {
+    ipx_status st = check_theta(model, theta, np, nll, grad);
+    if (st != IPX_OK) return st;
   }
   HIP_TRY(hipSetDevice(ctx->device));
   if (!d->self) {
@@ -1763,31 +1820,65 @@ static ipx_status run(ipx_ctx* ctx, const ipx_dataset* dc, const double* theta, 
   }
   ipx_plan* p = d->self;
   hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
-  MassHoist h1;
-  MassTimeHoist h2;
-  AngTimeHoist h3;
-  if (model == 1) { h1 = hoist_mass(theta); std::memcpy(p->h_consts, &h1.k, sizeof h1.k); }
-  else if (model == 2) { h2 = hoist_masstime(theta); std::memcpy(p->h_consts, &h2.k, sizeof h2.k); }
-  else { hoist_angtime_values(theta, h3.k, h3.ng); std::memcpy(p->h_consts, &h3.k, sizeof h3.k); }
+  EvalHoist h;
+  hoist_eval(model, theta, h);
+  std::memcpy(p->h_consts, h.consts, h.bytes);
   p->h_active[0] = 1;
   ipx_status st = enqueue_batch(p, grad != nullptr, s, ctx);
   if (st != IPX_OK) return st;
-  if (model == 3 && grad) angtime_derivatives(theta, h3);  // while the kernels run
+  if (model == 3 && grad) angtime_derivatives(theta, h.h3);  // while the kernels run
   HIP_TRY(hipStreamSynchronize(s));
-  const double* a = p->h_out;
-  if (!std::isfinite(a[0])) {
-    *nll = std::numeric_limits<double>::infinity();
-    if (grad)
-      for (int i = 0; i < np; ++i) grad[i] = std::numeric_limits<double>::quiet_NaN();
-    return fail(IPX_EDOMAIN, "non-finite likelihood (an event has P <= 0 or a non-finite term)");
-  }
-  *nll = -a[0];
-  if (grad) {
-    if (model == 1) grad_mass(h1, theta, a, grad);
-    else if (model == 2) grad_masstime(h2, theta, a, grad);
-    else grad_angtime(h3, theta, a, grad);
-  }
+  return finish_eval(model, h, theta, np, p->h_out, nll, grad);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free evaluation (nll_eval_noalloc).  Its per-call scratch -- the
+// one-segment record, the hoisted constants, the active flag, the reduced
+// totals, the tile table and the tile partials -- lives in `scratch`, a
+// file-scope device array of fixed size: every device the library runs on
+// holds its own copy until the process ends.  Host code never names the array
+// itself (on the host its name is not a device address): its device address is
+// taken once per device, with that device current, when the first context is
+// created there, and only that address is passed to copies and kernels.
+// ---------------------------------------------------------------------------
+constexpr int64_t kNoAllocMaxEvents = (int64_t)1 << 24;           // 16,777,216 events
+constexpr int64_t kNoAllocMaxTiles = kNoAllocMaxEvents / kTile;   // 16,384 tiles
+constexpr size_t kNaSeg = 0;                                      // SegInfo
+constexpr size_t kNaConst = 256;                                  // constant block (<= 2 KiB)
+constexpr size_t kNaActive = kNaConst + 2048;                     // one active flag
+constexpr size_t kNaOut = kNaActive + 256;                        // kAccMax reduced totals
+constexpr size_t kNaHead = kNaOut + 512;
+constexpr size_t kNaTiles = kNaHead;                              // TileRef x max tiles
+constexpr size_t kNaPartials = kNaTiles + (size_t)kNoAllocMaxTiles * sizeof(TileRef);
+constexpr size_t kNoAllocBytes = kNaPartials + (size_t)kNoAllocMaxTiles * kAccMax * sizeof(double);  // ~6.9 MB
+static_assert(sizeof(SegInfo) <= kNaConst - kNaSeg, "segment record");
+static_assert(sizeof(MassConst) <= 2048 && sizeof(MassTimeConst) <= 2048 && sizeof(AngTimeConst) <= 2048,
+              "constant block");
+static_assert(kAccMax * sizeof(double) <= kNaHead - kNaOut, "totals");
+static_assert(kNaTiles % 256 == 0 && kNaPartials % 256 == 0, "aligned regions");
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_noalloc_mu[kMaxDevices];              // one call at a time per device
+static std::atomic<unsigned char*> g_noalloc_ptr[kMaxDevices];
+
+// Called with `device` current (ipx_create).
+static ipx_status noalloc_setup(int device) {
+  if (device >= kMaxDevices) return fail(IPX_EINVAL, "ipx_create: device %d beyond the %d supported", device, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_noalloc_mu[device]);
+  if (g_noalloc_ptr[device].load()) return IPX_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p)
+    return fail(IPX_EDEVICE, "ipx_create: hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+  g_noalloc_ptr[device].store((unsigned char*)p);
   return IPX_OK;
+}
+
+__global__ void k_fill_tiles(TileRef* __restrict__ t, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) t[i] = TileRef{0, i};
 }
 
 // ---------------------------------------------------------------------------
@@ -1945,6 +2036,73 @@ ipx_status nll_grad(ipx_ctx* ctx, const ipx_dataset* ds, const double* theta, in
                     void* stream) {
   if (!grad) return fail(IPX_EINVAL, "nll_grad: grad is NULL");
   return run(ctx, ds, theta, np, nll, grad, stream);
+}
+
+ipx_status nll_eval_noalloc(ipx_ctx* ctx, int model, int64_t n, const double* const* cols, int ncols,
+                            const double* w, const double* theta, int np, double* nll, double* grad, void* stream) {
+  if (!ctx || !theta || !nll) return fail(IPX_EINVAL, "nll_eval_noalloc: NULL argument");
+  if (model < 1 || model > 3) return fail(IPX_EINVAL, "nll_eval_noalloc: unknown model %d", model);
+  if (ncols != kNCols[model])
+    return fail(IPX_EINVAL, "nll_eval_noalloc: model %d takes %d columns, got %d", model, kNCols[model], ncols);
+  if (np != kNParams[model])
+    return fail(IPX_EINVAL, "nll_eval_noalloc: model %d takes %d parameters, got %d", model, kNParams[model], np);
+  if (n < 0) return fail(IPX_EINVAL, "nll_eval_noalloc: negative size");
+  if (n > kNoAllocMaxEvents)
+    return fail(IPX_EINVAL, "nll_eval_noalloc: %lld events exceed the maximum of %lld (fixed scratch of %zu bytes)",
+                (long long)n, (long long)kNoAllocMaxEvents, kNoAllocBytes);
+  if (n > 0 && !cols) return fail(IPX_EINVAL, "nll_eval_noalloc: NULL cols");
+  for (int c = 0; c < ncols && n > 0; ++c)
+    if (!cols[c]) return fail(IPX_EINVAL, "nll_eval_noalloc: column %d is NULL", c);
+  {
+    ipx_status st = check_theta(model, theta, np, nll, grad);
+    if (st != IPX_OK) return st;
+  }
+  if (ctx->device >= kMaxDevices) return fail(IPX_EINVAL, "nll_eval_noalloc: device %d", ctx->device);
+  unsigned char* base = g_noalloc_ptr[ctx->device].load();
+  if (!base) return fail(IPX_EDEVICE, "nll_eval_noalloc: scratch address of device %d not set up", ctx->device);
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu[ctx->device]);
+
+  const int64_t n_tiles = (n + kTile - 1) / kTile;
+  SegInfo* segs = (SegInfo*)(base + kNaSeg);
+  const unsigned char* active = base + kNaActive;
+  double* out = (double*)(base + kNaOut);
+  TileRef* tiles = (TileRef*)(base + kNaTiles);
+  double* partials = (double*)(base + kNaPartials);
+
+  // head of the scratch (segment record, constants, active flag), staged on
+  // the host stack and copied in one transfer
+  alignas(16) unsigned char head[kNaOut];
+  std::memset(head, 0, sizeof head);
+  SegInfo seg{};
+  for (int c = 0; c < ncols; ++c) seg.cols.c[c] = cols ? cols[c] : nullptr;
+  seg.cols.w = w;
+  seg.cols.n = n;
+  seg.partials = partials;
+  seg.n_tiles = n_tiles;
+  std::memcpy(head + kNaSeg, &seg, sizeof seg);
+  EvalHoist h;
+  hoist_eval(model, theta, h);
+  std::memcpy(head + kNaConst, h.consts, h.bytes);
+  head[kNaActive] = 1;
+  HIP_TRY(hipMemcpyAsync(base, head, sizeof head, hipMemcpyHostToDevice, s));
+  if (n_tiles > 0) {
+    hipLaunchKernelGGL(k_fill_tiles, dim3((unsigned)((n_tiles + 255) / 256)), dim3(256), 0, s, tiles, (int)n_tiles);
+    HIP_TRY(hipGetLastError());
+  }
+  const bool g = grad != nullptr;
+  const int nacc = !g ? 1 : model == 1 ? kAccMass : model == 2 ? kAccMassTime : kAccAngTime;
+  {
+    ipx_status st = launch_eval(model, g, (unsigned)std::max<int64_t>(1, n_tiles), segs, tiles, n_tiles,
+                                base + kNaConst, active, 1, out, s, nullptr);
+    if (st != IPX_OK) return st;
+  }
+  double a[kAccMax];
+  HIP_TRY(hipMemcpyAsync(a, out, nacc * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (model == 3 && g) angtime_derivatives(theta, h.h3);  // while the kernels run
+  HIP_TRY(hipStreamSynchronize(s));
+  return finish_eval(model, h, theta, np, a, nll, grad);
 }
 
 }  // extern "C"

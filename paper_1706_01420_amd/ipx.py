@@ -64,6 +64,9 @@ _SIGNATURES = [
     ("nll_grad", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
       ctypes.c_void_p]),
+    ("nll_eval_noalloc", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     ("ipx_plan_create", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p), _c_void_pp]),
     ("ipx_plan_destroy", None, [ctypes.c_void_p]),
     ("nll_eval_batch", ctypes.c_int,
@@ -279,6 +282,38 @@ def nll_grad(ctx, ds, theta, stream=None):
         return float("inf"), np.full(n, np.nan)
     _check(st)
     return float(b.out[0]), b.g[:n].copy()
+
+
+def nll_eval_noalloc(ctx, model, cols, w, theta, grad=False, stream=None):
+    """nll_eval (grad=False: returns NLL) or nll_grad (grad=True: returns
+    (NLL, gradient)) over contiguous float64 CUDA tensors used in place, with
+    the library's fixed scratch (no allocation); +inf (and NaN gradients) for
+    IPX_EDOMAIN."""
+    ncols = len(cols)
+    ptrs = (ctypes.c_void_p * max(ncols, 1))()
+    n = None
+    for i, c in enumerate(cols):
+        if not (isinstance(c, torch.Tensor) and c.is_cuda and c.dtype == torch.float64 and c.is_contiguous()):
+            raise TypeError("columns must be contiguous float64 CUDA tensors")
+        ptrs[i] = c.data_ptr()
+        if n is None:
+            n = c.shape[0]
+        elif n != c.shape[0]:
+            raise ValueError("columns differ in length")
+    wp = None
+    if w is not None:
+        if not (isinstance(w, torch.Tensor) and w.is_cuda and w.dtype == torch.float64 and w.is_contiguous()):
+            raise TypeError("weights must be a contiguous float64 CUDA tensor")
+        if w.shape[0] != n:
+            raise ValueError("weights differ in length")
+        wp = w.data_ptr()
+    b, npar = _buffers(theta)
+    st = _lib.nll_eval_noalloc(ctx, int(model), int(n or 0), ptrs, ncols, wp, b.th_p, npar, b.out_p,
+                               b.g_p if grad else None, None if stream is None else _stream_ptr(stream))
+    if st == IPX_EDOMAIN:
+        return (float("inf"), np.full(npar, np.nan)) if grad else float("inf")
+    _check(st)
+    return (float(b.out[0]), b.g[:npar].copy()) if grad else float(b.out[0])
 
 
 class _NLL(torch.autograd.Function):
