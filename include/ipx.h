@@ -268,8 +268,17 @@ IPX_API ipx_status ipx_plan_autotune(ipx_ctx *ctx, ipx_plan *plan, const double 
  *   requests are already waiting; IPX_ENOMEM if the request alone exceeds the
  *   scratch budget).  Results are taken once, with ipx_poll (IPX_EBUSY while
  *   running) or ipx_wait (IPX_ETIMEOUT after timeout_ns; < 0 waits forever).
+ *   ipx_server_drain blocks until every request submitted before it has
+ *   finished (submissions during the drain return IPX_EBUSY); their results
+ *   stay available to ipx_poll / ipx_wait, and the server accepts requests
+ *   again afterwards.
  *   ipx_server_stop drains pending and in-flight requests, stops the device
- *   loop and frees the server.  Datasets must outlive the requests on them.
+ *   loop, wakes the clients blocked in ipx_wait (each returns its result, or
+ *   IPX_ENOTFOUND if its request could not finish), waits until every call
+ *   already inside the server has returned, and frees the server; results not
+ *   yet taken are discarded.  No call on the server may start once
+ *   ipx_server_stop has been called.  Datasets must outlive the requests on
+ *   them.
  */
 typedef struct ipx_server ipx_server;
 typedef struct {
@@ -300,6 +309,7 @@ IPX_API ipx_status ipx_server_start(ipx_ctx *ctx, const ipx_server_cfg *cfg, ipx
 IPX_API ipx_status ipx_submit(ipx_server *srv, const ipx_request *req, uint64_t *ticket);
 IPX_API ipx_status ipx_poll(ipx_server *srv, uint64_t ticket, ipx_result *out);
 IPX_API ipx_status ipx_wait(ipx_server *srv, uint64_t ticket, int64_t timeout_ns, ipx_result *out);
+IPX_API ipx_status ipx_server_drain(ipx_server *srv);
 IPX_API ipx_status ipx_server_stop(ipx_server *srv);
 /* Host-side counters of a running server (monitoring). */
 typedef struct {

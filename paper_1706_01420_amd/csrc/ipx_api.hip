@@ -1367,6 +1367,17 @@ struct ipx_server {
   std::atomic<int> n_pending{0};       // pending.size(), readable without mu
   std::map<uint64_t, ServeReq*> reqs;
   ipx_server_stats stats{};
+  int draining = 0;                    // ipx_server_drain calls in progress (submissions refused)
+  bool closed = false;                 // ipx_server_stop has drained: waiters return, nothing new starts
+  std::atomic<int> users{0};           // client calls inside the server (stop frees it only at 0)
+};
+
+// Counts a client call as inside the server for its whole duration, so that
+// ipx_server_stop frees the server only after such calls have returned.
+struct ServerUse {
+  ipx_server* S;
+  explicit ServerUse(ipx_server* s) : S(s) { S->users.fetch_add(1, std::memory_order_acq_rel); }
+  ~ServerUse() { S->users.fetch_sub(1, std::memory_order_acq_rel); }
 };
 
 static bool pool_alloc(ipx_server* S, size_t bytes, size_t* off) {
@@ -1631,6 +1642,7 @@ extern "C" ipx_status ipx_server_start(ipx_ctx* ctx, const ipx_server_cfg* cfg, 
 
 extern "C" ipx_status ipx_submit(ipx_server* S, const ipx_request* q, uint64_t* ticket) {
   if (!S || !q || !ticket || !q->ds || !q->theta) return fail(IPX_EINVAL, "ipx_submit: NULL argument");
+  ServerUse use(S);
   ipx_dataset* d = const_cast<ipx_dataset*>(q->ds);
   const int model = d->model, np = kNParams[model];
   if (q->np != np) return fail(IPX_EINVAL, "ipx_submit: model %d takes %d parameters", model, np);
@@ -1655,9 +1667,13 @@ extern "C" ipx_status ipx_submit(ipx_server* S, const ipx_request* q, uint64_t* 
     }
   }
   std::lock_guard<std::mutex> lk(S->mu);
-  if (S->stopping) {
+  if (S->stopping || S->closed) {
     delete r;
     return fail(IPX_EBUSY, "ipx_submit: server is stopping");
+  }
+  if (S->draining > 0) {
+    delete r;
+    return fail(IPX_EBUSY, "ipx_submit: server is draining");
   }
   if (r->bytes > S->cfg.scratch_bytes) {
     delete r;
@@ -1700,6 +1716,7 @@ static ipx_status take_result(ipx_server* S, std::map<uint64_t, ServeReq*>::iter
 
 extern "C" ipx_status ipx_poll(ipx_server* S, uint64_t ticket, ipx_result* out) {
   if (!S) return fail(IPX_EINVAL, "ipx_poll: NULL server");
+  ServerUse use(S);
   std::lock_guard<std::mutex> lk(S->mu);
   auto it = S->reqs.find(ticket);
   if (it == S->reqs.end()) return fail(IPX_ENOTFOUND, "ipx_poll: unknown ticket %llu", (unsigned long long)ticket);
@@ -1709,12 +1726,14 @@ extern "C" ipx_status ipx_poll(ipx_server* S, uint64_t ticket, ipx_result* out) 
 
 extern "C" ipx_status ipx_wait(ipx_server* S, uint64_t ticket, int64_t timeout_ns, ipx_result* out) {
   if (!S) return fail(IPX_EINVAL, "ipx_wait: NULL server");
+  ServerUse use(S);
   std::unique_lock<std::mutex> lk(S->mu);
   auto it = S->reqs.find(ticket);
   if (it == S->reqs.end()) return fail(IPX_ENOTFOUND, "ipx_wait: unknown ticket %llu", (unsigned long long)ticket);
   ServeReq* r = it->second;
   const auto deadline = std::chrono::steady_clock::now() + std::chrono::nanoseconds(timeout_ns < 0 ? (int64_t)1 << 62 : timeout_ns);
   while (!r->done) {
+    if (S->closed) return fail(IPX_ENOTFOUND, "ipx_wait: server stopped before ticket %llu finished", (unsigned long long)ticket);
     if (S->cv.wait_until(lk, deadline) == std::cv_status::timeout && !r->done)
       return fail(IPX_ETIMEOUT, "ipx_wait: ticket %llu not done", (unsigned long long)ticket);
   }
@@ -1723,11 +1742,33 @@ extern "C" ipx_status ipx_wait(ipx_server* S, uint64_t ticket, int64_t timeout_n
 
 extern "C" ipx_status ipx_server_stats_read(ipx_server* S, ipx_server_stats* out) {
   if (!S || !out) return fail(IPX_EINVAL, "ipx_server_stats_read: NULL argument");
+  ServerUse use(S);
   std::lock_guard<std::mutex> lk(S->mu);
   *out = S->stats;
   out->pending = S->pending.size();
   out->in_flight = 0;
   for (ServeReq* r : S->slot_req) out->in_flight += r != nullptr;
+  return IPX_OK;
+}
+
+// True when no request is waiting for a slot or in a device slot (S->mu held;
+// slot_req is written only under the lock).
+static bool server_idle(const ipx_server* S) {
+  if (!S->pending.empty()) return false;
+  for (const ServeReq* r : S->slot_req)
+    if (r) return false;
+  return true;
+}
+
+extern "C" ipx_status ipx_server_drain(ipx_server* S) {
+  if (!S) return fail(IPX_EINVAL, "ipx_server_drain: NULL server");
+  ServerUse use(S);
+  std::unique_lock<std::mutex> lk(S->mu);
+  if (S->stopping || S->closed) return fail(IPX_EBUSY, "ipx_server_drain: server is stopping");
+  ++S->draining;
+  // the host worker notifies after every completion and admission
+  while (!server_idle(S)) S->cv.wait_for(lk, std::chrono::milliseconds(1));
+  --S->draining;
   return IPX_OK;
 }
 
@@ -1742,6 +1783,21 @@ extern "C" ipx_status ipx_server_stop(ipx_server* S) {
   __atomic_store_n(&S->hs->stop, 1ull, __ATOMIC_RELEASE);
   (void)hipSetDevice(S->ctx->device);
   hipError_t e = hipStreamSynchronize(S->stream);
+  {
+    // every request has finished: wake the clients blocked in ipx_wait (they
+    // take their results) and let the calls inside the server return before
+    // it is freed
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->closed = true;
+    S->cv.notify_all();
+  }
+  while (S->users.load(std::memory_order_acquire) > 0) {
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->cv.notify_all();
+    }
+    std::this_thread::yield();
+  }
   for (auto& kv : S->reqs) delete kv.second;
   (void)hipFree(S->pool);
   (void)hipFree(S->st);

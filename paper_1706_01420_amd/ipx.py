@@ -76,6 +76,7 @@ _SIGNATURES = [
     ("ipx_submit", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
     ("ipx_poll", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
     ("ipx_wait", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64, ctypes.c_void_p]),
+    ("ipx_server_drain", ctypes.c_int, [ctypes.c_void_p]),
     ("ipx_server_stop", ctypes.c_int, [ctypes.c_void_p]),
     ("ipx_server_stats_read", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     ("toy_generate", ctypes.c_int,
@@ -451,6 +452,12 @@ def ipx_wait(srv, ticket, timeout_s=-1.0):
     if st not in (IPX_OK, IPX_EDOMAIN):
         _check(st)
     return _result_dict(r)
+
+
+def ipx_server_drain(srv):
+    """Block until every request submitted so far has finished (results stay
+    available to ipx_poll / ipx_wait)."""
+    _check(_lib.ipx_server_drain(srv))
 
 
 def ipx_server_stop(srv):

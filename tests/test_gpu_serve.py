@@ -162,15 +162,50 @@ def test_errors_stay_with_their_request_and_idle_relaunch(lib, ctx, datasets):
         lib.ipx_server_stop(srv)
 
 
-def test_stop_drains_pending_requests(lib, ctx, datasets):
+def test_drain_then_stop_with_blocked_waiters(lib, ctx, datasets):
+    """ipx_server_drain finishes every request submitted before it (with two
+    slots, most of the six wait for a slot when it is called): afterwards
+    every ticket polls done, with the plain call's bits.  Clients waiting in ipx_wait on other threads get
+    their results; the server stops cleanly after them."""
+    import threading
     model, d = datasets[-1]
     srv = lib.ipx_server_start(ctx, slots=2)
     th = np.array(M.THETA_GEN[3])
-    say("serve stop drains")
-    tickets = [lib.ipx_submit(srv, d, th, True) for _ in range(6)]
-    lib.ipx_server_stop(srv)
-    # the server is gone; its results were computed before it stopped
-    assert len(tickets) == 6
+    say("serve drain")
+    stopped = False
+    try:
+        tickets = [lib.ipx_submit(srv, d, th, True) for _ in range(6)]
+        lib.ipx_server_drain(srv)
+        st = lib.ipx_server_stats_read(srv)
+        assert st["published"] == 6 and st["completed"] == 6
+        assert st["pending"] == 0 and st["in_flight"] == 0
+        f, g = lib.nll_grad(ctx, d, th)
+        for t in tickets:
+            r = lib.ipx_poll(srv, t)          # done: never IPX_EBUSY after the drain
+            assert r["status"] == 0 and r["nll"] == f and np.array_equal(r["grad"], g)
+        # waiters blocked on their own tickets while the server drains and stops
+        tickets = [lib.ipx_submit(srv, d, th, bool(i % 2)) for i in range(8)]
+        got = {}
+
+        def waiter(t):
+            got[t] = lib.ipx_wait(srv, t, 60.0)
+
+        threads = [threading.Thread(target=waiter, args=(t,)) for t in tickets]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        say("serve stop")
+        lib.ipx_server_stop(srv)
+        stopped = True
+        assert sorted(got) == sorted(tickets)
+        f0 = lib.nll_eval(ctx, d, th)
+        for i, t in enumerate(tickets):
+            assert got[t]["status"] == 0
+            assert got[t]["nll"] == (f if i % 2 else f0)
+    finally:
+        if not stopped:
+            lib.ipx_server_stop(srv)
 
 
 def test_two_workgroups_and_counters(lib, ctx, datasets):
