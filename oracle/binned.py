@@ -130,10 +130,28 @@ def poisson_inverse(u, nu, exp_minus_nu):
     return k
 
 
+def poisson_inverse_array(u, nu, exp_minus_nu):
+    """poisson_inverse element by element, the bins stepped together (the same
+    operations in the same order on each element)."""
+    u = np.asarray(u, np.float64)
+    nu = np.asarray(nu, np.float64)
+    k = np.zeros(u.size)
+    p = np.array(exp_minus_nu, np.float64)
+    F = p.copy()
+    kmax = np.floor(nu + 30.0 * np.sqrt(nu + 1.0) + 30.0)
+    go = (u > F) & (k < kmax)
+    while go.any():
+        k = np.where(go, k + 1.0, k)
+        p = np.where(go, p * nu / np.where(go, k, 1.0), p)
+        F = np.where(go, F + p, F)
+        go = go & (u > F) & (k < kmax)
+    return k.astype(np.int64)
+
+
 def toy_counts(seed, hyp, toy, nu):
+    nu = np.asarray(nu, np.float64)
     u = toy_uniforms(seed, hyp, toy, nu.size)
-    em = np.exp(-nu)
-    return np.array([poisson_inverse(float(u[b]), float(nu[b]), float(em[b])) for b in range(nu.size)])
+    return poisson_inverse_array(u, nu, np.exp(-nu))
 
 
 def q_statistic(counts, s, b):

@@ -170,3 +170,12 @@ def test_planted_binned_mistake_is_caught(attr, fake, check, monkeypatch):
     monkeypatch.setattr(B, attr, fake)
     with pytest.raises(AssertionError):
         check()
+
+
+def test_array_inversion_is_the_scalar_one():
+    rng = np.random.default_rng(4)
+    nu = rng.uniform(0.0, 80.0, 3000)
+    u = rng.uniform(size=3000)
+    got = B.poisson_inverse_array(u, nu, np.exp(-nu))
+    ref = [B.poisson_inverse(float(a), float(b), float(np.exp(-b))) for a, b in zip(u, nu)]
+    assert np.array_equal(got, ref)
