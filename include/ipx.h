@@ -75,11 +75,47 @@ typedef enum {
  *       x G(m)/N_G, T_j the resolution-convolved e^{-Gamma t} x
  *       (cosh, sinh)(DeltaGamma t/2), (cos, sin)(Delta_m t), I_j their integrals
  *       over [0.3, 15], D_j = sum_k (integral f_k dOmega) C_kj.
+ *
+ * IPX_MODEL_ANGTIME_TAGGED (Example 2's flavour-tagged categories)
+ *   columns: the six of IPX_MODEL_ANGTIME, then qd = q (1 - 2 omega): q = +1
+ *            for a B_s tag, -1 for an anti-B_s tag, omega the event's mistag
+ *            probability (qd = 0: untagged)
+ *   theta:   as IPX_MODEL_ANGTIME                                       (12)
+ *   P as IPX_MODEL_ANGTIME with the cos and sin terms (j = 3, 4) scaled by
+ *   qd in the numerator and the normalisation alike: the normalised mixture
+ *   (1 - omega) P(B_s) + omega P(anti-B_s) of the two flavours' densities,
+ *   the anti-B_s one having c_k and d_k of the opposite sign.
+ *
+ * Both angular models take two per-dataset constants
+ * (ipx_dataset_set_angular): the normalisation weights xi_k (default the
+ * analytic integrals of a flat angular efficiency) and the S-P interference
+ * factor C_SP of the sample's KK-mass bin (default 1), which scales the
+ * S-P interference rows k = 8, 9, 10.
+ */
+/*
+ * IPX_MODEL_IPATIA (Example 1 with its Ipatia signal, normalised numerically)
+ *   columns: m [MeV], range [5200, 5500]
+ *   theta:   f, mu, sigma, lambda, zeta, beta, a, n, a2, n2, k        (11)
+ *   P(m) = f I(m - mu) / N_I + (1 - f) e^{-k (m - 5200)} / N_E, I the Ipatia
+ *   shape (Santos, Dupertuis, NIM A 764 (2014) 150): a generalised-hyperbolic
+ *   core q^{lambda - 1/2} K_{lambda - 1/2}(zeta q) e^{beta d}, d = m - mu,
+ *   q = sqrt(1 + d^2 / (A^2 sigma^2)), A^2 = zeta K_lambda(zeta) /
+ *   K_{lambda + 1}(zeta) (zeta = 0: q^{2 lambda - 1} e^{beta d} with
+ *   A^2 = -2 (lambda + 1), lambda < -1), and power-law tails A (B -+ d)^{-n}
+ *   below -a sigma and above a2 sigma matching the core's value and slope.
+ *   N_I = dm sum_g I(m_g - mu) over 16384 midpoints m_g of the range (step
+ *   dm), computed on the device at every call; N_E analytic.  Evaluated by
+ *   nll_eval and ipx_event_logp only (no analytic gradient, no plans, no
+ *   served requests: IPX_EINVAL).  Outside the domain (f in [0, 1],
+ *   sigma, a, n, a2, n2 > 0, zeta >= 0, and tails that fall away from the
+ *   core at both junctions) IPX_EDOMAIN.
  */
 typedef enum {
   IPX_MODEL_MASS = 1,
   IPX_MODEL_MASSTIME = 2,
-  IPX_MODEL_ANGTIME = 3
+  IPX_MODEL_ANGTIME = 3,
+  IPX_MODEL_ANGTIME_TAGGED = 4,
+  IPX_MODEL_IPATIA = 5
 } ipx_model;
 
 /* dataset creation flags */
@@ -133,6 +169,22 @@ IPX_API ipx_status ipx_dataset_column(const ipx_dataset *ds, int col, const doub
  * IPX_KEEP_ORDER).  Synchronous. */
 IPX_API ipx_status ipx_dataset_read(ipx_ctx *ctx, const ipx_dataset *ds, int col, int64_t offset, int64_t count,
                                     double *host);
+
+/*
+ * Per-dataset constants of the angular models (Example 2: each category has
+ * its own normalisation; a non-flat angular efficiency eps enters through the
+ * weights xi_k = integral eps(Omega) f_k(Omega) dOmega, obtained by the
+ * caller from simulated events or quadrature).
+ *   xi:   10 doubles (host memory), or NULL for the flat-efficiency values
+ *         (32 pi / 9 for k = 1, 2, 3, 7; 0 otherwise).
+ *   c_sp: the S-P interference factor of the sample's KK-mass bin (1 = none
+ *         of the interference is lost).
+ * Applies to every later evaluation of the dataset (plain, batched, served,
+ * simultaneous); requests already submitted keep the values they were
+ * hoisted with.  IPX_EINVAL for a dataset of another model or non-finite
+ * values.
+ */
+IPX_API ipx_status ipx_dataset_set_angular(ipx_ctx *ctx, ipx_dataset *ds, const double *xi, double c_sp);
 
 /*
  * NLL of the dataset at theta (np = ipx_model_nparams(model) doubles).
@@ -215,6 +267,33 @@ IPX_API ipx_status nll_eval_batch(ipx_ctx *ctx, ipx_plan *plan, const double *th
                                   double *nll, double *grad, void *stream);
 
 /*
+ * Simultaneous fit over categories (Example 2: the angular PDF fitted in bins
+ * of the KK mass and per flavour at once, each category normalised on its
+ * own, the P-wave and mixing parameters shared, the S-wave fraction and phase
+ * free per bin).  A simultaneous set holds ncat datasets of one angular model
+ * (IPX_MODEL_ANGTIME or IPX_MODEL_ANGTIME_TAGGED), dataset c in KK-mass bin
+ * bin[c] (0 <= bin[c] < nbins; the bin's C_SP is the dataset's, see
+ * ipx_dataset_set_angular).  Its parameter vector (np = 10 + 2 nbins) is
+ *   fL, fperp, delta_par, delta_perp, Gamma, DeltaGamma, Delta_m, phi_s,
+ *   mu_m, sigma_m, then Fs_b, delta_S_b for b = 0 .. nbins - 1,
+ * category c being evaluated at (fL, fperp, Fs_bin, delta_par, delta_perp,
+ * delta_S_bin, Gamma, DeltaGamma, Delta_m, phi_s, mu_m, sigma_m).
+ * nll_sim returns the sum of the categories' NLLs (added in category order)
+ * and, if grad is not NULL, its gradient (np doubles); all categories run in
+ * one batched launch (a plan over the datasets, created with the set).  A
+ * category outside its domain, or with a non-finite likelihood, makes the
+ * result +inf (NaN gradient) and the call return IPX_EDOMAIN.  The datasets
+ * cannot be destroyed before the set (IPX_EBUSY).
+ */
+typedef struct ipx_sim ipx_sim;
+IPX_API ipx_status ipx_sim_create(ipx_ctx *ctx, int ncat, ipx_dataset *const *ds, const int *bin, int nbins,
+                                  ipx_sim **out);
+IPX_API void ipx_sim_destroy(ipx_sim *sim);
+IPX_API int ipx_sim_nparams(const ipx_sim *sim);
+IPX_API ipx_status nll_sim(ipx_ctx *ctx, ipx_sim *sim, const double *theta, int np, double *nll, double *grad,
+                           void *stream);
+
+/*
  * Launch schedule of a plan's per-event kernel: how its tiles are handed to
  * workgroups.  Every tile writes its own partials and the reduction sums them
  * in tile order, so results are bitwise the same under every schedule; only
@@ -226,13 +305,17 @@ IPX_API ipx_status nll_eval_batch(ipx_ctx *ctx, ipx_plan *plan, const double *th
  *               index (the first tile of every segment, then the second, ...).
  *   graph:      1 = each evaluation replays a HIP graph of its kernels
  *               (captured on first use); 0 = the kernels are launched directly.
- * New plans start with {0, 0, 1}.  ipx_plan_set_schedule synchronises the
+ *   variant:    the per-event kernel's build (register budget and so waves per
+ *               SIMD; see ipx_schedule.variant).
+ * New plans start with {0, 0, 1, 0}.  ipx_plan_set_schedule synchronises the
  * context's stream and drops the plan's captured graphs (recaptured on the next
- * call).  IPX_EINVAL for negative workgroups, an unknown order or graph not 0/1.
+ * call).  IPX_EINVAL for negative workgroups, an unknown order, graph not 0/1
+ * or a variant the model does not have.
  *
  * ipx_plan_autotune times the candidate schedules (one workgroup per tile,
  * 8 and 16 workgroups per compute unit; both orders when the plan has several
- * segments; graph replay and direct launches) at theta (nb x np host doubles,
+ * segments; graph replay and direct launches; both kernel variants of the
+ * angular model) at theta (nb x np host doubles,
  * as for nll_eval_batch; grad != 0 times the gradient form) in `reps` rounds:
  * in each round every candidate is set and evaluated twice, the second call
  * timed.  It keeps the candidate with the smallest median wall time per call
@@ -244,6 +327,10 @@ typedef struct {
   int workgroups;
   int order;
   int graph;
+  int variant;   /* per-event kernel build: 0 = default register budget; 1 (angular
+                    model only) = the alternative: the gradient kernel at 3 waves
+                    per SIMD (no register spills), the NLL-only kernel at 6 (at
+                    most 80 registers); other models accept 0 only */
 } ipx_schedule;
 typedef struct {
   ipx_schedule schedule;
@@ -285,12 +372,17 @@ typedef struct {
   int slots;               /* concurrent requests on the device (<= 64; 0 = 32) */
   size_t scratch_bytes;    /* scratch budget for admitted requests (0 = 2 GiB) */
   int workgroups;          /* persistent workgroups, one of which polls the host
-                              (>= 2; 0 = 2 per compute unit) */
+                              (>= 2; 0 = 3 per compute unit) */
   int idle_iterations;     /* consecutive polls that find no new request and no
                               claimable work before the device loop exits
                               (0 = 20000, a few tens of ms); it is relaunched
                               when work arrives */
   int max_pending;         /* waiting requests accepted (0 = unlimited) */
+  int policy;              /* how workgroups pick among admitted requests:
+                              0 = the oldest admitted request first (its tiles
+                              are all claimed before a younger one's),
+                              1 = each workgroup from its own starting slot
+                              (admitted requests share the workgroups) */
 } ipx_server_cfg;
 typedef struct {
   const ipx_dataset *ds;
@@ -388,6 +480,73 @@ IPX_API ipx_status ipx_count_bad_events(ipx_ctx *ctx, const ipx_dataset *ds, con
  */
 IPX_API ipx_status ipx_event_logp(ipx_ctx *ctx, const ipx_dataset *ds, const double *theta, int np, double *out,
                                   void *stream);
+
+/*
+ * Binned path (Examples 3-5 of the paper on the binned side: a binned
+ * maximum-likelihood fit of a mass spectrum; CL_s from binned pseudo-data,
+ * with a signal shape filled per bin and convolved with a Gaussian on top of
+ * an exponential background; binned toys as a Poisson count per bin).
+ *
+ * A histogram has nbins equal bins on [lo, hi) (width dx, centres
+ * x_b = lo + (b + 1/2) dx), a signal template and observed counts.  The
+ * template is a Gaussian core exp(-(x_b - mu)^2 / (2 sigma_core^2)) smeared
+ * by a Gaussian of width sigma_smear (ipx_smear) and normalised to unit sum,
+ * all computed on the device at creation.  The background template is
+ * e_b = exp(-k (x_b - x_0)) / Z, Z = sum_b exp(-k b dx), and the expected
+ * counts are nu_b = ns s_b + nb e_b.  Parameters theta = (ns, nb, k).
+ *
+ * ipx_smear: S_b = sum_j h_j g(x_b - x_j) dx over n bins of width dx, g the
+ *   unit Gaussian density of width sigma (the rectangle rule of the
+ *   convolution integral, no wrap-around); h and out are DEVICE arrays of n
+ *   doubles (caller-owned, not overlapping); synchronous on `stream`.
+ * ipx_hist_create: counts (host, nullable = all zero) are non-negative
+ *   integers stored as doubles; 1 <= nbins <= 2^24.
+ * ipx_hist_read: which = 0 copies the signal template, 1 the counts, to host
+ *   memory (nbins doubles).
+ * nll_binned: NLL = sum_b [nu_b - n_b ln nu_b] (the constant sum_b ln n_b!
+ *   dropped) and, if grad is not NULL, its gradient in (ns, nb, k); np = 3;
+ *   IPX_EDOMAIN (+inf) for ns < 0, nb < 0, non-finite values, or a
+ *   non-positive expected count where counts were seen.
+ * ipx_binned_toy: the counts of one toy (host, nbins doubles) of hypothesis
+ *   hyp (0: background only, nu_b = nb e_b; 1: signal + background): n_b is
+ *   the smallest k with u <= F(k), F the Poisson CDF of nu_b summed from
+ *   k = 0 (p_0 = e^{-nu}, p_k = p_{k-1} nu / k), u from Philox4x64-10 with
+ *   key (seed, 0xB1), counter (b / 4, toy, hyp, 0), word b % 4, as
+ *   ((word >> 12) + 0.5) 2^-52; at most floor(nu + 30 sqrt(nu + 1) + 30).
+ *   Every expected count must be below 700 (e^{-nu} must not underflow),
+ *   else IPX_EDOMAIN (also for cls_toys).
+ * cls_toys: q = 2 sum_b [s_b - n_b ln(1 + s_b / b_b)] (s_b = ns S_b,
+ *   b_b = nb e_b) for the observed counts (q_obs) and for ntoys toys of each
+ *   hypothesis (toy ids 0 .. ntoys - 1, seed as above); n_b / n_sb = the
+ *   toys with q >= q_obs, CL_b = n_b / ntoys, CL_s+b = n_sb / ntoys,
+ *   CL_s = CL_s+b / CL_b.  q_toys (host, nullable): 2 ntoys doubles, the
+ *   background-only toys' q then the signal + background toys'.  nb must be
+ *   positive; 1 <= ntoys <= 2^24.  The toy kernel is timed by
+ *   ipx_timing_enable / ipx_timing_read like the evaluation kernels.
+ */
+typedef struct ipx_hist ipx_hist;
+typedef struct {
+  double cl_sb;
+  double cl_b;
+  double cl_s;
+  double q_obs;
+  int64_t n_sb;
+  int64_t n_b;
+} ipx_cls_result;
+IPX_API ipx_status ipx_smear(ipx_ctx *ctx, int n, double dx, double sigma, const double *h, double *out,
+                             void *stream);
+IPX_API ipx_status ipx_hist_create(ipx_ctx *ctx, int nbins, double lo, double hi, double mu, double sigma_core,
+                                   double sigma_smear, const double *counts, ipx_hist **out);
+IPX_API ipx_status ipx_hist_destroy(ipx_ctx *ctx, ipx_hist *hist);
+IPX_API int ipx_hist_nbins(const ipx_hist *hist);
+IPX_API ipx_status ipx_hist_read(ipx_ctx *ctx, const ipx_hist *hist, int which, double *host);
+IPX_API ipx_status ipx_hist_set_counts(ipx_ctx *ctx, ipx_hist *hist, const double *counts);
+IPX_API ipx_status nll_binned(ipx_ctx *ctx, const ipx_hist *hist, const double *theta, int np, double *nll,
+                              double *grad, void *stream);
+IPX_API ipx_status ipx_binned_toy(ipx_ctx *ctx, const ipx_hist *hist, const double *theta, uint64_t seed, int hyp,
+                                  uint64_t toy, double *counts);
+IPX_API ipx_status cls_toys(ipx_ctx *ctx, ipx_hist *hist, const double *theta, uint64_t seed, int ntoys,
+                            ipx_cls_result *result, double *q_toys);
 
 /*
  * Timing of the dominant kernel of nll_eval/nll_grad, measured with HIP events

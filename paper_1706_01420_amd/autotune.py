@@ -68,12 +68,14 @@ def tune_plan(ipx, ctx, plan, model, theta, sizes, grad=True, reps=5, path=None,
     cache = load(path)
     entry = cache.get(k)
     if entry is not None:
-        sched = {"workgroups": entry["workgroups"], "order": entry["order"], "graph": entry.get("graph", 1)}
+        sched = {"workgroups": entry["workgroups"], "order": entry["order"], "graph": entry.get("graph", 1),
+                 "variant": entry.get("variant", 0)}
         ipx.ipx_plan_set_schedule(plan, **sched)
         return sched, "cache"
     best, us, rows = ipx.ipx_plan_autotune(ctx, plan, theta, grad=grad, reps=reps)
     cache = load(path)  # another process may have written meanwhile
-    cache[k] = {"workgroups": best["workgroups"], "order": best["order"], "graph": best["graph"], "us": us,
-                "candidates": [[r[0]["workgroups"], r[0]["order"], r[0]["graph"], r[1]] for r in rows]}
+    cache[k] = {"workgroups": best["workgroups"], "order": best["order"], "graph": best["graph"],
+                "variant": best["variant"], "us": us,
+                "candidates": [[r[0]["workgroups"], r[0]["order"], r[0]["graph"], r[0]["variant"], r[1]] for r in rows]}
     save(cache, path)
     return best, "tuned"

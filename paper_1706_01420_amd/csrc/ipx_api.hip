@@ -34,6 +34,8 @@
 #include "ipx_toys.h"
 #include "ipx_batch.h"
 #include "ipx_serve.h"
+#include "ipx_binned.h"
+#include "ipx_ipatia.h"
 
 using namespace ipx;
 
@@ -80,7 +82,7 @@ struct ipx_dataset {
   int64_t n_pad = 0;
   int ncols = 0;
   double* base = nullptr;          // owned column storage (nullptr when borrowed)
-  const double* cols[6] = {};
+  const double* cols[7] = {};
   const double* w = nullptr;
   int64_t n_tiles = 0;
   bool sorted = false;             // events stored in resolution-band order
@@ -90,10 +92,15 @@ struct ipx_dataset {
   size_t bytes = 0;
   struct ipx_plan* self = nullptr; // one-dataset plan used by nll_eval / nll_grad
   int plan_refs = 0;               // user plans that reference this dataset
+  AngSettings ang = ang_settings_default();  // angular models: efficiency weights, C_SP
+  double* aux = nullptr;           // Ipatia model: constants, grid partials, 1/N_I, tile partials, total
 };
 
-static const int kNParams[4] = {-1, 4, 7, 12};
-static const int kNCols[4] = {-1, 1, 3, 6};
+static const int kNParams[6] = {-1, 4, 7, 12, 12, 11};
+static const int kNCols[6] = {-1, 1, 3, 6, 7, 1};
+static bool angular_model(int model) { return model == 3 || model == 4; }
+static bool time_model(int model) { return model >= 2 && model <= 4; }
+constexpr int kModelIpatia = 5;
 
 // ---------------------------------------------------------------------------
 // Event-store ordering for the models with a decay time: by the band of
@@ -185,8 +192,8 @@ const char* ipx_last_error(void) { return g_last_error.c_str(); }
 
 static ipx_status noalloc_setup(int device);
 
-int ipx_model_nparams(int model) { return (model >= 1 && model <= 3) ? kNParams[model] : -1; }
-int ipx_model_ncols(int model) { return (model >= 1 && model <= 3) ? kNCols[model] : -1; }
+int ipx_model_nparams(int model) { return (model >= 1 && model <= 5) ? kNParams[model] : -1; }
+int ipx_model_ncols(int model) { return (model >= 1 && model <= 5) ? kNCols[model] : -1; }
 
 ipx_status ipx_create(int device, ipx_ctx** out) {
   if (!out) return fail(IPX_EINVAL, "ipx_create: out is NULL");
@@ -240,6 +247,7 @@ static void free_dataset(ipx_dataset* d) {
   if (d->partials) (void)hipFree(d->partials);
   if (d->out_dev) (void)hipFree(d->out_dev);
   if (d->out_host) (void)hipHostFree(d->out_host);
+  if (d->aux) (void)hipFree(d->aux);
   delete d;
 }
 
@@ -247,7 +255,7 @@ ipx_status ipx_dataset_create(ipx_ctx* ctx, int model, int64_t n, const double* 
                               const double* w, unsigned flags, ipx_dataset** out) {
   if (!ctx || !out) return fail(IPX_EINVAL, "ipx_dataset_create: NULL ctx/out");
   *out = nullptr;
-  if (model < 1 || model > 3) return fail(IPX_EINVAL, "ipx_dataset_create: unknown model %d", model);
+  if (model < 1 || model > 5) return fail(IPX_EINVAL, "ipx_dataset_create: unknown model %d", model);
   if (ncols != kNCols[model])
     return fail(IPX_EINVAL, "ipx_dataset_create: model %d takes %d columns, got %d", model, kNCols[model], ncols);
   if (n < 0) return fail(IPX_EINVAL, "ipx_dataset_create: negative size");
@@ -292,7 +300,7 @@ ipx_status ipx_dataset_create(ipx_ctx* ctx, int model, int64_t n, const double* 
       free_dataset(d);
       return fail(IPX_EDEVICE, "ipx_dataset_create: copy failed: %s", hipGetErrorString(e));
     }
-    if (model >= 2 && !(flags & IPX_KEEP_ORDER) && n >= 2 && n <= 0x7fffffff) {
+    if (time_model(model) && !(flags & IPX_KEEP_ORDER) && n >= 2 && n <= 0x7fffffff) {
       ipx_status st = sort_events(d, ctx->stream);
       if (st != IPX_OK) {
         free_dataset(d);
@@ -324,6 +332,21 @@ ipx_status ipx_dataset_destroy(ipx_ctx* ctx, ipx_dataset* d) {
 size_t ipx_dataset_bytes(const ipx_dataset* d) { return d ? d->bytes : 0; }
 int64_t ipx_dataset_size(const ipx_dataset* d) { return d ? d->n : -1; }
 int ipx_dataset_model(const ipx_dataset* d) { return d ? d->model : -1; }
+
+ipx_status ipx_dataset_set_angular(ipx_ctx* ctx, ipx_dataset* d, const double* xi, double c_sp) {
+  if (!ctx || !d) return fail(IPX_EINVAL, "ipx_dataset_set_angular: NULL argument");
+  if (!angular_model(d->model))
+    return fail(IPX_EINVAL, "ipx_dataset_set_angular: model %d has no angular constants", d->model);
+  AngSettings a = ang_settings_default();
+  if (xi)
+    for (int k = 0; k < 10; ++k) a.xi[k] = xi[k];
+  a.c_sp = c_sp;
+  for (int k = 0; k < 10; ++k)
+    if (!std::isfinite(a.xi[k])) return fail(IPX_EINVAL, "ipx_dataset_set_angular: xi[%d] is not finite", k);
+  if (!std::isfinite(c_sp)) return fail(IPX_EINVAL, "ipx_dataset_set_angular: c_sp is not finite");
+  d->ang = a;
+  return IPX_OK;
+}
 
 ipx_status ipx_dataset_column(const ipx_dataset* d, int col, const double** p) {
   if (!d || !p) return fail(IPX_EINVAL, "ipx_dataset_column: NULL argument");
@@ -530,7 +553,7 @@ extern "C" ipx_status ipx_math_eval(ipx_ctx* ctx, int fn, int64_t n, const doubl
 // ---------------------------------------------------------------------------
 static EventCols cols_of(const ipx_dataset* d) {
   EventCols c;
-  for (int i = 0; i < 6; ++i) c.c[i] = d->cols[i];
+  for (int i = 0; i < 7; ++i) c.c[i] = d->cols[i];
   c.w = d->w;
   c.n = d->n;
   return c;
@@ -585,7 +608,7 @@ static void gen_setup(int model, const double* th, uint64_t seed, uint64_t toy, 
     g.M = (1.0 + 1e-3) * M;
   } else {
     AngTimeHoist a;
-    hoist_angtime_values(th, a.k, a.ng);
+    hoist_angtime(th, ang_settings_default(), a);
     double M = 0.0;
     for (int k = 0; k < 10; ++k) {
       double s = 0.0;
@@ -972,7 +995,7 @@ struct ipx_plan {
   SegInfo* d_segs = nullptr;
   TileRef* d_tiles = nullptr;
   int64_t n_tiles = 0;
-  ipx_schedule sched{0, 0, 1};     // launch schedule (results do not depend on it)
+  ipx_schedule sched{0, 0, 1, 0};  // launch schedule (results do not depend on it)
   void* h_consts = nullptr;        // pinned [constants | active flags], written by the host
   unsigned char* h_active = nullptr;
   void* d_consts = nullptr;        // the same block's device address (read by the kernels)
@@ -1020,6 +1043,9 @@ static std::vector<TileRef> tile_table(const ipx_plan* p, int order) {
 static size_t const_size_of(int model) {
   return model == 1 ? sizeof(MassConst) : model == 2 ? sizeof(MassTimeConst) : sizeof(AngTimeConst);
 }
+static int nacc_of(int model, bool grad) {
+  return !grad ? 1 : model == 1 ? kAccMass : model == 2 ? kAccMassTime : kAccAngTime;
+}
 
 static ipx_status plan_create(ipx_ctx* ctx, int nb, ipx_dataset* const* ds, ipx_plan** out, bool counted);
 extern "C" ipx_status ipx_plan_create(ipx_ctx* ctx, int nb, ipx_dataset* const* ds, ipx_plan** out) {
@@ -1030,6 +1056,8 @@ static ipx_status plan_create(ipx_ctx* ctx, int nb, ipx_dataset* const* ds, ipx_
   *out = nullptr;
   if (nb <= 0) return fail(IPX_EINVAL, "ipx_plan_create: empty batch");
   const int model = ds[0] ? ds[0]->model : 0;
+  if (model == kModelIpatia)
+    return fail(IPX_EINVAL, "ipx_plan_create: the Ipatia model is evaluated by nll_eval only");
   for (int j = 0; j < nb; ++j) {
     if (!ds[j]) return fail(IPX_EINVAL, "ipx_plan_create: dataset %d is NULL", j);
     if (ds[j]->model != model) return fail(IPX_EINVAL, "ipx_plan_create: datasets of different models");
@@ -1089,6 +1117,94 @@ extern "C" void ipx_plan_destroy(ipx_plan* p) {
   free_plan(p);
 }
 
+// ---------------------------------------------------------------------------
+// Simultaneous fit over categories: a plan over the categories' datasets,
+// evaluated in one batched launch; the categories' NLLs are added in
+// category order and their 12-parameter gradients are added at the positions
+// their parameters take in the simultaneous vector.
+// ---------------------------------------------------------------------------
+constexpr int kSimShared = 10;   // fL, fperp, dpa, dpe, Gamma, DeltaGamma, Dm, phis, mu_m, sigma_m
+struct ipx_sim {
+  ipx_ctx* ctx = nullptr;
+  ipx_plan* plan = nullptr;
+  int ncat = 0, nbins = 0;
+  std::vector<int> bin;
+  std::vector<double> th, f, g;   // per-category parameters, NLLs, gradients
+};
+
+// Position in the simultaneous vector of parameter j (model order) of bin b.
+static int sim_index(int j, int b) {
+  static const int kMap[12] = {0, 1, -1, 2, 3, -2, 4, 5, 6, 7, 8, 9};
+  const int m = kMap[j];
+  return m == -1 ? kSimShared + 2 * b : m == -2 ? kSimShared + 2 * b + 1 : m;
+}
+
+extern "C" ipx_status ipx_sim_create(ipx_ctx* ctx, int ncat, ipx_dataset* const* ds, const int* bin, int nbins,
+                                     ipx_sim** out) {
+  if (!ctx || !ds || !bin || !out) return fail(IPX_EINVAL, "ipx_sim_create: NULL argument");
+  *out = nullptr;
+  if (ncat <= 0 || nbins <= 0 || nbins > (1 << 20)) return fail(IPX_EINVAL, "ipx_sim_create: ncat %d, nbins %d", ncat, nbins);
+  for (int c = 0; c < ncat; ++c) {
+    if (!ds[c]) return fail(IPX_EINVAL, "ipx_sim_create: dataset %d is NULL", c);
+    if (!angular_model(ds[c]->model)) return fail(IPX_EINVAL, "ipx_sim_create: dataset %d is not of an angular model", c);
+    if (bin[c] < 0 || bin[c] >= nbins) return fail(IPX_EINVAL, "ipx_sim_create: bin %d of category %d", bin[c], c);
+  }
+  ipx_plan* p = nullptr;
+  ipx_status st = plan_create(ctx, ncat, ds, &p, true);
+  if (st != IPX_OK) return st;
+  ipx_sim* S = new (std::nothrow) ipx_sim();
+  if (!S) {
+    ipx_plan_destroy(p);
+    return fail(IPX_ENOMEM, "ipx_sim_create: host allocation failed");
+  }
+  S->ctx = ctx;
+  S->plan = p;
+  S->ncat = ncat;
+  S->nbins = nbins;
+  S->bin.assign(bin, bin + ncat);
+  S->th.resize((size_t)ncat * 12);
+  S->f.resize(ncat);
+  S->g.resize((size_t)ncat * 12);
+  *out = S;
+  return IPX_OK;
+}
+
+extern "C" void ipx_sim_destroy(ipx_sim* S) {
+  if (!S) return;
+  ipx_plan_destroy(S->plan);
+  delete S;
+}
+
+extern "C" int ipx_sim_nparams(const ipx_sim* S) { return S ? kSimShared + 2 * S->nbins : -1; }
+
+extern "C" ipx_status nll_sim(ipx_ctx* ctx, ipx_sim* S, const double* theta, int np, double* nll, double* grad,
+                              void* stream) {
+  if (!ctx || !S || !theta || !nll) return fail(IPX_EINVAL, "nll_sim: NULL argument");
+  if (S->ctx != ctx) return fail(IPX_EINVAL, "nll_sim: set belongs to another context");
+  if (np != kSimShared + 2 * S->nbins)
+    return fail(IPX_EINVAL, "nll_sim: the set takes %d parameters, got %d", kSimShared + 2 * S->nbins, np);
+  for (int c = 0; c < S->ncat; ++c)
+    for (int j = 0; j < 12; ++j) S->th[(size_t)c * 12 + j] = theta[sim_index(j, S->bin[c])];
+  const ipx_status st = nll_eval_batch(ctx, S->plan, S->th.data(), nullptr, S->f.data(),
+                                       grad ? S->g.data() : nullptr, stream);
+  if (st == IPX_EDOMAIN) {
+    *nll = std::numeric_limits<double>::infinity();
+    if (grad)
+      for (int i = 0; i < np; ++i) grad[i] = std::numeric_limits<double>::quiet_NaN();
+    return fail(IPX_EDOMAIN, "nll_sim: a category is outside its domain or has a non-finite likelihood");
+  }
+  if (st != IPX_OK) return st;
+  double tot = 0.0;
+  for (int c = 0; c < S->ncat; ++c) tot += S->f[c];
+  *nll = tot;
+  if (grad) {
+    for (int i = 0; i < np; ++i) grad[i] = 0.0;
+    for (int c = 0; c < S->ncat; ++c)
+      for (int j = 0; j < 12; ++j) grad[sim_index(j, S->bin[c])] += S->g[(size_t)c * 12 + j];
+  }
+  return IPX_OK;
+}
+
 // The body of one batched evaluation, as stream operations (captured once
 // into a graph per plan and mode).
 static ipx_status timing_begin(ipx_ctx* ctx, hipStream_t s) {
@@ -1111,9 +1227,12 @@ static ipx_status timing_end(ipx_ctx* ctx, hipStream_t s) {
 // then the per-segment reductions writing nacc totals per segment to `out`.
 // Shared by plans and the allocation-free entry point, so a dataset's tiles
 // run the same instructions whichever way it is evaluated.
+// Waves-per-SIMD targets of the angular kernel variants (schedule.variant = 1).
+constexpr int kAltWavesGrad = 3, kAltWavesNll = 6;
+
 static ipx_status launch_eval(int model, bool grad, unsigned grid, const SegInfo* segs, const TileRef* tiles,
                               int64_t n_tiles, const void* consts, const unsigned char* active, int nb, double* out,
-                              hipStream_t s, ipx_ctx* timer) {
+                              hipStream_t s, ipx_ctx* timer, int variant = 0) {
   int nacc = 1;
   {
     ipx_status st = timing_begin(timer, s);
@@ -1127,10 +1246,17 @@ static ipx_status launch_eval(int model, bool grad, unsigned grid, const SegInfo
     nacc = grad ? kAccMassTime : 1;
     if (grad) hipLaunchKernelGGL((k_nll_batch<2, true>), dim3(grid), dim3(kThreads), 0, s, segs, tiles, n_tiles, (const MassTimeConst*)consts, active);
     else hipLaunchKernelGGL((k_nll_batch<2, false>), dim3(grid), dim3(kThreads), 0, s, segs, tiles, n_tiles, (const MassTimeConst*)consts, active);
+  } else if (model == 3) {
+    nacc = grad ? kAccAngTime : 1;
+    const AngTimeConst* k3 = (const AngTimeConst*)consts;
+    if (grad && variant == 1) hipLaunchKernelGGL((k_angtime_batch<true, false, kAltWavesGrad>), dim3(grid), dim3(kThreads), 0, s, segs, tiles, n_tiles, k3, active);
+    else if (grad) hipLaunchKernelGGL((k_angtime_batch<true>), dim3(grid), dim3(kThreads), 0, s, segs, tiles, n_tiles, k3, active);
+    else if (variant == 1) hipLaunchKernelGGL((k_angtime_batch<false, false, kAltWavesNll>), dim3(grid), dim3(kThreads), 0, s, segs, tiles, n_tiles, k3, active);
+    else hipLaunchKernelGGL((k_angtime_batch<false>), dim3(grid), dim3(kThreads), 0, s, segs, tiles, n_tiles, k3, active);
   } else {
     nacc = grad ? kAccAngTime : 1;
-    if (grad) hipLaunchKernelGGL((k_angtime_batch<true>), dim3(grid), dim3(kThreads), 0, s, segs, tiles, n_tiles, (const AngTimeConst*)consts, active);
-    else hipLaunchKernelGGL((k_angtime_batch<false>), dim3(grid), dim3(kThreads), 0, s, segs, tiles, n_tiles, (const AngTimeConst*)consts, active);
+    if (grad) hipLaunchKernelGGL((k_angtime_batch<true, true>), dim3(grid), dim3(kThreads), 0, s, segs, tiles, n_tiles, (const AngTimeConst*)consts, active);
+    else hipLaunchKernelGGL((k_angtime_batch<false, true>), dim3(grid), dim3(kThreads), 0, s, segs, tiles, n_tiles, (const AngTimeConst*)consts, active);
   }
   HIP_TRY(hipGetLastError());
   {
@@ -1152,7 +1278,7 @@ static ipx_status enqueue_batch(ipx_plan* p, bool grad, hipStream_t s, ipx_ctx* 
   const int64_t wg = p->sched.workgroups > 0 ? std::min<int64_t>(p->sched.workgroups, p->n_tiles) : p->n_tiles;
   const unsigned grid = (unsigned)std::max<int64_t>(1, wg);
   return launch_eval(p->model, grad, grid, p->d_segs, p->d_tiles, p->n_tiles, p->d_consts, p->d_active, p->nb,
-                     p->h_out_dev, s, timer);
+                     p->h_out_dev, s, timer, p->sched.variant);
 }
 
 extern "C" ipx_status nll_eval_batch(ipx_ctx* ctx, ipx_plan* p, const double* theta, const unsigned char* active,
@@ -1183,7 +1309,7 @@ extern "C" ipx_status nll_eval_batch(ipx_ctx* ctx, ipx_plan* p, const double* th
     char* dst = (char*)p->h_consts + (size_t)j * p->const_size;
     if (model == 1) { h1[j] = hoist_mass(th); std::memcpy(dst, &h1[j].k, sizeof(MassConst)); }
     else if (model == 2) { h2[j] = hoist_masstime(th); std::memcpy(dst, &h2[j].k, sizeof(MassTimeConst)); }
-    else { hoist_angtime_values(th, h3[j].k, h3[j].ng); std::memcpy(dst, &h3[j].k, sizeof(AngTimeConst)); }
+    else { hoist_angtime(th, p->ds[j]->ang, h3[j]); std::memcpy(dst, &h3[j].k, sizeof(AngTimeConst)); }
   }
   if (n_active > 0) {
     hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
@@ -1211,7 +1337,7 @@ extern "C" ipx_status nll_eval_batch(ipx_ctx* ctx, ipx_plan* p, const double* th
     if (p->sched.graph) HIP_TRY(hipGraphLaunch(p->exec[mode], s));
     // the derivative tables of the angular coefficients serve only the
     // gradient's Jacobian: computed while the kernels run
-    if (model == 3 && grad)
+    if (angular_model(model) && grad)
       for (int j = 0; j < nb; ++j)
         if (p->h_active[j]) angtime_derivatives(theta + (size_t)j * np, h3[j]);
     HIP_TRY(hipStreamSynchronize(s));
@@ -1249,6 +1375,8 @@ extern "C" ipx_status ipx_plan_set_schedule(ipx_plan* p, const ipx_schedule* sc)
   if (sc->workgroups < 0) return fail(IPX_EINVAL, "ipx_plan_set_schedule: workgroups %d < 0", sc->workgroups);
   if (sc->order < 0 || sc->order > 1) return fail(IPX_EINVAL, "ipx_plan_set_schedule: unknown order %d", sc->order);
   if (sc->graph < 0 || sc->graph > 1) return fail(IPX_EINVAL, "ipx_plan_set_schedule: graph must be 0 or 1");
+  if (sc->variant < 0 || sc->variant > (p->model == 3 ? 1 : 0))
+    return fail(IPX_EINVAL, "ipx_plan_set_schedule: kernel variant %d for model %d", sc->variant, p->model);
   HIP_TRY(hipSetDevice(p->ctx->device));
   HIP_TRY(hipStreamSynchronize(p->ctx->stream));
   if (sc->order != p->sched.order) {
@@ -1283,9 +1411,10 @@ extern "C" ipx_status ipx_plan_autotune(ipx_ctx* ctx, ipx_plan* p, const double*
   // replayed as a graph or launched directly
   const int cu = std::max(1, ctx->n_cu);
   std::vector<ipx_schedule> cand;
-  for (int graph = 1; graph >= 0; --graph)
-    for (int order = 0; order <= (p->nb > 1 ? 1 : 0); ++order)
-      for (int wg : {0, 16 * cu, 8 * cu}) cand.push_back(ipx_schedule{wg, order, graph});
+  for (int variant = 0; variant <= (p->model == 3 ? 1 : 0); ++variant)
+    for (int graph = 1; graph >= 0; --graph)
+      for (int order = 0; order <= (p->nb > 1 ? 1 : 0); ++order)
+        for (int wg : {0, 16 * cu, 8 * cu}) cand.push_back(ipx_schedule{wg, order, graph, variant});
   std::vector<double> nll(p->nb), g(grad ? (size_t)p->nb * np : 0);
   // rounds over all candidates (so that clock drift does not favour one):
   // in each, a candidate is set, evaluated once untimed (graph capture, first
@@ -1412,10 +1541,7 @@ static void pool_free(ipx_server* S, size_t off, size_t bytes) {
 
 static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
-static int serve_nacc(int model, int grad) {
-  if (!grad) return 1;
-  return model == 1 ? kAccMass : model == 2 ? kAccMassTime : kAccAngTime;
-}
+static int serve_nacc(int model, int grad) { return nacc_of(model, grad != 0); }
 
 static size_t request_bytes(const ipx_dataset* d, int grad) {
   return align256((size_t)std::max<int64_t>(1, d->n_tiles) * serve_nacc(d->model, grad) * sizeof(double));
@@ -1525,7 +1651,7 @@ static void serve_worker(ipx_server* S) {
       if (e == hipSuccess) e = hipMemsetD32Async((hipDeviceptr_t)&S->ctl->quit, 0, 1, S->stream);
       if (e == hipSuccess) {
         hipLaunchKernelGGL(k_serve, dim3((unsigned)S->cfg.workgroups), dim3(kThreads), 0, S->stream, S->hs_dev,
-                           S->ctl, S->dd, S->st, nslots, S->cfg.idle_iterations);
+                           S->ctl, S->dd, S->st, nslots, S->cfg.idle_iterations, S->cfg.policy);
         e = hipGetLastError();
       }
       if (e == hipSuccess) e = hipEventRecord(S->kernel_done, S->stream);
@@ -1601,7 +1727,9 @@ extern "C" ipx_status ipx_server_start(ipx_ctx* ctx, const ipx_server_cfg* cfg, 
   if (c.slots <= 0) c.slots = 32;
   if (c.slots > kServeMaxSlots) return fail(IPX_EINVAL, "ipx_server_start: at most %d slots", kServeMaxSlots);
   if (c.scratch_bytes == 0) c.scratch_bytes = (size_t)1 << 31;
-  if (c.workgroups == 0) c.workgroups = 2 * std::max(1, ctx->n_cu);
+  if (c.workgroups == 0) c.workgroups = 3 * std::max(1, ctx->n_cu);
+  if (c.policy != kServeOldestFirst && c.policy != kServeSpread)
+    return fail(IPX_EINVAL, "ipx_server_start: unknown claim policy %d", c.policy);
   if (c.workgroups < 2) return fail(IPX_EINVAL, "ipx_server_start: at least 2 workgroups (one polls the host)");
   if (c.idle_iterations <= 0) c.idle_iterations = 20000;
   HIP_TRY(hipSetDevice(ctx->device));
@@ -1645,6 +1773,7 @@ extern "C" ipx_status ipx_submit(ipx_server* S, const ipx_request* q, uint64_t* 
   ServerUse use(S);
   ipx_dataset* d = const_cast<ipx_dataset*>(q->ds);
   const int model = d->model, np = kNParams[model];
+  if (model == kModelIpatia) return fail(IPX_EINVAL, "ipx_submit: the Ipatia model is evaluated by nll_eval only");
   if (q->np != np) return fail(IPX_EINVAL, "ipx_submit: model %d takes %d parameters", model, np);
   ServeReq* r = new (std::nothrow) ServeReq();
   if (!r) return fail(IPX_ENOMEM, "ipx_submit: host allocation failed");
@@ -1662,7 +1791,7 @@ extern "C" ipx_status ipx_submit(ipx_server* S, const ipx_request* q, uint64_t* 
     if (model == 1) r->h1 = hoist_mass(r->theta);
     else if (model == 2) r->h2 = hoist_masstime(r->theta);
     else {
-      hoist_angtime_values(r->theta, r->h3.k, r->h3.ng);
+      hoist_angtime(r->theta, d->ang, r->h3);
       if (r->grad) angtime_derivatives(r->theta, r->h3);
     }
   }
@@ -1834,10 +1963,10 @@ static ipx_status check_theta(int model, const double* theta, int np, double* nl
                                 : "parameters outside the domain of model %d", model);
 }
 
-static void hoist_eval(int model, const double* theta, EvalHoist& h) {
+static void hoist_eval(int model, const double* theta, const AngSettings& set, EvalHoist& h) {
   if (model == 1) { h.h1 = hoist_mass(theta); h.consts = &h.h1.k; h.bytes = sizeof h.h1.k; }
   else if (model == 2) { h.h2 = hoist_masstime(theta); h.consts = &h.h2.k; h.bytes = sizeof h.h2.k; }
-  else { hoist_angtime_values(theta, h.h3.k, h.h3.ng); h.consts = &h.h3.k; h.bytes = sizeof h.h3.k; }
+  else { hoist_angtime(theta, set, h.h3); h.consts = &h.h3.k; h.bytes = sizeof h.h3.k; }
 }
 
 // NLL and gradient from the reduced totals a[] (a[0] = sum of w ln P).
@@ -1858,12 +1987,109 @@ static ipx_status finish_eval(int model, const EvalHoist& h, const double* theta
   return IPX_OK;
 }
 
+// out[c] = sum of part[c * nwg .. c * nwg + nwg) in the fixed order of
+// reduce_component; grid (components).
+static __global__ __launch_bounds__(kThreads) void k_reduce_parts(const double* __restrict__ part, int nwg,
+                                                                  double* __restrict__ out) {
+  const double t = reduce_component(part + (int64_t)blockIdx.x * nwg, nwg);
+  if (threadIdx.x == 0) out[blockIdx.x] = t;
+}
+
+// ---------------------------------------------------------------------------
+// Ipatia model (nll_eval only): grid pass -> 1/N_I, tile pass, tile reduction.
+// The dataset's aux buffer: [constants | grid partials (64) | 1/N_I | total |
+// tile partials (n_tiles)].
+// ---------------------------------------------------------------------------
+constexpr size_t kIpaConstBytes = (sizeof(IpatiaConst) + 255) / 256 * 256;
+static double* ipa_part(ipx_dataset* d) { return (double*)((char*)d->aux + kIpaConstBytes); }
+static double* ipa_inv(ipx_dataset* d) { return ipa_part(d) + kIpatiaGridWg; }
+static double* ipa_total(ipx_dataset* d) { return ipa_inv(d) + 1; }
+static double* ipa_tiles(ipx_dataset* d) { return ipa_inv(d) + 2; }
+
+static __global__ __launch_bounds__(kThreads) void k_ipatia_tiles(EventCols cols, const IpatiaConst* __restrict__ kc,
+                                                                  double* __restrict__ partials, int64_t n_tiles) {
+  __shared__ RedBuf<1> red;
+  const IpatiaConst& c = *kc;
+  const double inv = *c.inv_norm;
+  const int64_t tile = blockIdx.x;
+  const int64_t base = tile * kTile;
+  double acc[1] = {0.0};
+#pragma unroll 1
+  for (int e = 0; e < kEventsPerLane; ++e) {
+    const unsigned j = threadIdx.x + (unsigned)e * kThreads;
+    if (base + j < cols.n) {
+      const double w = cols.w ? ldg(cols.w + base, j) : 1.0;
+      event_ipatia(c, inv, ldg(cols.c[0] + base, j), w, acc);
+    }
+  }
+  tile_store<1, false, 1>(acc, partials, tile, n_tiles, red);
+}
+
+static __global__ __launch_bounds__(kThreads) void k_event_logp_ipatia(EventCols cols,
+                                                                       const IpatiaConst* __restrict__ kc,
+                                                                       double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= cols.n) return;
+  const IpatiaConst& c = *kc;
+  double acc[1] = {0.0};
+  event_ipatia(c, *c.inv_norm, cols.c[0][i], cols.w ? cols.w[i] : 1.0, acc);
+  out[i] = acc[0];
+}
+
+// Hoists theta into the dataset's aux buffer and enqueues the grid passes.
+static ipx_status ipatia_prepare(ipx_ctx* ctx, ipx_dataset* d, const double* theta, hipStream_t s) {
+  IpatiaConst c;
+  if (!hoist_ipatia(theta, c)) return fail(IPX_EDOMAIN, "parameters outside the domain of the Ipatia model");
+  if (!d->aux) {
+    const size_t bytes = kIpaConstBytes + (kIpatiaGridWg + 2 + (size_t)std::max<int64_t>(1, d->n_tiles)) * sizeof(double);
+    HIP_TRY(hipMalloc(&d->aux, bytes));
+  }
+  c.inv_norm = ipa_inv(d);
+  HIP_TRY(hipMemcpyAsync(d->aux, &c, sizeof c, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_ipatia_grid, dim3(kIpatiaGridWg), dim3(kThreads), 0, s, (const IpatiaConst*)d->aux, ipa_part(d));
+  hipLaunchKernelGGL(k_ipatia_norm, dim3(1), dim3(kThreads), 0, s, (const IpatiaConst*)d->aux, ipa_part(d), ipa_inv(d));
+  HIP_TRY(hipGetLastError());
+  return IPX_OK;
+}
+
+static ipx_status run_ipatia(ipx_ctx* ctx, ipx_dataset* d, const double* theta, double* nll, double* grad,
+                             void* stream) {
+  if (grad) return fail(IPX_EINVAL, "the Ipatia model has no analytic gradient (nll_eval only)");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+  ipx_status st = ipatia_prepare(ctx, d, theta, s);
+  if (st != IPX_OK) {
+    *nll = std::numeric_limits<double>::infinity();
+    return st;
+  }
+  const unsigned grid = (unsigned)std::max<int64_t>(1, d->n_tiles);
+  st = timing_begin(ctx, s);
+  if (st != IPX_OK) return st;
+  hipLaunchKernelGGL(k_ipatia_tiles, dim3(grid), dim3(kThreads), 0, s, cols_of(d), (const IpatiaConst*)d->aux,
+                     ipa_tiles(d), d->n_tiles);
+  HIP_TRY(hipGetLastError());
+  st = timing_end(ctx, s);
+  if (st != IPX_OK) return st;
+  hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(kThreads), 0, s, ipa_tiles(d), (int)d->n_tiles, ipa_total(d));
+  HIP_TRY(hipGetLastError());
+  double a = 0.0;
+  HIP_TRY(hipMemcpyAsync(&a, ipa_total(d), sizeof a, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (!std::isfinite(a)) {
+    *nll = std::numeric_limits<double>::infinity();
+    return fail(IPX_EDOMAIN, "non-finite likelihood (an event has P <= 0 or a non-finite term)");
+  }
+  *nll = -a;
+  return IPX_OK;
+}
+
 static ipx_status run(ipx_ctx* ctx, const ipx_dataset* dc, const double* theta, int np, double* nll,
                       double* grad, void* stream) {
   if (!ctx || !dc || !theta || !nll) return fail(IPX_EINVAL, "NULL argument");
   ipx_dataset* d = const_cast<ipx_dataset*>(dc);  // lazily created plan and scratch only
   const int model = d->model;
   if (np != kNParams[model]) return fail(IPX_EINVAL, "model %d takes %d parameters, got %d", model, kNParams[model], np);
+  if (model == kModelIpatia) return run_ipatia(ctx, d, theta, nll, grad, stream);
   {
     ipx_status st = check_theta(model, theta, np, nll, grad);
     if (st != IPX_OK) return st;
@@ -1877,12 +2103,12 @@ static ipx_status run(ipx_ctx* ctx, const ipx_dataset* dc, const double* theta, 
   ipx_plan* p = d->self;
   hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
   EvalHoist h;
-  hoist_eval(model, theta, h);
+  hoist_eval(model, theta, d->ang, h);
   std::memcpy(p->h_consts, h.consts, h.bytes);
   p->h_active[0] = 1;
   ipx_status st = enqueue_batch(p, grad != nullptr, s, ctx);
   if (st != IPX_OK) return st;
-  if (model == 3 && grad) angtime_derivatives(theta, h.h3);  // while the kernels run
+  if (angular_model(model) && grad) angtime_derivatives(theta, h.h3);  // while the kernels run
   HIP_TRY(hipStreamSynchronize(s));
   return finish_eval(model, h, theta, np, p->h_out, nll, grad);
 }
@@ -1960,6 +2186,7 @@ __global__ __launch_bounds__(kThreads) void k_count_bad(EventCols cols,
   if (threadIdx.x == 0) counts[blockIdx.x] = (long long)wcount[0] + wcount[1] + wcount[2] + wcount[3];
 }
 
+template <bool TAG>
 __global__ __launch_bounds__(kThreads) void k_count_bad_angtime(EventCols cols, const AngTimeConst* __restrict__ k,
                                                                 long long* __restrict__ counts) {
   __shared__ int wcount[kThreads / 64];
@@ -1968,8 +2195,8 @@ __global__ __launch_bounds__(kThreads) void k_count_bad_angtime(EventCols cols, 
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < cols.n; i += stride) {
     double acc[1] = {0.0};
     const double w = cols.w ? cols.w[i] : 1.0;
-    event_angtime<false>(*k, &k->C[0][0], cols.c[0][i], cols.c[1][i], cols.c[2][i], cols.c[3][i], cols.c[4][i],
-                         cols.c[5][i], w, acc, nullptr);
+    event_angtime<false, false, TAG>(*k, &k->C[0][0], cols.c[0][i], cols.c[1][i], cols.c[2][i], cols.c[3][i],
+                                     cols.c[4][i], cols.c[5][i], w, acc, nullptr, TAG ? cols.c[6][i] : 1.0);
     bad += !isfinite(acc[0]);
   }
   for (int off = 32; off >= 1; off >>= 1) bad += __shfl_xor(bad, off, 64);
@@ -1995,6 +2222,7 @@ __global__ __launch_bounds__(kThreads) void k_event_logp(EventCols cols, typenam
   out[i] = acc[0];
 }
 
+template <bool TAG>
 __global__ __launch_bounds__(kThreads) void k_event_logp_angtime(EventCols cols, AngTimeConst k,
                                                                  double* __restrict__ out) {
   __shared__ double sC[40];
@@ -2004,8 +2232,9 @@ __global__ __launch_bounds__(kThreads) void k_event_logp_angtime(EventCols cols,
   if (i >= cols.n) return;
   double acc[1] = {0.0};
   const double w = cols.w ? ldg(cols.w + i, 0u) : 1.0;
-  event_angtime<false>(k, sC, ldg(cols.c[0] + i, 0u), ldg(cols.c[1] + i, 0u), ldg(cols.c[2] + i, 0u),
-                       ldg(cols.c[3] + i, 0u), ldg(cols.c[4] + i, 0u), ldg(cols.c[5] + i, 0u), w, acc, nullptr);
+  event_angtime<false, false, TAG>(k, sC, ldg(cols.c[0] + i, 0u), ldg(cols.c[1] + i, 0u), ldg(cols.c[2] + i, 0u),
+                                   ldg(cols.c[3] + i, 0u), ldg(cols.c[4] + i, 0u), ldg(cols.c[5] + i, 0u), w, acc,
+                                   nullptr, TAG ? ldg(cols.c[6] + i, 0u) : 1.0);
   out[i] = acc[0];
 }
 
@@ -2016,6 +2245,8 @@ ipx_status ipx_count_bad_events(ipx_ctx* ctx, const ipx_dataset* d, const double
   const int model = d->model;
   if (np != kNParams[model])
     return fail(IPX_EINVAL, "ipx_count_bad_events: model %d takes %d parameters, got %d", model, kNParams[model], np);
+  if (model == kModelIpatia)
+    return fail(IPX_EINVAL, "ipx_count_bad_events: use ipx_event_logp for the Ipatia model");
   if (!theta_valid(model, theta)) return fail(IPX_EDOMAIN, "ipx_count_bad_events: parameters outside the domain");
   *count = 0;
   if (d->n == 0) return IPX_OK;
@@ -2038,9 +2269,12 @@ ipx_status ipx_count_bad_events(ipx_ctx* ctx, const ipx_dataset* d, const double
     if (e == hipSuccess) hipLaunchKernelGGL(k_count_bad<2>, dim3(grid), dim3(kThreads), 0, ctx->stream, cols, (const MassTimeConst*)buf, counts);
   } else {
     AngTimeHoist h;
-    hoist_angtime_values(theta, h.k, h.ng);
+    hoist_angtime(theta, d->ang, h);
     e = hipMemcpyAsync(buf, &h.k, sizeof h.k, hipMemcpyHostToDevice, ctx->stream);
-    if (e == hipSuccess) hipLaunchKernelGGL(k_count_bad_angtime, dim3(grid), dim3(kThreads), 0, ctx->stream, cols, (const AngTimeConst*)buf, counts);
+    if (e == hipSuccess) {
+      if (model == 3) hipLaunchKernelGGL(k_count_bad_angtime<false>, dim3(grid), dim3(kThreads), 0, ctx->stream, cols, (const AngTimeConst*)buf, counts);
+      else hipLaunchKernelGGL(k_count_bad_angtime<true>, dim3(grid), dim3(kThreads), 0, ctx->stream, cols, (const AngTimeConst*)buf, counts);
+    }
   }
   if (e == hipSuccess) e = hipGetLastError();
   std::vector<long long> hc(grid);
@@ -2062,6 +2296,19 @@ ipx_status ipx_event_logp(ipx_ctx* ctx, const ipx_dataset* d, const double* thet
   if (np != kNParams[model])
     return fail(IPX_EINVAL, "ipx_event_logp: model %d takes %d parameters, got %d", model, kNParams[model], np);
   if (d->n > 0 && !out) return fail(IPX_EINVAL, "ipx_event_logp: out is NULL");
+  if (model == kModelIpatia) {
+    if (d->n == 0) return IPX_OK;
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+    ipx_dataset* dd = const_cast<ipx_dataset*>(d);
+    ipx_status st = ipatia_prepare(ctx, dd, theta, s);
+    if (st != IPX_OK) return st;
+    hipLaunchKernelGGL(k_event_logp_ipatia, dim3((unsigned)((d->n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
+                       cols_of(d), (const IpatiaConst*)dd->aux, out);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    return IPX_OK;
+  }
   if (!theta_valid(model, theta)) return fail(IPX_EDOMAIN, "ipx_event_logp: parameters outside the domain");
   if (d->n == 0) return IPX_OK;
   HIP_TRY(hipSetDevice(ctx->device));
@@ -2076,8 +2323,9 @@ ipx_status ipx_event_logp(ipx_ctx* ctx, const ipx_dataset* d, const double* thet
     hipLaunchKernelGGL(k_event_logp<2>, dim3(grid), dim3(kThreads), 0, s, cols, h.k, out);
   } else {
     AngTimeHoist h;
-    hoist_angtime_values(theta, h.k, h.ng);
-    hipLaunchKernelGGL(k_event_logp_angtime, dim3(grid), dim3(kThreads), 0, s, cols, h.k, out);
+    hoist_angtime(theta, d->ang, h);
+    if (model == 3) hipLaunchKernelGGL(k_event_logp_angtime<false>, dim3(grid), dim3(kThreads), 0, s, cols, h.k, out);
+    else hipLaunchKernelGGL(k_event_logp_angtime<true>, dim3(grid), dim3(kThreads), 0, s, cols, h.k, out);
   }
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s));
@@ -2097,7 +2345,7 @@ ipx_status nll_grad(ipx_ctx* ctx, const ipx_dataset* ds, const double* theta, in
 ipx_status nll_eval_noalloc(ipx_ctx* ctx, int model, int64_t n, const double* const* cols, int ncols,
                             const double* w, const double* theta, int np, double* nll, double* grad, void* stream) {
   if (!ctx || !theta || !nll) return fail(IPX_EINVAL, "nll_eval_noalloc: NULL argument");
-  if (model < 1 || model > 3) return fail(IPX_EINVAL, "nll_eval_noalloc: unknown model %d", model);
+  if (model < 1 || model > 4) return fail(IPX_EINVAL, "nll_eval_noalloc: unknown model %d (1 .. 4)", model);
   if (ncols != kNCols[model])
     return fail(IPX_EINVAL, "nll_eval_noalloc: model %d takes %d columns, got %d", model, kNCols[model], ncols);
   if (np != kNParams[model])
@@ -2139,7 +2387,7 @@ ipx_status nll_eval_noalloc(ipx_ctx* ctx, int model, int64_t n, const double* co
   seg.n_tiles = n_tiles;
   std::memcpy(head + kNaSeg, &seg, sizeof seg);
   EvalHoist h;
-  hoist_eval(model, theta, h);
+  hoist_eval(model, theta, ang_settings_default(), h);
   std::memcpy(head + kNaConst, h.consts, h.bytes);
   head[kNaActive] = 1;
   HIP_TRY(hipMemcpyAsync(base, head, sizeof head, hipMemcpyHostToDevice, s));
@@ -2148,7 +2396,7 @@ ipx_status nll_eval_noalloc(ipx_ctx* ctx, int model, int64_t n, const double* co
     HIP_TRY(hipGetLastError());
   }
   const bool g = grad != nullptr;
-  const int nacc = !g ? 1 : model == 1 ? kAccMass : model == 2 ? kAccMassTime : kAccAngTime;
+  const int nacc = nacc_of(model, g);
   {
     ipx_status st = launch_eval(model, g, (unsigned)std::max<int64_t>(1, n_tiles), segs, tiles, n_tiles,
                                 base + kNaConst, active, 1, out, s, nullptr);
@@ -2156,9 +2404,316 @@ ipx_status nll_eval_noalloc(ipx_ctx* ctx, int model, int64_t n, const double* co
   }
   double a[kAccMax];
   HIP_TRY(hipMemcpyAsync(a, out, nacc * sizeof(double), hipMemcpyDeviceToHost, s));
-  if (model == 3 && g) angtime_derivatives(theta, h.h3);  // while the kernels run
+  if (angular_model(model) && g) angtime_derivatives(theta, h.h3);  // while the kernels run
   HIP_TRY(hipStreamSynchronize(s));
   return finish_eval(model, h, theta, np, a, nll, grad);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Binned path: histograms, smearing, binned likelihood, toys and CL_s
+// ---------------------------------------------------------------------------
+struct ipx_hist {
+  int n = 0;
+  double lo = 0.0, hi = 0.0, dx = 0.0;
+  double sig_sum = 0.0;            // sum of the normalised signal template
+  double sig_max = 0.0;            // its largest entry
+  double* sig = nullptr;           // device [n]: the signal template
+  double* cnt = nullptr;           // device [n]: observed counts
+  double* work = nullptr;          // device: partials, tables, q_obs, counters
+  double* q = nullptr;             // device [2][q_cap]: toy statistics
+  int q_cap = 0;
+  double* host = nullptr;          // pinned: results read back
+  int nwg = 0;
+};
+
+static constexpr int kHistMaxBins = 1 << 24;
+
+static size_t hist_work_doubles(int n, int nwg) {
+  // partials (kBinnedAcc x nwg) | totals (8) | tables: nu, em, kmax (2n each), L (n) | q_obs (1) | counters (2)
+  return (size_t)kBinnedAcc * nwg + 8 + 7 * (size_t)n + 1 + 2;
+}
+
+static ToyTables hist_tables(const ipx_hist* H) {
+  double* t = H->work + (size_t)kBinnedAcc * H->nwg + 8;
+  return ToyTables{t, t + 2 * (size_t)H->n, t + 4 * (size_t)H->n, t + 6 * (size_t)H->n};
+}
+static double* hist_qobs(const ipx_hist* H) { return H->work + (size_t)kBinnedAcc * H->nwg + 8 + 7 * (size_t)H->n; }
+static unsigned long long* hist_counters(const ipx_hist* H) { return (unsigned long long*)(hist_qobs(H) + 1); }
+
+static void free_hist(ipx_hist* H) {
+  if (H->sig) (void)hipFree(H->sig);
+  if (H->cnt) (void)hipFree(H->cnt);
+  if (H->work) (void)hipFree(H->work);
+  if (H->q) (void)hipFree(H->q);
+  if (H->host) (void)hipHostFree(H->host);
+  delete H;
+}
+
+// sum_{b < n} exp(-k b dx), a geometric sum.
+static double geometric_norm(double k, double dx, int n) {
+  if (k == 0.0) return (double)n;
+  return std::expm1(-k * dx * n) / std::expm1(-k * dx);
+}
+
+
+// Binned-model constants at theta = (ns, nb, k); false outside the domain.
+static bool binned_const(const ipx_hist* H, const double* th, BinnedConst* c) {
+  const double ns = th[0], nb = th[1], k = th[2];
+  if (!std::isfinite(ns) || !std::isfinite(nb) || !std::isfinite(k) || ns < 0.0 || nb < 0.0) return false;
+  const double Z = geometric_norm(k, H->dx, H->n);
+  if (!(Z > 0.0) || !std::isfinite(Z)) return false;
+  *c = BinnedConst{ns, nb, k, 1.0 / Z, H->lo, H->dx, H->n};
+  return true;
+}
+
+extern "C" {
+
+ipx_status ipx_smear(ipx_ctx* ctx, int n, double dx, double sigma, const double* h, double* out, void* stream) {
+  if (!ctx || (n > 0 && (!h || !out))) return fail(IPX_EINVAL, "ipx_smear: NULL argument");
+  if (n < 0 || n > kHistMaxBins) return fail(IPX_EINVAL, "ipx_smear: %d bins", n);
+  if (!(dx > 0.0) || !(sigma > 0.0) || !std::isfinite(dx) || !std::isfinite(sigma))
+    return fail(IPX_EINVAL, "ipx_smear: bin width and sigma must be positive");
+  if (n == 0) return IPX_OK;
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+  double* kern = nullptr;
+  HIP_TRY(hipMalloc(&kern, (size_t)(2 * n - 1) * sizeof(double)));
+  hipLaunchKernelGGL(k_smear_kernel, dim3((2 * n - 1 + kThreads - 1) / kThreads), dim3(kThreads), 0, s, kern, n, dx, sigma);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_smear, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, h, kern, out, n);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(kern);
+  if (e != hipSuccess) return fail(IPX_EDEVICE, "ipx_smear: %s", hipGetErrorString(e));
+  return IPX_OK;
+}
+
+ipx_status ipx_hist_create(ipx_ctx* ctx, int nbins, double lo, double hi, double mu, double sigma_core,
+                           double sigma_smear, const double* counts, ipx_hist** out) {
+  if (!ctx || !out) return fail(IPX_EINVAL, "ipx_hist_create: NULL argument");
+  *out = nullptr;
+  if (nbins < 1 || nbins > kHistMaxBins) return fail(IPX_EINVAL, "ipx_hist_create: %d bins", nbins);
+  if (!std::isfinite(lo) || !std::isfinite(hi) || !(hi > lo) || !std::isfinite(mu) || !(sigma_core > 0.0) ||
+      !(sigma_smear > 0.0) || !std::isfinite(sigma_core) || !std::isfinite(sigma_smear))
+    return fail(IPX_EINVAL, "ipx_hist_create: bad range or shape parameters");
+  if (counts)
+    for (int b = 0; b < nbins; ++b)
+      if (!(counts[b] >= 0.0) || !std::isfinite(counts[b]) || counts[b] != std::floor(counts[b]))
+        return fail(IPX_EINVAL, "ipx_hist_create: count %d is not a non-negative integer", b);
+  HIP_TRY(hipSetDevice(ctx->device));
+  ipx_hist* H = new (std::nothrow) ipx_hist();
+  if (!H) return fail(IPX_ENOMEM, "ipx_hist_create: host allocation failed");
+  H->n = nbins;
+  H->lo = lo;
+  H->hi = hi;
+  H->dx = (hi - lo) / nbins;
+  H->nwg = (nbins + kThreads - 1) / kThreads;
+  const int n = nbins;
+  const size_t wd = std::max(hist_work_doubles(n, H->nwg), (size_t)(3 * n));   // the smearing's kernel and core first
+  hipError_t e = hipMalloc(&H->sig, n * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&H->cnt, n * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&H->work, wd * sizeof(double));
+  if (e == hipSuccess) e = hipHostMalloc((void**)&H->host, 16 * sizeof(double), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    free_hist(H);
+    return fail(IPX_ENOMEM, "ipx_hist_create: allocation failed: %s", hipGetErrorString(e));
+  }
+  hipStream_t s = ctx->stream;
+  double* kern = H->work;              // 2n - 1
+  double* core = H->work + 2 * n;      // n (overlaps nothing of kern: 2n - 1 < 2n)
+  const unsigned g1 = (unsigned)((n + kThreads - 1) / kThreads), g2 = (unsigned)((2 * n - 1 + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL(k_gauss_core, dim3(g1), dim3(kThreads), 0, s, core, n, lo, H->dx, mu, sigma_core);
+  hipLaunchKernelGGL(k_smear_kernel, dim3(g2), dim3(kThreads), 0, s, kern, n, H->dx, sigma_smear);
+  hipLaunchKernelGGL(k_smear, dim3(g1), dim3(kThreads), 0, s, core, kern, H->sig, n);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(kThreads), 0, s, H->sig, n, H->host);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  const double total = H->host[0];
+  if (e == hipSuccess && !(total > 0.0 && std::isfinite(total))) {
+    free_hist(H);
+    return fail(IPX_EDOMAIN, "ipx_hist_create: the signal shape has no weight in the range");
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_scale, dim3(g1), dim3(kThreads), 0, s, H->sig, n, 1.0 / total);
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(kThreads), 0, s, H->sig, n, H->host);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    if (counts) e = hipMemcpyAsync(H->cnt, counts, n * sizeof(double), hipMemcpyHostToDevice, s);
+    else e = hipMemsetAsync(H->cnt, 0, n * sizeof(double), s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    free_hist(H);
+    return fail(IPX_EDEVICE, "ipx_hist_create: %s", hipGetErrorString(e));
+  }
+  H->sig_sum = H->host[0];
+  {
+    std::vector<double> t(n);
+    e = hipMemcpy(t.data(), H->sig, n * sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      free_hist(H);
+      return fail(IPX_EDEVICE, "ipx_hist_create: %s", hipGetErrorString(e));
+    }
+    for (double v : t) H->sig_max = std::fmax(H->sig_max, v);
+  }
+  *out = H;
+  return IPX_OK;
+}
+
+ipx_status ipx_hist_destroy(ipx_ctx* ctx, ipx_hist* H) {
+  if (!ctx || !H) return fail(IPX_EINVAL, "ipx_hist_destroy: NULL argument");
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  free_hist(H);
+  return IPX_OK;
+}
+
+int ipx_hist_nbins(const ipx_hist* H) { return H ? H->n : -1; }
+
+ipx_status ipx_hist_read(ipx_ctx* ctx, const ipx_hist* H, int which, double* host) {
+  if (!ctx || !H || !host) return fail(IPX_EINVAL, "ipx_hist_read: NULL argument");
+  if (which != 0 && which != 1) return fail(IPX_EINVAL, "ipx_hist_read: which = %d", which);
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipMemcpyAsync(host, which == 0 ? H->sig : H->cnt, H->n * sizeof(double), hipMemcpyDeviceToHost,
+                         ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return IPX_OK;
+}
+
+ipx_status ipx_hist_set_counts(ipx_ctx* ctx, ipx_hist* H, const double* counts) {
+  if (!ctx || !H || !counts) return fail(IPX_EINVAL, "ipx_hist_set_counts: NULL argument");
+  for (int b = 0; b < H->n; ++b)
+    if (!(counts[b] >= 0.0) || !std::isfinite(counts[b]) || counts[b] != std::floor(counts[b]))
+      return fail(IPX_EINVAL, "ipx_hist_set_counts: count %d is not a non-negative integer", b);
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipMemcpyAsync(H->cnt, counts, H->n * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return IPX_OK;
+}
+
+ipx_status nll_binned(ipx_ctx* ctx, const ipx_hist* H, const double* theta, int np, double* nll, double* grad,
+                      void* stream) {
+  if (!ctx || !H || !theta || !nll) return fail(IPX_EINVAL, "nll_binned: NULL argument");
+  if (np != 3) return fail(IPX_EINVAL, "nll_binned: 3 parameters (ns, nb, k), got %d", np);
+  BinnedConst c;
+  if (!binned_const(H, theta, &c)) {
+    *nll = std::numeric_limits<double>::infinity();
+    if (grad)
+      for (int i = 0; i < 3; ++i) grad[i] = std::numeric_limits<double>::quiet_NaN();
+    return fail(IPX_EDOMAIN, "nll_binned: parameters outside the domain");
+  }
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+  double* part = H->work;
+  double* tot = H->work + (size_t)kBinnedAcc * H->nwg;
+  hipLaunchKernelGGL(k_binned_nll, dim3(H->nwg), dim3(kThreads), 0, s, c, H->sig, H->cnt, part);
+  hipLaunchKernelGGL(k_reduce_parts, dim3(kBinnedAcc), dim3(kThreads), 0, s, part, H->nwg, tot);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(H->host, tot, kBinnedAcc * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const double* a = H->host;
+  if (!std::isfinite(a[0])) {
+    *nll = std::numeric_limits<double>::infinity();
+    if (grad)
+      for (int i = 0; i < 3; ++i) grad[i] = std::numeric_limits<double>::quiet_NaN();
+    return fail(IPX_EDOMAIN, "nll_binned: non-finite likelihood (an expected count is not positive where "
+                             "events were seen)");
+  }
+  *nll = a[0];
+  if (grad) {
+    const double ybar = a[4] * c.invZ;
+    grad[0] = a[1];
+    grad[1] = a[2] * c.invZ;
+    grad[2] = c.nb * c.invZ * (ybar * a[2] - a[3]);
+  }
+  return IPX_OK;
+}
+
+static ipx_status toy_tables(ipx_ctx* ctx, const ipx_hist* H, const double* theta, BinnedConst* c, hipStream_t s,
+                             const char* who) {
+  if (!binned_const(H, theta, c) || !(c->nb > 0.0))
+    return fail(IPX_EDOMAIN, "%s: parameters outside the domain (ns >= 0, nb > 0, finite k)", who);
+  // the inversion starts from p_0 = e^{-nu}: it must not underflow (the
+  // background template is monotonic, largest at one end)
+  const double emax = std::fmax(1.0, std::exp(-c->k * H->dx * (H->n - 1)));
+  const double nu_max = c->ns * H->sig_max + c->nb * emax * c->invZ;
+  if (!(nu_max < 700.0))
+    return fail(IPX_EDOMAIN, "%s: an expected count reaches %g (the Poisson inversion needs < 700)", who, nu_max);
+  hipLaunchKernelGGL(k_toy_tables, dim3(H->nwg), dim3(kThreads), 0, s, *c, H->sig, hist_tables(H));
+  HIP_TRY(hipGetLastError());
+  return IPX_OK;
+}
+
+ipx_status ipx_binned_toy(ipx_ctx* ctx, const ipx_hist* H, const double* theta, uint64_t seed, int hyp,
+                          uint64_t toy, double* counts) {
+  if (!ctx || !H || !theta || !counts) return fail(IPX_EINVAL, "ipx_binned_toy: NULL argument");
+  if (hyp != 0 && hyp != 1) return fail(IPX_EINVAL, "ipx_binned_toy: hypothesis %d", hyp);
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  BinnedConst c;
+  ipx_status st = toy_tables(ctx, H, theta, &c, s, "ipx_binned_toy");
+  if (st != IPX_OK) return st;
+  double* dev = nullptr;
+  HIP_TRY(hipMalloc(&dev, H->n * sizeof(double)));
+  const int nblk = (H->n + 3) / 4;
+  hipLaunchKernelGGL(k_toy_counts, dim3((nblk + kThreads - 1) / kThreads), dim3(kThreads), 0, s, hist_tables(H), H->n,
+                     hyp, seed, toy, dev);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(counts, dev, H->n * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(dev);
+  if (e != hipSuccess) return fail(IPX_EDEVICE, "ipx_binned_toy: %s", hipGetErrorString(e));
+  return IPX_OK;
+}
+
+ipx_status cls_toys(ipx_ctx* ctx, ipx_hist* H, const double* theta, uint64_t seed, int ntoys, ipx_cls_result* res,
+                    double* q_toys) {
+  if (!ctx || !H || !theta || !res) return fail(IPX_EINVAL, "cls_toys: NULL argument");
+  if (ntoys < 1 || ntoys > (1 << 24)) return fail(IPX_EINVAL, "cls_toys: %d toys", ntoys);
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  if (H->q_cap < ntoys) {
+    if (H->q) (void)hipFree(H->q);
+    H->q = nullptr;
+    H->q_cap = 0;
+    HIP_TRY(hipMalloc(&H->q, 2 * (size_t)ntoys * sizeof(double)));
+    H->q_cap = ntoys;
+  }
+  BinnedConst c;
+  ipx_status st = toy_tables(ctx, H, theta, &c, s, "cls_toys");
+  if (st != IPX_OK) return st;
+  const double S = c.ns * H->sig_sum;
+  const ToyTables tb = hist_tables(H);
+  hipLaunchKernelGGL(k_q_counts, dim3(1), dim3(kThreads), 0, s, H->cnt, tb.L, H->n, S, hist_qobs(H));
+  HIP_TRY(hipGetLastError());
+  st = timing_begin(ctx, s);
+  if (st != IPX_OK) return st;
+  hipLaunchKernelGGL(k_cls_toys, dim3((unsigned)ntoys, 2), dim3(kThreads), 0, s, tb, H->n, S, seed, (uint64_t)0, ntoys,
+                     H->q);
+  HIP_TRY(hipGetLastError());
+  st = timing_end(ctx, s);
+  if (st != IPX_OK) return st;
+  HIP_TRY(hipMemsetAsync(hist_counters(H), 0, 2 * sizeof(unsigned long long), s));
+  hipLaunchKernelGGL(k_count_ge, dim3((unsigned)((ntoys + kThreads - 1) / kThreads), 2), dim3(kThreads), 0, s, H->q,
+                     ntoys, hist_qobs(H), hist_counters(H));
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(H->host, hist_qobs(H), 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (q_toys) HIP_TRY(hipMemcpyAsync(q_toys, H->q, 2 * (size_t)ntoys * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  unsigned long long ge[2];
+  std::memcpy(ge, H->host + 1, sizeof ge);
+  res->q_obs = H->host[0];
+  res->n_b = (int64_t)ge[0];
+  res->n_sb = (int64_t)ge[1];
+  res->cl_b = (double)ge[0] / ntoys;
+  res->cl_sb = (double)ge[1] / ntoys;
+  res->cl_s = ge[0] > 0 ? res->cl_sb / res->cl_b : std::numeric_limits<double>::quiet_NaN();
+  return IPX_OK;
 }
 
 }  // extern "C"

@@ -58,6 +58,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 // Reduction rows that hold a wave's adjoint block: whole 16-byte units per
 // wave, so that every wave's block starts 16-byte aligned.
 constexpr int kOuterCap = ((kOuterBlock + kRedPitch - 1) / kRedPitch + 1) & ~1;
+constexpr int kOuterCapTag = ((kOuterBlockTag + kRedPitch - 1) / kRedPitch + 1) & ~1;
 
 // Angular model; C is the coefficient table in LDS.  For the gradient, after
 // each round of 64 events a wave forms the 40 coefficient adjoints of those
@@ -68,10 +69,11 @@ constexpr int kOuterCap = ((kOuterBlock + kRedPitch - 1) / kRedPitch + 1) & ~1;
 // 8b + g, g < 5, keeps the running total of coefficient (5h + g, j).  Lanes
 // without an event write zeros to the block.  The block is the wave's part of
 // the reduction buffer, which the tile reduction reuses afterwards.
-template <bool GRAD, bool COH, int CAP>
+template <bool GRAD, bool COH, int CAP, bool TAG = false>
 __device__ __forceinline__ void tile_angtime(const SegInfo& S, const AngTimeConst& k, const double* C,
                                              int64_t tile, RedBuf<CAP>& red) {
-  static_assert(!GRAD || (CAP >= kOuterCap && CAP % 2 == 0), "the adjoint block lives in the reduction buffer");
+  static_assert(!GRAD || (CAP >= (TAG ? kOuterCapTag : kOuterCap) && CAP % 2 == 0),
+                "the adjoint block lives in the reduction buffer");
   constexpr int NACC = GRAD ? kAngInner : 1;
   double acc[NACC];
 #pragma unroll
@@ -93,9 +95,15 @@ __device__ __forceinline__ void tile_angtime(const SegInfo& S, const AngTimeCons
         blk[kOuterWRow * kOuterPitch + outer_col(lane)] = w;
         w = 0.0;  // the event reads its weight back from the block
       }
-      event_angtime<GRAD, COH>(k, C, ldg<COH>(cl.c[0] + base, j), ldg<COH>(cl.c[1] + base, j),
-                               ldg<COH>(cl.c[2] + base, j), ldg<COH>(cl.c[3] + base, j), ldg<COH>(cl.c[4] + base, j),
-                               ldg<COH>(cl.c[5] + base, j), w, acc, blk + outer_col(lane));
+      double qd = TAG ? ldg<COH>(cl.c[6] + base, j) : 1.0;
+      if constexpr (GRAD && TAG) {
+        blk[kOuterQRow * kOuterPitch + outer_col(lane)] = qd;
+        qd = 0.0;  // read back from the block where it is used
+      }
+      event_angtime<GRAD, COH, TAG>(k, C, ldg<COH>(cl.c[0] + base, j), ldg<COH>(cl.c[1] + base, j),
+                                    ldg<COH>(cl.c[2] + base, j), ldg<COH>(cl.c[3] + base, j),
+                                    ldg<COH>(cl.c[4] + base, j), ldg<COH>(cl.c[5] + base, j), w, acc,
+                                    blk + outer_col(lane), qd);
     } else if constexpr (GRAD) {
 #pragma unroll
       for (int r = 0; r < kOuterRows; ++r) blk[r * kOuterPitch + outer_col(lane)] = 0.0;
@@ -154,13 +162,15 @@ __global__ __launch_bounds__(kThreads) void k_nll_batch(const SegInfo* __restric
 // The gradient instance is held to 128 VGPRs (4 waves/SIMD; the extra wave
 // shortens the tail of the launch more than the few spilled registers cost);
 // its LDS (adjoint blocks sharing the reduction buffer, ~35 KB) allows 4
-// workgroups per compute unit.
-template <bool GRAD>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(GRAD ? 4 : 1))) void k_angtime_batch(const SegInfo* __restrict__ segs,
+// workgroups per compute unit.  WPE > 0 builds a variant for another
+// waves-per-SIMD target (a launch-schedule choice: the arithmetic, and so
+// every result, is the same).
+template <bool GRAD, bool TAG = false, int WPE = 0>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : (GRAD ? 4 : 1)))) void k_angtime_batch(const SegInfo* __restrict__ segs,
                                                             const TileRef* __restrict__ tiles, int64_t n_tiles,
                                                             const AngTimeConst* __restrict__ consts,
                                                             const unsigned char* __restrict__ active) {
-  constexpr int kCap = GRAD ? kOuterCap : 1;
+  constexpr int kCap = GRAD ? (TAG ? kOuterCapTag : kOuterCap) : 1;
   __shared__ double sC[40];
   __shared__ RedBuf<kCap> red;
   for (int64_t g = blockIdx.x; g < n_tiles; g += gridDim.x) {
@@ -169,7 +179,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(GRAD ?
     const AngTimeConst& k = consts[tr.seg];
     if (threadIdx.x < 40) sC[threadIdx.x] = (&k.C[0][0])[threadIdx.x];
     __syncthreads();
-    tile_angtime<GRAD, false>(segs[tr.seg], k, sC, tr.tile, red);
+    tile_angtime<GRAD, false, kCap, TAG>(segs[tr.seg], k, sC, tr.tile, red);
   }
 }
 

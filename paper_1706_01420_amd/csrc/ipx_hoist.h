@@ -89,7 +89,7 @@ inline bool theta_valid(int model, const double* th) {
   if (model == 2)
     return all_finite(th, 7) && th[0] >= 0.0 && th[0] <= 1.0 && th[2] > 0.0 && th[4] > 0.0 && th[5] > 0.0 &&
            th[6] > 0.0;
-  if (model == 3)
+  if (model == 3 || model == 4)
     return all_finite(th, 12) && th[0] >= 0.0 && th[1] >= 0.0 && th[0] + th[1] <= 1.0 && th[2] >= 0.0 &&
            th[2] <= 1.0 && th[11] > 0.0 && th[6] - std::fabs(th[7]) / 2.0 > 0.0;
   return false;
@@ -101,7 +101,7 @@ inline bool theta_valid(int model, const double* th) {
 // squared modulus, computed as the hoisting computes it, is positive.
 inline bool theta_grad_valid(int model, const double* th) {
   if (!theta_valid(model, th)) return false;
-  if (model != 3) return true;
+  if (model != 3 && model != 4) return true;
   const double fL = th[0], fpe = th[1], Fs = th[2];
   const double a0 = (1.0 - Fs) * fL, ape = (1.0 - Fs) * fpe, apa = (1.0 - Fs) * (1.0 - fL - fpe);
   return a0 > 0.0 && ape > 0.0 && apa > 0.0 && Fs > 0.0;
@@ -192,10 +192,26 @@ constexpr double kXi[10] = {32.0 * M_PI / 9.0, 32.0 * M_PI / 9.0, 32.0 * M_PI / 
 
 using HD7 = HD<7>;  // directions: fL, fperp, Fs, dpa, dpe, dS, phis
 
-// C[k][j] = N_k (a_k, b_k, c_k, d_k), |lambda| = 1, C_SP = 1, delta_0 = 0;
-// T = double for the values, HD7 for values and derivatives.
+// Per-dataset constants of the angular models: the normalisation weights
+// xi_k = integral eps(Omega) f_k dOmega of the angular efficiency eps (the
+// analytic integrals for a flat efficiency) and the S-P interference factor
+// C_SP of the sample's KK-mass bin (Example 2 fits one sample per bin).
+struct AngSettings {
+  double xi[10];
+  double c_sp;
+};
+inline AngSettings ang_settings_default() {
+  AngSettings a;
+  for (int k = 0; k < 10; ++k) a.xi[k] = kXi[k];
+  a.c_sp = 1.0;
+  return a;
+}
+
+// C[k][j] = N_k (a_k, b_k, c_k, d_k), |lambda| = 1, delta_0 = 0, the S-P
+// rows (k = 8, 9, 10) scaled by c_sp; T = double for the values, HD7 for
+// values and derivatives.
 template <typename T>
-inline void angular_coefficients(const double* th, T C[10][4]) {
+inline void angular_coefficients(const double* th, T C[10][4], double c_sp) {
   const T fL = hvar<T>(th[0], 0), fpe = hvar<T>(th[1], 1), Fs = hvar<T>(th[2], 2);
   const T dpa = hvar<T>(th[3], 3), dpe = hvar<T>(th[4], 4), dS = hvar<T>(th[5], 5);
   const T phis = hvar<T>(th[9], 6);
@@ -212,7 +228,8 @@ inline void angular_coefficients(const double* th, T C[10][4]) {
   const T cpS = hcos(dpa - dS), spS = hsin(dpa - dS);
   const T seS = hsin(dpe - dS);
   const T c0S = hcos(d0 - dS), s0S = hsin(d0 - dS);
-  const T N[10] = {a0, apa, ape, rpa * rpe, r0 * rpa, r0 * rpe, aS, rS * rpa, rS * rpe, rS * r0};
+  const T csp(c_sp);
+  const T N[10] = {a0, apa, ape, rpa * rpe, r0 * rpa, r0 * rpe, aS, csp * (rS * rpa), csp * (rS * rpe), csp * (rS * r0)};
   const T abcd[10][4] = {
       {one, Dd, Cc, -S},
       {one, Dd, Cc, -S},
@@ -233,17 +250,18 @@ struct AngTimeHoist {
   AngTimeConst k;
   HD7 C[10][4];   // the coefficient table with its derivatives (for the gradient only)
   GaussNorm ng;
+  AngSettings set = ang_settings_default();  // the dataset's constants used by this hoist
 };
 // The kernel constants alone (what a launch needs); the derivative table can
 // follow while the kernel runs (angtime_derivatives).
-inline void hoist_angtime_values(const double* th, AngTimeConst& k, GaussNorm& ng) {
+inline void hoist_angtime_values(const double* th, const AngSettings& set, AngTimeConst& k, GaussNorm& ng) {
   double Cv[10][4];
-  angular_coefficients(th, Cv);
+  angular_coefficients(th, Cv, set.c_sp);
   for (int j = 0; j < 4; ++j) {
     double s = 0.0;
     for (int kk = 0; kk < 10; ++kk) {
       k.C[kk][j] = Cv[kk][j];
-      s += kXi[kk] * Cv[kk][j];
+      s += set.xi[kk] * Cv[kk][j];
     }
     k.D[j] = s;
   }
@@ -274,7 +292,12 @@ inline void hoist_angtime_values(const double* th, AngTimeConst& k, GaussNorm& n
   k.q = 1.0 / (2.0 * sig * sig);
   k.lnNG = std::log(ng.N);
 }
-inline void angtime_derivatives(const double* th, AngTimeHoist& h) { angular_coefficients(th, h.C); }
+// Fills h (kernel constants, mass normalisation, the settings used).
+inline void hoist_angtime(const double* th, const AngSettings& set, AngTimeHoist& h) {
+  h.set = set;
+  hoist_angtime_values(th, set, h.k, h.ng);
+}
+inline void angtime_derivatives(const double* th, AngTimeHoist& h) { angular_coefficients(th, h.C, h.set.c_sp); }
 inline void grad_angtime(const AngTimeHoist& h, const double* th, const double* a, double* g) {
   // total adjoint of C_kj: direct plus through D_j = sum_k xi_k C_kj
   // layout: a[0] l, a[1..4] dD_j, a[5..8] d(Gamma_H, Gamma_L, Re z, dm),
@@ -282,7 +305,7 @@ inline void grad_angtime(const AngTimeHoist& h, const double* th, const double* 
   double phys[7] = {0, 0, 0, 0, 0, 0, 0};
   for (int kk = 0; kk < 10; ++kk)
     for (int j = 0; j < 4; ++j) {
-      const double adj = a[12 + 4 * kk + j] + kXi[kk] * a[1 + j];
+      const double adj = a[12 + 4 * kk + j] + h.set.xi[kk] * a[1 + j];
       for (int p = 0; p < 7; ++p) phys[p] += adj * h.C[kk][j].d[p];
     }
   const double dG = a[5] + a[6] + a[7];

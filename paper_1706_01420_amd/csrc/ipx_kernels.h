@@ -358,7 +358,9 @@ constexpr int kAngOuter = 40;
 constexpr int kOuterPitch = 68;
 constexpr int kOuterRows = 14;
 constexpr int kOuterWRow = 14;  // one more row: the events' weights until their last use
+constexpr int kOuterQRow = 15;  // tagged model: the events' tag factors qd until their last use
 constexpr int kOuterBlock = (kOuterRows + 1) * kOuterPitch;
+constexpr int kOuterBlockTag = (kOuterRows + 2) * kOuterPitch;
 __device__ __forceinline__ unsigned outer_col(unsigned e) { return e + ((e >> 5) << 1); }
 
 // One event.  C is the coefficient table in LDS (row-major 10 x 4).  For the
@@ -366,10 +368,15 @@ __device__ __forceinline__ unsigned outer_col(unsigned e) { return e + ((e >> 5)
 // ob, and takes the weight from the block's weight row (the caller puts it
 // there when it loads the columns), not from w: read back only where it is
 // first used, it holds no register through the event.
-template <bool GRAD, bool COH = false>
+// TAG (tagged model): qd = q (1 - 2 omega) scales the cos and sin time terms
+// and their integrals (the normalised mixture of the two flavours' PDFs for
+// an event tagged q with mistag probability omega); untagged, qd is 1 and
+// never read.  For the tagged gradient qd, like the weight, comes from the
+// block (row kOuterQRow), read where it is used.
+template <bool GRAD, bool COH = false, bool TAG = false>
 __device__ __forceinline__ void event_angtime(const AngTimeConst& k, const double* __restrict__ C,
                                               double ck, double cl, double ph, double t, double sig,
-                                              double m, double w, double* acc, double* ob) {
+                                              double m, double w, double* acc, double* ob, double qd = 1.0) {
   // time: per-event factors shared by t, T_LO and T_HI
   const double s2 = sig * sig;
   const double inv_sig = rcp(sig);
@@ -400,8 +407,9 @@ __device__ __forceinline__ void event_angtime(const AngTimeConst& k, const doubl
   const double IH = (dphi + Xa.FH - Xb.FH) * k.inv_gH;
   const double IL = (dphi + Xa.FL - Xb.FL) * k.inv_gL;
   const cplx Ic = cmul(cplx{dphi + Xa.Fc.re - Xb.Fc.re, Xa.Fc.im - Xb.Fc.im}, cplx{k.izr, k.izi});
-  const double T[4] = {0.5 * (Xt.FH + Xt.FL), 0.5 * (Xt.FH - Xt.FL), Xt.Fc.re, Xt.Fc.im};
-  const double I[4] = {0.5 * (IH + IL), 0.5 * (IH - IL), Ic.re, Ic.im};
+  double T[4] = {0.5 * (Xt.FH + Xt.FL), 0.5 * (Xt.FH - Xt.FL), Xt.Fc.re, Xt.Fc.im};
+  double I[4] = {0.5 * (IH + IL), 0.5 * (IH - IL), Ic.re, Ic.im};
+
 
   // angular part: A_j = sum_k f_k C_kj
   double f[10];
@@ -416,8 +424,21 @@ __device__ __forceinline__ void event_angtime(const AngTimeConst& k, const doubl
   for (int kk = 0; kk < 10; ++kk)
 #pragma unroll
     for (int j = 0; j < 4; ++j) A[j] += f[kk] * C[4 * kk + j];
+  double D2 = k.D[2], D3 = k.D[3];
+  if constexpr (TAG) {
+    // the tag factor multiplies the cos and sin terms: folded into their
+    // angular sums and normalisation coefficients
+    if constexpr (GRAD) {
+      asm volatile("" ::: "memory");
+      qd = ob[kOuterQRow * kOuterPitch];
+    }
+    A[2] *= qd;
+    A[3] *= qd;
+    D2 *= qd;
+    D3 *= qd;
+  }
   const double num = A[0] * T[0] + A[1] * T[1] + A[2] * T[2] + A[3] * T[3];
-  const double den = k.D[0] * I[0] + k.D[1] * I[1] + k.D[2] * I[2] + k.D[3] * I[3];
+  const double den = k.D[0] * I[0] + k.D[1] * I[1] + D2 * I[2] + D3 * I[3];
   const double d = m - k.mu;
   if constexpr (GRAD) {
     asm volatile("" ::: "memory");
@@ -427,10 +448,24 @@ __device__ __forceinline__ void event_angtime(const AngTimeConst& k, const doubl
 
   if constexpr (GRAD) {
     const double inum = w * rcp(num), iden = w * rcp(den);
+    if constexpr (TAG) {
+      // the derivatives with respect to the table's cos and sin columns and
+      // their normalisation coefficients carry the tag factor
+      const double inq = inum * qd, idq = iden * qd;
+      ob[10 * kOuterPitch] = T[0] * inum;
+      ob[11 * kOuterPitch] = T[1] * inum;
+      ob[12 * kOuterPitch] = T[2] * inq;
+      ob[13 * kOuterPitch] = T[3] * inq;
+      acc[1] -= I[0] * iden;
+      acc[2] -= I[1] * iden;
+      acc[3] -= I[2] * idq;
+      acc[4] -= I[3] * idq;
+    } else {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) ob[(10 + j) * kOuterPitch] = T[j] * inum;
+      for (int j = 0; j < 4; ++j) ob[(10 + j) * kOuterPitch] = T[j] * inum;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[1 + j] -= I[j] * iden;
+      for (int j = 0; j < 4; ++j) acc[1 + j] -= I[j] * iden;
+    }
     const double Gt = Xt.g * kInvSqrt2Pi * inv_sig;
     const double Ga = Xa.g * kInvSqrt2Pi * inv_sig;
     const double Gb = Xb.g * kInvSqrt2Pi * inv_sig;
@@ -444,8 +479,8 @@ __device__ __forceinline__ void event_angtime(const AngTimeConst& k, const doubl
     const cplx dIc = cmul(cplx{-Ic.re + dFca.re - dFcb.re, -Ic.im + dFca.im - dFcb.im}, cplx{k.izr, k.izi});
     acc[5] += 0.5 * (A[0] + A[1]) * dFHt * inum - 0.5 * (k.D[0] + k.D[1]) * dIH * iden;
     acc[6] += 0.5 * (A[0] - A[1]) * dFLt * inum - 0.5 * (k.D[0] - k.D[1]) * dIL * iden;
-    acc[7] += (A[2] * dFct.re + A[3] * dFct.im) * inum - (k.D[2] * dIc.re + k.D[3] * dIc.im) * iden;
-    acc[8] += (A[2] * dFct.im - A[3] * dFct.re) * inum - (k.D[2] * dIc.im - k.D[3] * dIc.re) * iden;
+    acc[7] += (A[2] * dFct.re + A[3] * dFct.im) * inum - (D2 * dIc.re + D3 * dIc.im) * iden;
+    acc[8] += (A[2] * dFct.im - A[3] * dFct.re) * inum - (D2 * dIc.im - D3 * dIc.re) * iden;
     acc[9] += w * 2.0 * k.q * d;
     acc[10] -= w * d * d;
     acc[11] += w;

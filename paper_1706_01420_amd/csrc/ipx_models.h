@@ -24,7 +24,7 @@ constexpr int kAccAngTime = 52;   // l, dD[4], dgH, dgL, dzr, ddm, dmu, dq, sum_
 constexpr int kAccMax = 52;
 
 struct EventCols {
-  const double* c[6];
+  const double* c[7];
   const double* w;  // nullptr: unit weights
   int64_t n;
 };

@@ -11,9 +11,12 @@
 //           counters, writes lim[s] = (seq << 32) | items, then publishes
 //           claim[s] = seq << 32 and sets the slot's bit in the claimable-slot
 //           mask.
-//   workers scan the mask and take one item at a time with one atomic add on
-//           claim[s]; the returned word names the request (high half) and the
-//           item (low half).  The item is valid if lim[s] names the same
+//   workers take one item at a time with one atomic add on claim[s] of a
+//           slot in the mask: the oldest opened request first (policy 0:
+//           the first wave reads the open stamps of the claimable slots and
+//           picks the smallest), or each workgroup from its own starting slot
+//           (policy 1, requests spread over the workers); the returned word
+//           names the request (high half) and the item (low half).  The item is valid if lim[s] names the same
 //           request and the item is below its count; any other increment is a
 //           late claim on a finished request and is dropped, so no request
 //           can lose an item.  The worker that takes a slot's last item
@@ -71,6 +74,7 @@ struct ServeSlot {                 // device memory, touched by the GPU only
   unsigned long long claim;        // (seq << 32) | next item
   unsigned long long lim;          // (seq << 32) | items of the request in the slot
   unsigned long long open;         // last seq opened by the poller
+  unsigned long long stamp;        // opening order of the request in the slot (ServeCtl::opened)
   unsigned int done;               // completed items
   unsigned int pad;
 };
@@ -78,9 +82,13 @@ struct ServeSlot {                 // device memory, touched by the GPU only
 struct ServeCtl {                  // device memory
   unsigned long long mask;         // slots that may have unclaimed items
   unsigned long long stop;         // mirror of the host's stop
+  unsigned long long opened;       // requests opened so far (written by the poller only)
   unsigned int live;               // worker workgroups still running (set by the host at launch)
   unsigned int quit;               // set by the poller after idle_limit idle polls (0 at launch)
 };
+
+// Claim policies of the workers.
+enum : int { kServeOldestFirst = 0, kServeSpread = 1 };
 
 struct ServeShared {               // fine-grained host memory
   unsigned long long gen;          // bumped by the host after each publication
@@ -132,6 +140,9 @@ __device__ __forceinline__ void serve_open(ServeShared* hs, ServeCtl* ctl, Serve
   __syncthreads();
   if (threadIdx.x == 0) {
     const unsigned items = (unsigned)load_dev(&dd[s].items);
+    const unsigned long long stamp = load_dev(&ctl->opened) + 1ull;
+    store_dev(&ctl->opened, stamp);
+    store_dev(&st[s].stamp, stamp);
     store_dev(&st[s].open, seq);
     store_dev(&st[s].done, 0u);
     store_dev(&st[s].lim, (seq << 32) | (unsigned long long)items);
@@ -191,15 +202,69 @@ __device__ __forceinline__ void serve_poll(ServeShared* hs, ServeCtl* ctl, Serve
   }
 }
 
+// Thread 0: one claim on slot s; true (and the item in cslot/citem) if the
+// claim names the request in the slot and an item below its count.
+__device__ __forceinline__ bool serve_claim(ServeCtl* ctl, ServeSlot* __restrict__ st, int s, int* cslot,
+                                            int* citem) {
+  const unsigned long long old =
+      __hip_atomic_fetch_add(&st[s].claim, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  wait_mem();  // lim is read after the claim word it validates
+  const unsigned long long lim = load_dev(&st[s].lim);
+  const unsigned item = (unsigned)(old & 0xffffffffull);
+  const unsigned n = (unsigned)(lim & 0xffffffffull);
+  if ((lim >> 32) != (old >> 32) || item >= n) return false;
+  *cslot = s;
+  *citem = (int)item;
+  if (item == n - 1u)
+    __hip_atomic_fetch_and(&ctl->mask, ~(1ull << s), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return true;
+}
+
 __device__ __forceinline__ void serve_work(ServeShared* hs, ServeCtl* ctl, ServeDesc* __restrict__ dd,
-                                           ServeSlot* __restrict__ st) {
+                                           ServeSlot* __restrict__ st, int policy) {
   __shared__ ServeDesc sd;          // the current item's request
-  __shared__ RedBuf<kOuterCap> red;
+  __shared__ RedBuf<kOuterCapTag> red;
   __shared__ int cmd, cslot, citem;
   __shared__ int last;
   const unsigned rot = blockIdx.x & 63u;  // spreads the workers' first choice over the slots
   for (;;) {
-    if (threadIdx.x == 0) {
+    if (policy == kServeOldestFirst) {
+      // the first wave picks the claimable slot with the smallest open stamp
+      // (lane s reads slot s's stamp); thread 0 claims, and on a refusal
+      // (the slot ran out of items meanwhile) the next oldest is tried
+      if (threadIdx.x < 64) {
+        const unsigned lane = threadIdx.x;
+        int ex = 0;
+        unsigned long long m = 0ull;
+        if (lane == 0) {
+          ex = load_dev(&ctl->stop) || load_dev(&ctl->quit);
+          if (!ex) m = load_dev(&ctl->mask);
+        }
+        ex = __shfl(ex, 0, 64);
+        m = __shfl(m, 0, 64);
+        int got = 0;
+        if (lane == 0) cmd = ex ? kCmdExit : kCmdIdle;
+        if (!ex && m != 0ull) {
+          const unsigned long long stamp = ((m >> lane) & 1ull) ? load_dev(&st[lane].stamp) : ~0ull;
+          while (m != 0ull && !got) {
+            unsigned long long key = ((m >> lane) & 1ull) ? ((stamp << 6) | lane) : ~0ull;
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+              const unsigned long long o = __shfl_xor(key, off, 64);
+              key = o < key ? o : key;
+            }
+            const int s = (int)(key & 63ull);
+            if (lane == 0 && serve_claim(ctl, st, s, &cslot, &citem)) {
+              cmd = kCmdWork;
+              got = 1;
+            }
+            got = __shfl(got, 0, 64);
+            m &= ~(1ull << s);
+          }
+        }
+        if (lane == 0) wait_mem();  // the descriptor is read after the claim
+      }
+    } else if (threadIdx.x == 0) {
       cmd = kCmdIdle;
       if (load_dev(&ctl->stop) || load_dev(&ctl->quit)) {
         cmd = kCmdExit;
@@ -209,19 +274,7 @@ __device__ __forceinline__ void serve_work(ServeShared* hs, ServeCtl* ctl, Serve
         while (m != 0ull && cmd == kCmdIdle) {
           const int s = (int)((__builtin_ctzll(m) + rot) & 63u);
           m &= m - 1ull;
-          const unsigned long long old =
-              __hip_atomic_fetch_add(&st[s].claim, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          wait_mem();  // lim is read after the claim word it validates
-          const unsigned long long lim = load_dev(&st[s].lim);
-          const unsigned item = (unsigned)(old & 0xffffffffull);
-          const unsigned n = (unsigned)(lim & 0xffffffffull);
-          if ((lim >> 32) == (old >> 32) && item < n) {
-            cmd = kCmdWork;
-            cslot = s;
-            citem = (int)item;
-            if (item == n - 1u)
-              __hip_atomic_fetch_and(&ctl->mask, ~(1ull << s), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          }
+          if (serve_claim(ctl, st, s, &cslot, &citem)) cmd = kCmdWork;
         }
       }
       wait_mem();  // the descriptor is read after the claim
@@ -250,9 +303,12 @@ __device__ __forceinline__ void serve_work(ServeShared* hs, ServeCtl* ctl, Serve
     } else if (sd.model == 2) {
       if (sd.grad) tile_nll<2, true, true>(sd.seg, sd.k.m2, tile, red);
       else tile_nll<2, false, true>(sd.seg, sd.k.m2, tile, red);
+    } else if (sd.model == 3) {
+      if (sd.grad) tile_angtime<true, true, kOuterCapTag>(sd.seg, sd.k.m3, &sd.k.m3.C[0][0], tile, red);
+      else tile_angtime<false, true, kOuterCapTag>(sd.seg, sd.k.m3, &sd.k.m3.C[0][0], tile, red);
     } else {
-      if (sd.grad) tile_angtime<true, true>(sd.seg, sd.k.m3, &sd.k.m3.C[0][0], tile, red);
-      else tile_angtime<false, true>(sd.seg, sd.k.m3, &sd.k.m3.C[0][0], tile, red);
+      if (sd.grad) tile_angtime<true, true, kOuterCapTag, true>(sd.seg, sd.k.m3, &sd.k.m3.C[0][0], tile, red);
+      else tile_angtime<false, true, kOuterCapTag, true>(sd.seg, sd.k.m3, &sd.k.m3.C[0][0], tile, red);
     }
     // every lane's stores of this item (its tile partials) complete before
     // the item is counted as done
@@ -282,10 +338,13 @@ __device__ __forceinline__ void serve_work(ServeShared* hs, ServeCtl* ctl, Serve
 }
 
 // Workgroup 0 polls the host, the others evaluate; grid >= 2 workgroups.
-__global__ __launch_bounds__(kThreads) void k_serve(ServeShared* hs, ServeCtl* ctl, ServeDesc* __restrict__ dd,
-                                                    ServeSlot* __restrict__ st, int nslots, int idle_limit) {
+// Held to 168 VGPRs (3 waves per SIMD): the one kernel carries every model's
+// tile body, and at 128 it would spill ~50 registers.
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_serve(
+    ServeShared* hs, ServeCtl* ctl, ServeDesc* __restrict__ dd, ServeSlot* __restrict__ st, int nslots,
+    int idle_limit, int policy) {
   if (blockIdx.x == 0) serve_poll(hs, ctl, dd, st, nslots, idle_limit);
-  else serve_work(hs, ctl, dd, st);
+  else serve_work(hs, ctl, dd, st, policy);
 }
 
 }  // namespace ipx

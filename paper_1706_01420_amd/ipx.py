@@ -30,6 +30,8 @@ STATUS_NAMES = {0: "IPX_OK", -1: "IPX_EINVAL", -2: "IPX_ENOMEM", -3: "IPX_EDEVIC
 IPX_MODEL_MASS = 1
 IPX_MODEL_MASSTIME = 2
 IPX_MODEL_ANGTIME = 3
+IPX_MODEL_ANGTIME_TAGGED = 4
+IPX_MODEL_IPATIA = 5
 
 IPX_COPY_HOST = 0
 IPX_COPY_DEVICE = 1
@@ -56,6 +58,7 @@ _SIGNATURES = [
     ("ipx_dataset_size", ctypes.c_int64, [ctypes.c_void_p]),
     ("ipx_dataset_model", ctypes.c_int, [ctypes.c_void_p]),
     ("ipx_dataset_column", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_void_pp]),
+    ("ipx_dataset_set_angular", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double]),
     ("ipx_dataset_read", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_int64, _c_double_p]),
     # pointer arguments as plain addresses (the per-call marshalling below)
@@ -67,6 +70,13 @@ _SIGNATURES = [
     ("nll_eval_noalloc", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    ("ipx_sim_create", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+      _c_void_pp]),
+    ("ipx_sim_destroy", None, [ctypes.c_void_p]),
+    ("ipx_sim_nparams", ctypes.c_int, [ctypes.c_void_p]),
+    ("nll_sim", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_void_p, _c_double_p, ctypes.c_int, _c_double_p, ctypes.c_void_p, ctypes.c_void_p]),
     ("ipx_plan_create", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p), _c_void_pp]),
     ("ipx_plan_destroy", None, [ctypes.c_void_p]),
     ("nll_eval_batch", ctypes.c_int,
@@ -85,6 +95,23 @@ _SIGNATURES = [
     ("toy_generate_batch", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_int, _c_double_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p,
       ctypes.c_void_p, ctypes.c_uint, ctypes.c_void_p, ctypes.c_void_p]),
+    ("ipx_smear", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+      ctypes.c_void_p]),
+    ("ipx_hist_create", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+      ctypes.c_double, ctypes.c_void_p, _c_void_pp]),
+    ("ipx_hist_destroy", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("ipx_hist_nbins", ctypes.c_int, [ctypes.c_void_p]),
+    ("ipx_hist_read", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, _c_double_p]),
+    ("ipx_hist_set_counts", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, _c_double_p]),
+    ("nll_binned", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_void_p, _c_double_p, ctypes.c_int, _c_double_p, ctypes.c_void_p, ctypes.c_void_p]),
+    ("ipx_binned_toy", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_void_p, _c_double_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64, _c_double_p]),
+    ("cls_toys", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_void_p, _c_double_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p,
+      ctypes.c_void_p]),
     ("ipx_timing_enable", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     ("ipx_timing_read", ctypes.c_int,
      [ctypes.c_void_p, _c_double_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]),
@@ -228,6 +255,18 @@ def ipx_dataset_column(ds, col):
     return p.value
 
 
+def ipx_dataset_set_angular(ctx, ds, xi=None, c_sp=1.0):
+    """Normalisation weights xi (10 values, None: flat efficiency) and S-P
+    factor c_sp of an angular dataset."""
+    xp = None
+    if xi is not None:
+        xi = np.ascontiguousarray(xi, dtype=np.float64)
+        if xi.shape != (10,):
+            raise ValueError("xi takes 10 values")
+        xp = xi.ctypes.data
+    _check(_lib.ipx_dataset_set_angular(ctx, ds, xp, float(c_sp)))
+
+
 def ipx_dataset_read(ctx, ds, col, offset=0, count=None):
     """Host copy (numpy) of column `col` of a dataset, in storage order."""
     n = ipx_dataset_size(ds)
@@ -339,6 +378,37 @@ def nll(ctx, ds, theta):
     return _NLL.apply(theta, ctx, ds)
 
 
+def ipx_sim_create(ctx, datasets, bins, nbins):
+    """Simultaneous set of angular categories (dataset c in KK-mass bin bins[c])."""
+    arr = (ctypes.c_void_p * len(datasets))(*[d.value for d in datasets])
+    b = (ctypes.c_int * len(datasets))(*[int(x) for x in bins])
+    h = ctypes.c_void_p()
+    _check(_lib.ipx_sim_create(ctx, len(datasets), arr, b, int(nbins), ctypes.byref(h)))
+    return h
+
+
+def ipx_sim_destroy(sim):
+    _lib.ipx_sim_destroy(sim)
+
+
+def ipx_sim_nparams(sim):
+    return _lib.ipx_sim_nparams(sim)
+
+
+def nll_sim(ctx, sim, theta, grad=False, stream=None):
+    """Joint NLL of the set's categories (and its gradient); +inf (NaN
+    gradient) for IPX_EDOMAIN."""
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    out = np.empty(1)
+    g = np.empty(th.shape[0]) if grad else None
+    st = _lib.nll_sim(ctx, sim, _dbl(th), th.shape[0], _dbl(out), None if g is None else g.ctypes.data,
+                      None if stream is None else _stream_ptr(stream))
+    if st == IPX_EDOMAIN:
+        return (float("inf"), np.full(th.shape[0], np.nan)) if grad else float("inf")
+    _check(st)
+    return (float(out[0]), g) if grad else float(out[0])
+
+
 def ipx_plan_create(ctx, datasets):
     arr = (ctypes.c_void_p * len(datasets))(*[d.value for d in datasets])
     h = ctypes.c_void_p()
@@ -351,23 +421,28 @@ def ipx_plan_destroy(plan):
 
 
 class _Schedule(ctypes.Structure):
-    _fields_ = [("workgroups", ctypes.c_int), ("order", ctypes.c_int), ("graph", ctypes.c_int)]
+    _fields_ = [("workgroups", ctypes.c_int), ("order", ctypes.c_int), ("graph", ctypes.c_int),
+                ("variant", ctypes.c_int)]
 
 
 class _TuneEntry(ctypes.Structure):
     _fields_ = [("schedule", _Schedule), ("us", ctypes.c_double)]
 
 
-def ipx_plan_set_schedule(plan, workgroups=0, order=0, graph=1):
+def _sched_dict(sc):
+    return {"workgroups": sc.workgroups, "order": sc.order, "graph": sc.graph, "variant": sc.variant}
+
+
+def ipx_plan_set_schedule(plan, workgroups=0, order=0, graph=1, variant=0):
     """Launch schedule of the plan's per-event kernel (results do not depend on it)."""
-    sc = _Schedule(int(workgroups), int(order), int(graph))
+    sc = _Schedule(int(workgroups), int(order), int(graph), int(variant))
     _check(_lib.ipx_plan_set_schedule(plan, ctypes.byref(sc)))
 
 
 def ipx_plan_get_schedule(plan):
     sc = _Schedule()
     _check(_lib.ipx_plan_get_schedule(plan, ctypes.byref(sc)))
-    return {"workgroups": sc.workgroups, "order": sc.order, "graph": sc.graph}
+    return _sched_dict(sc)
 
 
 def ipx_plan_autotune(ctx, plan, theta, grad=True, reps=5):
@@ -376,13 +451,12 @@ def ipx_plan_autotune(ctx, plan, theta, grad=True, reps=5):
     th = np.ascontiguousarray(theta, dtype=np.float64)
     best = _Schedule()
     best_us = ctypes.c_double()
-    table = (_TuneEntry * 16)()
-    n = ctypes.c_int(16)
+    table = (_TuneEntry * 64)()
+    n = ctypes.c_int(64)
     _check(_lib.ipx_plan_autotune(ctx, plan, _dbl(th), 1 if grad else 0, int(reps), ctypes.byref(best),
                                   ctypes.byref(best_us), table, ctypes.byref(n)))
-    rows = [({"workgroups": table[i].schedule.workgroups, "order": table[i].schedule.order,
-              "graph": table[i].schedule.graph}, table[i].us) for i in range(n.value)]
-    return {"workgroups": best.workgroups, "order": best.order, "graph": best.graph}, best_us.value, rows
+    rows = [(_sched_dict(table[i].schedule), table[i].us) for i in range(n.value)]
+    return _sched_dict(best), best_us.value, rows
 
 
 def nll_eval_batch(ctx, plan, theta, active=None, grad=False, stream=None):
@@ -404,7 +478,7 @@ def nll_eval_batch(ctx, plan, theta, active=None, grad=False, stream=None):
 
 class ServerCfg(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_int), ("scratch_bytes", ctypes.c_size_t), ("workgroups", ctypes.c_int),
-                ("idle_iterations", ctypes.c_int), ("max_pending", ctypes.c_int)]
+                ("idle_iterations", ctypes.c_int), ("max_pending", ctypes.c_int), ("policy", ctypes.c_int)]
 
 
 class _Request(ctypes.Structure):
@@ -420,8 +494,13 @@ def _result_dict(r):
     return {"status": r.status, "nll": r.nll, "grad": np.array(r.grad[:r.np]), "latency_us": r.latency_us}
 
 
-def ipx_server_start(ctx, slots=0, scratch_bytes=0, workgroups=0, idle_iterations=0, max_pending=0):
-    cfg = ServerCfg(slots, scratch_bytes, workgroups, idle_iterations, max_pending)
+SERVE_OLDEST_FIRST = 0
+SERVE_SPREAD = 1
+
+
+def ipx_server_start(ctx, slots=0, scratch_bytes=0, workgroups=0, idle_iterations=0, max_pending=0,
+                     policy=SERVE_OLDEST_FIRST):
+    cfg = ServerCfg(slots, scratch_bytes, workgroups, idle_iterations, max_pending, policy)
     h = ctypes.c_void_p()
     _check(_lib.ipx_server_start(ctx, ctypes.byref(cfg), ctypes.byref(h)))
     return h
@@ -564,3 +643,82 @@ def ipx_fp64_peak_probe(ctx):
     ghz = ctypes.c_double()
     _check(_lib.ipx_fp64_peak_probe(ctx, ctypes.byref(tf), ctypes.byref(ghz)))
     return tf.value, ghz.value
+
+
+# ---------------------------------------------------------------------------
+# Binned path
+# ---------------------------------------------------------------------------
+class _ClsResult(ctypes.Structure):
+    _fields_ = [("cl_sb", ctypes.c_double), ("cl_b", ctypes.c_double), ("cl_s", ctypes.c_double),
+                ("q_obs", ctypes.c_double), ("n_sb", ctypes.c_int64), ("n_b", ctypes.c_int64)]
+
+
+def ipx_smear(ctx, h, dx, sigma, out=None, stream=None):
+    """Gaussian smearing of the binned shape h (a float64 CUDA tensor); returns out."""
+    if not (isinstance(h, torch.Tensor) and h.is_cuda and h.dtype == torch.float64 and h.is_contiguous()):
+        raise TypeError("h must be a contiguous float64 CUDA tensor")
+    if out is None:
+        out = torch.empty_like(h)
+    _check(_lib.ipx_smear(ctx, int(h.shape[0]), float(dx), float(sigma), h.data_ptr(), out.data_ptr(),
+                          None if stream is None else _stream_ptr(stream)))
+    return out
+
+
+def ipx_hist_create(ctx, nbins, lo, hi, mu, sigma_core, sigma_smear, counts=None):
+    cp = None
+    if counts is not None:
+        counts = np.ascontiguousarray(counts, dtype=np.float64)
+        if counts.shape != (nbins,):
+            raise ValueError("counts must have nbins entries")
+        cp = counts.ctypes.data
+    h = ctypes.c_void_p()
+    _check(_lib.ipx_hist_create(ctx, int(nbins), float(lo), float(hi), float(mu), float(sigma_core),
+                                float(sigma_smear), cp, ctypes.byref(h)))
+    return h
+
+
+def ipx_hist_destroy(ctx, hist):
+    _check(_lib.ipx_hist_destroy(ctx, hist))
+
+
+def ipx_hist_read(ctx, hist, which=0):
+    out = np.empty(_lib.ipx_hist_nbins(hist))
+    _check(_lib.ipx_hist_read(ctx, hist, int(which), _dbl(out)))
+    return out
+
+
+def ipx_hist_set_counts(ctx, hist, counts):
+    c = np.ascontiguousarray(counts, dtype=np.float64)
+    _check(_lib.ipx_hist_set_counts(ctx, hist, _dbl(c)))
+
+
+def nll_binned(ctx, hist, theta, grad=False, stream=None):
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    out = np.empty(1)
+    g = np.empty(3) if grad else None
+    st = _lib.nll_binned(ctx, hist, _dbl(th), th.shape[0], _dbl(out), None if g is None else g.ctypes.data,
+                         None if stream is None else _stream_ptr(stream))
+    if st == IPX_EDOMAIN:
+        return (float("inf"), np.full(3, np.nan)) if grad else float("inf")
+    _check(st)
+    return (float(out[0]), g) if grad else float(out[0])
+
+
+def ipx_binned_toy(ctx, hist, theta, seed, hyp, toy):
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    out = np.empty(_lib.ipx_hist_nbins(hist))
+    _check(_lib.ipx_binned_toy(ctx, hist, _dbl(th), ctypes.c_uint64(seed), int(hyp), ctypes.c_uint64(toy), _dbl(out)))
+    return out
+
+
+def cls_toys(ctx, hist, theta, seed, ntoys, want_q=False):
+    """dict(cl_sb, cl_b, cl_s, q_obs, n_sb, n_b[, q_b, q_sb])."""
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    r = _ClsResult()
+    q = np.empty(2 * ntoys) if want_q else None
+    _check(_lib.cls_toys(ctx, hist, _dbl(th), ctypes.c_uint64(seed), int(ntoys), ctypes.byref(r),
+                         None if q is None else q.ctypes.data))
+    out = {k: getattr(r, k) for k, _ in _ClsResult._fields_}
+    if q is not None:
+        out["q_b"], out["q_sb"] = q[:ntoys], q[ntoys:]
+    return out

@@ -13,6 +13,10 @@ CPU reference are fed from these arrays in tests and benchmarks.
     angtime   cos(theta_K), cos(theta_l) ~ U(-1, 1), phi ~ U(-pi, pi); t as
               above with tau = 1/0.66 ps; m Gaussian (5367, 15) truncated;
               weights ~ U(0.8, 1.0)
+    ipatia    the mass sample (a peaked signal on the exponential background)
+    tagged    the angtime columns plus qd = q (1 - 2 omega): tag decision
+              q = +1 / -1 with equal probability (or fixed), mistag
+              probability omega ~ U(0.05, 0.45) (or fixed)
 """
 import numpy as np
 
@@ -81,8 +85,16 @@ def angtime_events(n, seed=BENCH_SEED + 3, weights=True):
     return [ck, cl, ph, t, st, m], w
 
 
+def tagged_events(n, seed=BENCH_SEED + 4, weights=True, q=None, omega=None):
+    cols, w = angtime_events(n, seed=seed, weights=weights)
+    rng = np.random.default_rng(seed + 1000003)
+    qq = np.where(rng.random(n) < 0.5, 1.0, -1.0) if q is None else np.full(n, float(q))
+    om = rng.uniform(0.05, 0.45, n) if omega is None else np.full(n, float(omega))
+    return cols + [qq * (1.0 - 2.0 * om)], w
+
+
 def events(model, n, seed=None, **kw):
-    fn = {1: mass_events, 2: masstime_events, 3: angtime_events}[model]
+    fn = {1: mass_events, 2: masstime_events, 3: angtime_events, 4: tagged_events, 5: mass_events}[model]
     return fn(n, **kw) if seed is None else fn(n, seed=seed, **kw)
 
 
@@ -92,3 +104,6 @@ THETA_GEN = {
     2: (0.3, 5367.0, 15.0, 0.002, 1.5, 0.7, 1.0),
     3: (0.52, 0.25, 0.05, 3.26, 3.08, 0.35, 0.66, 0.08, 17.8, -0.03, 5367.0, 15.0),
 }
+THETA_GEN[4] = THETA_GEN[3]
+# the Ipatia model: f, mu, sigma, lambda, zeta, beta, a, n, a2, n2, k
+THETA_GEN[5] = (0.3, 5367.0, 15.0, -2.5, 0.01, 0.0, 2.0, 2.5, 2.5, 3.0, 0.002)

@@ -43,9 +43,9 @@ def test_one_hip_runtime_in_process():
 
 def test_host_only_queries():
     from paper_1706_01420_amd import ipx
-    assert [ipx.ipx_model_nparams(m) for m in (1, 2, 3)] == [4, 7, 12]
-    assert [ipx.ipx_model_ncols(m) for m in (1, 2, 3)] == [1, 3, 6]
-    assert ipx.ipx_model_nparams(0) == -1 and ipx.ipx_model_ncols(4) == -1
+    assert [ipx.ipx_model_nparams(m) for m in (1, 2, 3, 4, 5)] == [4, 7, 12, 12, 11]
+    assert [ipx.ipx_model_ncols(m) for m in (1, 2, 3, 4, 5)] == [1, 3, 6, 7, 1]
+    assert ipx.ipx_model_nparams(0) == -1 and ipx.ipx_model_ncols(6) == -1
 
 
 def test_create_without_device_is_an_error_not_a_crash():

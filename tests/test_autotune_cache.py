@@ -11,13 +11,14 @@ class FakeLib:
         self.applied = []
         self.tuned = 0
 
-    def ipx_plan_set_schedule(self, plan, workgroups=0, order=0, graph=1):
-        self.applied.append((workgroups, order, graph))
+    def ipx_plan_set_schedule(self, plan, workgroups=0, order=0, graph=1, variant=0):
+        self.applied.append((workgroups, order, graph, variant))
 
     def ipx_plan_autotune(self, ctx, plan, theta, grad=True, reps=5):
         self.tuned += 1
-        rows = [({"workgroups": 0, "order": 0, "graph": 1}, 120.0), ({"workgroups": 4096, "order": 1, "graph": 0}, 100.0)]
-        return {"workgroups": 4096, "order": 1, "graph": 0}, 100.0, rows
+        rows = [({"workgroups": 0, "order": 0, "graph": 1, "variant": 0}, 120.0),
+                ({"workgroups": 4096, "order": 1, "graph": 0, "variant": 1}, 100.0)]
+        return {"workgroups": 4096, "order": 1, "graph": 0, "variant": 1}, 100.0, rows
 
 
 def test_bucket_and_key():
@@ -36,15 +37,15 @@ def test_tune_then_cache(tmp_path):
     path = str(tmp_path / "sub" / "tune.json")
     lib = FakeLib()
     s, src = autotune.tune_plan(lib, None, None, 3, None, [1000, 2000], path=path, arch="gfx950")
-    assert src == "tuned" and s == {"workgroups": 4096, "order": 1, "graph": 0} and lib.tuned == 1
+    assert src == "tuned" and s == {"workgroups": 4096, "order": 1, "graph": 0, "variant": 1} and lib.tuned == 1
     data = json.load(open(path))
     assert len(data) == 1
     (entry,) = data.values()
-    assert entry["workgroups"] == 4096 and entry["order"] == 1 and entry["graph"] == 0
+    assert entry["workgroups"] == 4096 and entry["order"] == 1 and entry["graph"] == 0 and entry["variant"] == 1
     assert len(entry["candidates"]) == 2
     s, src = autotune.tune_plan(lib, None, None, 3, None, [1100, 1900], path=path, arch="gfx950")
-    assert src == "cache" and s == {"workgroups": 4096, "order": 1, "graph": 0}
-    assert lib.tuned == 1 and lib.applied == [(4096, 1, 0)]
+    assert src == "cache" and s == {"workgroups": 4096, "order": 1, "graph": 0, "variant": 1}
+    assert lib.tuned == 1 and lib.applied == [(4096, 1, 0, 1)]
 
 
 def test_unreadable_cache_is_empty(tmp_path):

@@ -13,7 +13,8 @@ CSRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
 
 @pytest.mark.parametrize("script,header", [("gen_weideman.py", "weideman_coeffs.h"),
                                            ("gen_cfdepth.py", "cf_depth.h"),
-                                           ("gen_minimax.py", "minimax_coeffs.h")])
+                                           ("gen_minimax.py", "minimax_coeffs.h"),
+                                           ("gen_rgamma.py", "rgamma_coeffs.h")])
 def test_header_matches_generator(script, header):
     out = subprocess.run([sys.executable, os.path.join(CSRC, script)], cwd=CSRC, check=True,
                          capture_output=True, text=True, timeout=600).stdout

@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 from oracle import models as M
+from oracle import nll as N
 from paper_1706_01420_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -43,10 +44,11 @@ def _thetas(model, nb, seed):
 @pytest.mark.parametrize("model", [1, 2, 3])
 def test_batch_equals_plain_bitwise(lib, ctx, model):
     sizes = [0, 1, 1023, 1024, 5000, 13331, 777]
-    ds = []
+    ds, data = [], []
     try:
         for j, n in enumerate(sizes):
             cols, w = W.events(model, n, seed=100 + j)
+            data.append((cols, w))
             ds.append(lib.ipx_dataset_create(ctx, model, cols, w))
         th = _thetas(model, len(ds), model)
         say("batch vs plain model", model)
@@ -59,6 +61,14 @@ def test_batch_equals_plain_bitwise(lib, ctx, model):
                     assert f[j] == lib.nll_eval(ctx, d, th[j]), (rep, j)
                     fj, gj = lib.nll_grad(ctx, d, th[j])
                     assert fg[j] == fj and np.array_equal(g[j], gj), (rep, j)
+            # and two entries directly against the oracle
+            for j in (4, 5):
+                cols, w = data[j]
+                fref, gref = N.nll_grad(model, cols, th[j], w)
+                assert abs(fg[j] - fref) <= 1e-10 * abs(fref), (j, fg[j], fref)
+                scale = np.abs(N.event_grad(model, cols, th[j]) * (1.0 if w is None else w)).sum(axis=1)
+                bound = 1e-6 * np.abs(gref) + 1e-9 * scale + 1e-13 * sizes[j]
+                assert np.all(np.abs(g[j] - gref) <= bound), (j, g[j], gref)
             # masks: inactive entries are skipped, active ones unchanged
             act = np.array([j % 2 for j in range(len(ds))], dtype=np.uint8)
             th2 = th * (1 + 1e-3)

@@ -43,20 +43,23 @@ def test_schedules_do_not_change_results(lib, ctx, model):
         thb = np.tile(th, (len(ds), 1)) * (1.0 + 1e-3 * rng.standard_normal((len(ds), th.size)))
         ref_f, ref_g = lib.nll_eval_batch(ctx, plan, thb, grad=True)
         ref_e = lib.nll_eval_batch(ctx, plan, thb)
-        for wg, order, graph in [(w, o, 1) for w in (0, 1, 7, 256, 2048) for o in (0, 1)] + [(0, 0, 0), (7, 1, 0)]:
-            lib.ipx_plan_set_schedule(plan, wg, order, graph)
-            assert lib.ipx_plan_get_schedule(plan) == {"workgroups": wg, "order": order, "graph": graph}
+        variants = (0, 1) if model == 3 else (0,)
+        for wg, order, graph, var in ([(w, o, 1, v) for w in (0, 1, 7, 256, 2048) for o in (0, 1) for v in variants]
+                                      + [(0, 0, 0, 0), (7, 1, 0, variants[-1])]):
+            lib.ipx_plan_set_schedule(plan, wg, order, graph, var)
+            assert lib.ipx_plan_get_schedule(plan) == {"workgroups": wg, "order": order, "graph": graph,
+                                                       "variant": var}
             for _ in range(2):   # the first call captures the graph (if any), the second replays it
                 f, g = lib.nll_eval_batch(ctx, plan, thb, grad=True)
-                assert np.array_equal(f, ref_f) and np.array_equal(g, ref_g), (wg, order, graph)
-                assert np.array_equal(lib.nll_eval_batch(ctx, plan, thb), ref_e), (wg, order, graph)
+                assert np.array_equal(f, ref_f) and np.array_equal(g, ref_g), (wg, order, graph, var)
+                assert np.array_equal(lib.nll_eval_batch(ctx, plan, thb), ref_e), (wg, order, graph, var)
         best, us, rows = lib.ipx_plan_autotune(ctx, plan, thb, grad=True, reps=2)
         say("autotune", best, round(us, 1), rows)
         assert best in [r[0] for r in rows] and us == min(r[1] for r in rows)
         assert lib.ipx_plan_get_schedule(plan) == best
         f, g = lib.nll_eval_batch(ctx, plan, thb, grad=True)
         assert np.array_equal(f, ref_f) and np.array_equal(g, ref_g)
-        for bad in ((-1, 0, 1), (0, 2, 1), (0, 0, 2)):
+        for bad in ((-1, 0, 1), (0, 2, 1), (0, 0, 2), (0, 0, 1, 2) if model == 3 else (0, 0, 1, 1)):
             with pytest.raises(lib.IpxError) as e:
                 lib.ipx_plan_set_schedule(plan, *bad)
             assert e.value.status == lib.IPX_EINVAL

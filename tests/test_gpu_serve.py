@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 from oracle import models as M
+from oracle import nll as N
 from paper_1706_01420_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -31,10 +32,13 @@ def ctx(lib):
     lib.ipx_destroy(c)
 
 
+DATASET_SIZES = ((1, [1000, 50000]), (2, [777, 40000]), (3, [1, 5000, 100000]))
+
+
 @pytest.fixture(scope="module")
 def datasets(lib, ctx):
     out = []
-    for model, sizes in ((1, [1000, 50000]), (2, [777, 40000]), (3, [1, 5000, 100000])):
+    for model, sizes in DATASET_SIZES:
         for j, n in enumerate(sizes):
             cols, w = W.events(model, n, seed=300 + 10 * model + j)
             out.append((model, lib.ipx_dataset_create(ctx, model, cols, w)))
@@ -72,6 +76,18 @@ def test_single_requests_equal_plain_calls(lib, ctx, datasets):
                 if grad:
                     assert np.array_equal(r["grad"], g)
                 assert r["latency_us"] > 0
+        # two served requests directly against the oracle
+        for model, j in ((2, 0), (3, 1)):
+            n = DATASET_SIZES[model - 1][1][j]
+            cols, w = W.events(model, n, seed=300 + 10 * model + j)
+            d = [dd for mm, dd in datasets if mm == model][j]
+            th = _theta(model, rng)
+            r = lib.ipx_wait(srv, lib.ipx_submit(srv, d, th, True), 60.0)
+            fref, gref = N.nll_grad(model, cols, th, w)
+            assert abs(r["nll"] - fref) <= 1e-10 * abs(fref), (model, r["nll"], fref)
+            scale = np.abs(N.event_grad(model, cols, th) * (1.0 if w is None else w)).sum(axis=1)
+            bound = 1e-6 * np.abs(gref) + 1e-9 * scale + 1e-13 * n
+            assert np.all(np.abs(r["grad"] - gref) <= bound), (model, r["grad"], gref)
     finally:
         lib.ipx_server_stop(srv)
 

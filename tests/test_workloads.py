@@ -23,3 +23,14 @@ def test_shapes_ranges_and_seeding():
             assert w.min() >= 0.8 and w.max() <= 1.0
         else:
             assert w is None
+
+
+def test_tagged_column():
+    cols, w = W.events(4, 4000, seed=2)
+    base, _ = W.events(3, 4000, seed=2)
+    assert len(cols) == 7 and all(np.array_equal(a, b) for a, b in zip(cols[:6], base))
+    qd = cols[6]
+    assert np.all(np.abs(qd) <= 0.9 + 1e-15) and np.all(np.abs(qd) >= 0.1 - 1e-15)
+    assert 0.4 < np.mean(qd > 0) < 0.6
+    c1, _ = W.events(4, 100, seed=2, q=-1.0, omega=0.0)
+    assert np.all(c1[6] == -1.0)
