@@ -498,7 +498,10 @@ IPX_API ipx_status ipx_event_logp(ipx_ctx *ctx, const ipx_dataset *ds, const dou
  * ipx_smear: S_b = sum_j h_j g(x_b - x_j) dx over n bins of width dx, g the
  *   unit Gaussian density of width sigma (the rectangle rule of the
  *   convolution integral, no wrap-around); h and out are DEVICE arrays of n
- *   doubles (caller-owned, not overlapping); synchronous on `stream`.
+ *   doubles (caller-owned, not overlapping); synchronous on `stream`.  Its
+ *   work space ((2n - 1) + c n doubles, c <= 2048 input chunks, c n held to
+ *   2^23 where n allows) is kept by the context, grown when a call needs
+ *   more and freed by ipx_destroy; calls on one context take turns.
  * ipx_hist_create: counts (host, nullable = all zero) are non-negative
  *   integers stored as doubles; 1 <= nbins <= 2^24.
  * ipx_hist_read: which = 0 copies the signal template, 1 the counts, to host

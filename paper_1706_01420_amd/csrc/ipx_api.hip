@@ -74,6 +74,9 @@ struct ipx_ctx {
   int ev_used = 0;
   double timing_ms = 0.0;
   int64_t timing_launches = 0;
+  std::mutex ws_mu;                // guards the smearing workspace
+  double* smear_ws = nullptr;      // kernel table and chunk partials of ipx_smear (grows, kept)
+  size_t smear_ws_doubles = 0;
 };
 
 struct ipx_dataset {
@@ -237,6 +240,7 @@ void ipx_destroy(ipx_ctx* c) {
     (void)hipEventDestroy(c->ev_pool[1][i]);
   }
   (void)hipStreamDestroy(c->stream);
+  if (c->smear_ws) (void)hipFree(c->smear_ws);
   delete c;
 }
 
@@ -2478,16 +2482,31 @@ ipx_status ipx_smear(ipx_ctx* ctx, int n, double dx, double sigma, const double*
   if (n == 0) return IPX_OK;
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
-  double* kern = nullptr;
-  HIP_TRY(hipMalloc(&kern, (size_t)(2 * n - 1) * sizeof(double)));
+  int chunks = 1, steps = 1;
+  smear_grid(n, &chunks, &steps);
+  // the kernel table (2n - 1), then the chunk partials (chunks x n), in the
+  // context's workspace (allocated on first need, grown, kept until
+  // ipx_destroy); calls on one context take turns
+  std::lock_guard<std::mutex> lk(ctx->ws_mu);
+  const size_t need = (size_t)(2 * n - 1) + (size_t)chunks * n;
+  if (need > ctx->smear_ws_doubles) {
+    if (ctx->smear_ws) HIP_TRY(hipFree(ctx->smear_ws));
+    ctx->smear_ws = nullptr;
+    ctx->smear_ws_doubles = 0;
+    HIP_TRY(hipMalloc(&ctx->smear_ws, need * sizeof(double)));
+    ctx->smear_ws_doubles = need;
+  }
+  double* kern = ctx->smear_ws;
+  double* part = kern + (2 * n - 1);
   hipLaunchKernelGGL(k_smear_kernel, dim3((2 * n - 1 + kThreads - 1) / kThreads), dim3(kThreads), 0, s, kern, n, dx, sigma);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_smear, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, h, kern, out, n);
+    hipLaunchKernelGGL(k_smear_part, dim3((n + kSmearOut - 1) / kSmearOut, chunks), dim3(kThreads), 0, s, h, kern, part,
+                       n, steps);
+    hipLaunchKernelGGL(k_smear_sum, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, part, out, n, chunks);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(kern);
   if (e != hipSuccess) return fail(IPX_EDEVICE, "ipx_smear: %s", hipGetErrorString(e));
   return IPX_OK;
 }
@@ -2513,7 +2532,10 @@ ipx_status ipx_hist_create(ipx_ctx* ctx, int nbins, double lo, double hi, double
   H->dx = (hi - lo) / nbins;
   H->nwg = (nbins + kThreads - 1) / kThreads;
   const int n = nbins;
-  const size_t wd = std::max(hist_work_doubles(n, H->nwg), (size_t)(3 * n));   // the smearing's kernel and core first
+  int chunks = 1, steps = 1;
+  smear_grid(n, &chunks, &steps);
+  // the smearing's kernel, core and chunk partials first
+  const size_t wd = std::max(hist_work_doubles(n, H->nwg), (size_t)(3 * n) + (size_t)chunks * n);
   hipError_t e = hipMalloc(&H->sig, n * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&H->cnt, n * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&H->work, wd * sizeof(double));
@@ -2525,10 +2547,13 @@ ipx_status ipx_hist_create(ipx_ctx* ctx, int nbins, double lo, double hi, double
   hipStream_t s = ctx->stream;
   double* kern = H->work;              // 2n - 1
   double* core = H->work + 2 * n;      // n (overlaps nothing of kern: 2n - 1 < 2n)
+  double* part = H->work + 3 * n;      // chunks x n
   const unsigned g1 = (unsigned)((n + kThreads - 1) / kThreads), g2 = (unsigned)((2 * n - 1 + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(k_gauss_core, dim3(g1), dim3(kThreads), 0, s, core, n, lo, H->dx, mu, sigma_core);
   hipLaunchKernelGGL(k_smear_kernel, dim3(g2), dim3(kThreads), 0, s, kern, n, H->dx, sigma_smear);
-  hipLaunchKernelGGL(k_smear, dim3(g1), dim3(kThreads), 0, s, core, kern, H->sig, n);
+  hipLaunchKernelGGL(k_smear_part, dim3((n + kSmearOut - 1) / kSmearOut, chunks), dim3(kThreads), 0, s, core, kern, part,
+                     n, steps);
+  hipLaunchKernelGGL(k_smear_sum, dim3(g1), dim3(kThreads), 0, s, part, H->sig, n, chunks);
   hipLaunchKernelGGL(k_sum, dim3(1), dim3(kThreads), 0, s, H->sig, n, H->host);
   e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(s);

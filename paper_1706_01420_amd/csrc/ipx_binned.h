@@ -6,8 +6,8 @@
 // Conventions (equal bins of width dx on [lo, hi), centres x_b = lo + (b + 1/2) dx):
 //   smearing     S_b = sum_j h_j g(x_b - x_j) dx, g the unit Gaussian density
 //                (the rectangle rule of the convolution integral, no
-//                wrap-around at the ends); a banded Toeplitz product, tiled
-//                through LDS: 256 outputs per workgroup, 256 inputs per step.
+//                wrap-around at the ends); a Toeplitz product, tiled over
+//                outputs and input chunks through LDS (k_smear_part).
 //   background   e_b = exp(-k (x_b - x_0)) / Z, Z = sum_b exp(-k b dx) in
 //                closed form (a geometric sum).
 //   likelihood   NLL = sum_b [nu_b - n_b ln nu_b], nu_b = ns s_b + nb e_b.
@@ -54,28 +54,93 @@ __global__ __launch_bounds__(kThreads) void k_smear_kernel(double* __restrict__ 
   kern[i] = exp(-d * d / (2.0 * sigma * sigma)) / (2.5066282746310005024 * sigma) * dx;
 }
 
-// out[b] = sum_j h[j] kern[b - j + n - 1].
-__global__ __launch_bounds__(kThreads) void k_smear(const double* __restrict__ h, const double* __restrict__ kern,
-                                                    double* __restrict__ out, int n) {
-  __shared__ double sh[kThreads];
-  __shared__ double sk[2 * kThreads];
-  const int b0 = blockIdx.x * kThreads;
+// Smearing as a Toeplitz product out[b] = sum_j h[j] kern[b - j + n - 1],
+// tiled over outputs and inputs: workgroup (bx, by) takes the 1024 outputs
+// from 1024 bx and the inputs of chunk by (kSmearChunk x steps inputs from
+// jA = by x steps x kSmearChunk) and writes its partial sums to
+// part[by n + b]; k_smear_sum adds the chunks in order.  Lane t holds the
+// four outputs 1024 bx + 4t + r.  Per step of 256 inputs the workgroup stages
+// the 1279 kernel values the tile touches and the 256 inputs in LDS; per
+// eight inputs a lane reads the eleven kernel values its 4 x 8 products use
+// (output r and input q take value r - q + 7 of the window) and eight inputs
+// as four broadcast pairs, then does 32 fused multiply-adds.  The kernel
+// values are stored skewed (position i + i / 4) so that the lanes' windows,
+// four values apart, spread over the banks.  Each output's products are
+// added in increasing input order.
+constexpr int kSmearOut = 1024;       // outputs per workgroup (4 per lane)
+constexpr int kSmearChunk = 256;      // inputs staged per step
+constexpr int kSmearWin = kSmearOut + kSmearChunk - 1;
+__device__ __forceinline__ int smear_pos(int i) { return i + (i >> 2); }
+
+__global__ __launch_bounds__(kThreads) void k_smear_part(const double* __restrict__ h, const double* __restrict__ kern,
+                                                         double* __restrict__ part, int n, int steps) {
+  __shared__ double sk[kSmearWin + kSmearWin / 4 + 4];
+  __shared__ __attribute__((aligned(16))) double sh[kSmearChunk];
   const int t = threadIdx.x;
-  double acc = 0.0;
-  for (int j0 = 0; j0 < n; j0 += kThreads) {
-    sh[t] = j0 + t < n ? h[j0 + t] : 0.0;
-    // kernel indices b - j + n - 1 for b in [b0, b0 + 255], j in [j0, j0 + 255]
-    const int base = b0 - j0 - (kThreads - 1) + n - 1;
-    for (int s = t; s < 2 * kThreads; s += kThreads) {
-      const int i = base + s;
-      sk[s] = (i >= 0 && i < 2 * n - 1) ? kern[i] : 0.0;
+  const int b0 = blockIdx.x * kSmearOut;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int st = 0; st < steps; ++st) {
+    const int jA = (blockIdx.y * steps + st) * kSmearChunk;
+    if (jA >= n) break;
+    // kernel index of window entry i: b0 - jA + n - kSmearChunk + i
+    const int kb = b0 - jA + n - kSmearChunk;
+    __syncthreads();  // the previous step's reads are done
+    for (int i = t; i < kSmearWin; i += kThreads) {
+      const int g = kb + i;
+      sk[smear_pos(i)] = (g >= 0 && g < 2 * n - 1) ? kern[g] : 0.0;
     }
+    sh[t] = jA + t < n ? h[jA + t] : 0.0;
     __syncthreads();
-#pragma unroll 8
-    for (int jj = 0; jj < kThreads; ++jj) acc = fma(sh[jj], sk[t - jj + kThreads - 1], acc);
-    __syncthreads();
+#pragma unroll 2
+    for (int jb = 0; jb < kSmearChunk; jb += 8) {
+      // window entry base + s, base = 4t - jb + kSmearChunk - 8 (a multiple of 4)
+      const int u = t - (jb >> 2) + (kSmearChunk >> 2) - 2;
+      double w[11];
+#pragma unroll
+      for (int s = 0; s < 11; ++s) w[s] = sk[5 * u + s + (s >> 2)];
+      const double2* hp = reinterpret_cast<const double2*>(sh + jb);
+      double hv[8];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double2 v = hp[q];
+        hv[2 * q] = v.x;
+        hv[2 * q + 1] = v.y;
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] = fma(hv[q], w[r - q + 7], acc[r]);
+    }
   }
-  if (b0 + t < n) out[b0 + t] = acc;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int b = b0 + 4 * t + r;
+    if (b < n) part[(size_t)blockIdx.y * n + b] = acc[r];
+  }
+}
+
+// out[b] = sum over c < nc of part[c n + b], c in increasing order.
+__global__ __launch_bounds__(kThreads) void k_smear_sum(const double* __restrict__ part, double* __restrict__ out,
+                                                        int n, int nc) {
+  const int b = blockIdx.x * kThreads + threadIdx.x;
+  if (b >= n) return;
+  double s = 0.0;
+  for (int c = 0; c < nc; ++c) s += part[(size_t)c * n + b];
+  out[b] = s;
+}
+
+// Input chunks of a smearing launch: enough workgroups to fill the chip, the
+// partials held to 2^23 doubles (64 MiB) where n allows.
+inline void smear_grid(int n, int* chunks, int* steps) {
+  const int nstep = (n + kSmearChunk - 1) / kSmearChunk;
+  const int nout = (n + kSmearOut - 1) / kSmearOut;
+  int c = (2048 + nout - 1) / nout;                       // ~2048 workgroups
+  const long long cap = (1ll << 23) / (n > 0 ? n : 1);
+  if (c > cap) c = (int)cap;
+  if (c > nstep) c = nstep;
+  if (c < 1) c = 1;
+  *steps = (nstep + c - 1) / c;
+  *chunks = (nstep + *steps - 1) / *steps;
 }
 
 // core[b] = exp(-(x_b - mu)^2 / (2 sigma^2)).
