@@ -379,10 +379,13 @@ typedef struct {
                               when work arrives */
   int max_pending;         /* waiting requests accepted (0 = unlimited) */
   int policy;              /* how workgroups pick among admitted requests:
-                              0 = the oldest admitted request first (its tiles
+                              0 = each workgroup from its own starting slot
+                              (admitted requests share the workgroups; the
+                              lowest latency measured),
+                              1 = the oldest admitted request first (its tiles
                               are all claimed before a younger one's),
-                              1 = each workgroup from its own starting slot
-                              (admitted requests share the workgroups) */
+                              2 = the request with the fewest unclaimed
+                              tiles first */
 } ipx_server_cfg;
 typedef struct {
   const ipx_dataset *ds;

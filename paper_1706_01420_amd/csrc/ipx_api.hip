@@ -1732,7 +1732,7 @@ extern "C" ipx_status ipx_server_start(ipx_ctx* ctx, const ipx_server_cfg* cfg, 
   if (c.slots > kServeMaxSlots) return fail(IPX_EINVAL, "ipx_server_start: at most %d slots", kServeMaxSlots);
   if (c.scratch_bytes == 0) c.scratch_bytes = (size_t)1 << 31;
   if (c.workgroups == 0) c.workgroups = 3 * std::max(1, ctx->n_cu);
-  if (c.policy != kServeOldestFirst && c.policy != kServeSpread)
+  if (c.policy != kServeOldestFirst && c.policy != kServeSpread && c.policy != kServeFewestFirst)
     return fail(IPX_EINVAL, "ipx_server_start: unknown claim policy %d", c.policy);
   if (c.workgroups < 2) return fail(IPX_EINVAL, "ipx_server_start: at least 2 workgroups (one polls the host)");
   if (c.idle_iterations <= 0) c.idle_iterations = 20000;

@@ -12,10 +12,12 @@
 //           claim[s] = seq << 32 and sets the slot's bit in the claimable-slot
 //           mask.
 //   workers take one item at a time with one atomic add on claim[s] of a
-//           slot in the mask: the oldest opened request first (policy 0:
-//           the first wave reads the open stamps of the claimable slots and
-//           picks the smallest), or each workgroup from its own starting slot
-//           (policy 1, requests spread over the workers); the returned word
+//           slot in the mask: each workgroup from its own starting slot
+//           (policy 0, requests spread over the workers), the oldest opened
+//           request first (policy 1: the first wave reads the open stamps of
+//           the claimable slots and picks the smallest), or the request with
+//           the fewest unclaimed items first (policy 2: the first wave reads
+//           the claim and limit words of the claimable slots); the returned word
 //           names the request (high half) and the item (low half).  The item is valid if lim[s] names the same
 //           request and the item is below its count; any other increment is a
 //           late claim on a finished request and is dropped, so no request
@@ -88,7 +90,7 @@ struct ServeCtl {                  // device memory
 };
 
 // Claim policies of the workers.
-enum : int { kServeOldestFirst = 0, kServeSpread = 1 };
+enum : int { kServeSpread = 0, kServeOldestFirst = 1, kServeFewestFirst = 2 };
 
 struct ServeShared {               // fine-grained host memory
   unsigned long long gen;          // bumped by the host after each publication
@@ -228,10 +230,11 @@ __device__ __forceinline__ void serve_work(ServeShared* hs, ServeCtl* ctl, Serve
   __shared__ int last;
   const unsigned rot = blockIdx.x & 63u;  // spreads the workers' first choice over the slots
   for (;;) {
-    if (policy == kServeOldestFirst) {
-      // the first wave picks the claimable slot with the smallest open stamp
-      // (lane s reads slot s's stamp); thread 0 claims, and on a refusal
-      // (the slot ran out of items meanwhile) the next oldest is tried
+    if (policy != kServeSpread) {
+      // the first wave picks the claimable slot with the smallest key (lane s
+      // reads slot s's open stamp, or its unclaimed items); thread 0 claims,
+      // and on a refusal (the slot ran out of items meanwhile) the next
+      // smallest is tried
       if (threadIdx.x < 64) {
         const unsigned lane = threadIdx.x;
         int ex = 0;
@@ -245,7 +248,18 @@ __device__ __forceinline__ void serve_work(ServeShared* hs, ServeCtl* ctl, Serve
         int got = 0;
         if (lane == 0) cmd = ex ? kCmdExit : kCmdIdle;
         if (!ex && m != 0ull) {
-          const unsigned long long stamp = ((m >> lane) & 1ull) ? load_dev(&st[lane].stamp) : ~0ull;
+          unsigned long long stamp = ~0ull;
+          if ((m >> lane) & 1ull) {
+            if (policy == kServeOldestFirst) {
+              stamp = load_dev(&st[lane].stamp);
+            } else {
+              // unclaimed items of the request the claim word names (a
+              // claim word of another request, or none left: last)
+              const unsigned long long c = load_dev(&st[lane].claim), l = load_dev(&st[lane].lim);
+              const unsigned next = (unsigned)(c & 0xffffffffull), n = (unsigned)(l & 0xffffffffull);
+              stamp = ((c >> 32) == (l >> 32) && next < n) ? (unsigned long long)(n - next) : (1ull << 40);
+            }
+          }
           while (m != 0ull && !got) {
             unsigned long long key = ((m >> lane) & 1ull) ? ((stamp << 6) | lane) : ~0ull;
 #pragma unroll

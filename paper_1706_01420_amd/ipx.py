@@ -494,12 +494,13 @@ def _result_dict(r):
     return {"status": r.status, "nll": r.nll, "grad": np.array(r.grad[:r.np]), "latency_us": r.latency_us}
 
 
-SERVE_OLDEST_FIRST = 0
-SERVE_SPREAD = 1
+SERVE_SPREAD = 0
+SERVE_OLDEST_FIRST = 1
+SERVE_FEWEST_FIRST = 2
 
 
 def ipx_server_start(ctx, slots=0, scratch_bytes=0, workgroups=0, idle_iterations=0, max_pending=0,
-                     policy=SERVE_OLDEST_FIRST):
+                     policy=SERVE_SPREAD):
     cfg = ServerCfg(slots, scratch_bytes, workgroups, idle_iterations, max_pending, policy)
     h = ctypes.c_void_p()
     _check(_lib.ipx_server_start(ctx, ctypes.byref(cfg), ctypes.byref(h)))

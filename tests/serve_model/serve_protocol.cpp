@@ -10,7 +10,8 @@
 //            order, sets open/done/lim, publishes claim[s] = seq << 32
 //            (release) and the slot's bit in the mask.
 //   workers  take one item with one fetch_add on claim[s] of a slot in the
-//            mask (oldest stamp first, or from a per-worker starting slot);
+//            mask (from a per-worker starting slot, oldest stamp first, or
+//            fewest unclaimed items first, read from the claim and lim words);
 //            the item is valid iff lim[s] names the same sequence number and
 //            the item is below its count; the last valid item clears the
 //            mask bit; after the item, done[s] += 1 (acq_rel), and the worker
@@ -73,7 +74,7 @@ struct Request {
 
 struct Model {
   int nslots = 4;
-  int policy = 0;            // 0 oldest first, 1 spread
+  int policy = 0;            // 0 spread, 1 oldest first, 2 fewest unclaimed items first
   // host <-> device words
   std::atomic<uint64_t> gen{0}, stop{0};
   std::atomic<uint64_t> mail[kMaxSlots];
@@ -166,17 +167,33 @@ void worker(Model& M, int id) {
   const unsigned rot = (unsigned)id & 63u;
   for (;;) {
     if (M.stop.load(std::memory_order_acquire) || M.quit.load(std::memory_order_acquire)) break;
+    if (M.late_worker >= 0 && id != M.late_worker && M.late_phase.load() == 0) {
+      // forced interleaving: the others start only once the late worker has
+      // chosen its slot (else they could finish the first request before it
+      // looks, and the host would wait for a choice that never comes)
+      std::this_thread::yield();
+      continue;
+    }
     uint64_t m = M.mask.load(std::memory_order_acquire);
     int s = -1, item = -1;
-    if (M.policy == 0) {
+    if (M.policy != 0) {
       while (m != 0 && s < 0) {
         int best = -1;
         uint64_t bst = ~0ull;
         for (int k = 0; k < M.nslots; ++k)
           if ((m >> k) & 1ull) {
-            const uint64_t v = M.st[k].stamp.load(std::memory_order_relaxed);
+            uint64_t v;
+            if (M.policy == 1) {
+              v = M.st[k].stamp.load(std::memory_order_relaxed);
+            } else {
+              const uint64_t c = M.st[k].claim.load(std::memory_order_relaxed);
+              const uint64_t l = M.st[k].lim.load(std::memory_order_relaxed);
+              const unsigned next = (unsigned)(c & 0xffffffffull), n = (unsigned)(l & 0xffffffffull);
+              v = ((c >> 32) == (l >> 32) && next < n) ? (uint64_t)(n - next) : (1ull << 40);
+            }
             if (v < bst) { bst = v; best = k; }
           }
+        if (best < 0) break;
         const uint64_t seen = M.st[best].claim.load(std::memory_order_relaxed) >> 32;
         if (id == M.late_worker && M.late_phase.load() == 0) {
           M.late_phase.store(1);

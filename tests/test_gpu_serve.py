@@ -92,8 +92,9 @@ def test_single_requests_equal_plain_calls(lib, ctx, datasets):
         lib.ipx_server_stop(srv)
 
 
-def test_mixed_concurrent_traffic_is_bitwise_equal_to_alone(lib, ctx, datasets):
-    srv = lib.ipx_server_start(ctx, slots=16)
+@pytest.mark.parametrize("policy", [0, 1, 2])
+def test_mixed_concurrent_traffic_is_bitwise_equal_to_alone(lib, ctx, datasets, policy):
+    srv = lib.ipx_server_start(ctx, slots=16, policy=policy)
     rng = np.random.default_rng(2)
     jobs = []
     for i in range(160):
@@ -114,7 +115,7 @@ def test_mixed_concurrent_traffic_is_bitwise_equal_to_alone(lib, ctx, datasets):
             else:
                 results[i] = lib.ipx_wait(srv, t, 60.0)
     try:
-        say("serve mixed traffic 160 requests, 8 client threads")
+        say("serve mixed traffic 160 requests, 8 client threads, policy", policy)
         threads = [threading.Thread(target=client, args=(k,)) for k in range(8)]
         for th in threads:
             th.start()

@@ -2,7 +2,7 @@
 (tests/serve_model/serve_protocol.cpp: the same claim, limit, done and fin
 words and rules as the device loop) and run under ThreadSanitizer:
 
-  * random traffic, both claim policies, several slot and worker counts:
+  * random traffic, the three claim policies, several slot and worker counts:
     every item processed once, every request completed once with its sum,
     no data race on the descriptors, partials or results;
   * a forced late claim: a worker that chose a slot while its request was
@@ -37,7 +37,7 @@ def model_bin(tmp_path_factory):
     return _build(tmp_path_factory.mktemp("serve_model"), "serve_protocol")
 
 
-@pytest.mark.parametrize("policy", [0, 1])
+@pytest.mark.parametrize("policy", [0, 1, 2])
 @pytest.mark.parametrize("workers,slots,seed", [(4, 4, 1), (7, 2, 2), (3, 16, 3), (12, 64, 4)])
 def test_random_traffic_under_tsan(model_bin, policy, workers, slots, seed):
     r = subprocess.run([model_bin, "stress", str(policy), "200", str(workers), str(slots), str(seed)],
@@ -46,7 +46,7 @@ def test_random_traffic_under_tsan(model_bin, policy, workers, slots, seed):
     assert "ThreadSanitizer" not in r.stderr
 
 
-@pytest.mark.parametrize("policy", [0, 1])
+@pytest.mark.parametrize("policy", [0, 1, 2])
 def test_late_claim_lands_on_the_next_request(model_bin, policy):
     r = subprocess.run([model_bin, "late", str(policy)], capture_output=True, text=True, env=ENV, timeout=120)
     assert r.returncode == 0, r.stdout + r.stderr
@@ -54,6 +54,6 @@ def test_late_claim_lands_on_the_next_request(model_bin, policy):
 
 def test_old_claim_rule_loses_the_item(tmp_path):
     old = _build(tmp_path, "serve_protocol_old", ("-DOLD_PROTOCOL",))
-    r = subprocess.run([old, "late", "0"], capture_output=True, text=True, env=ENV, timeout=120)
+    r = subprocess.run([old, "late", "1"], capture_output=True, text=True, env=ENV, timeout=120)
     assert r.returncode == 3, r.stdout + r.stderr
     assert "stalled" in r.stderr
