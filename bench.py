@@ -113,7 +113,7 @@ def parse():
 # HBM traffic of the dominant kernel from the rocprofv3 FETCH_SIZE / WRITE_SIZE
 # runs (scaled by the calibration copy), valid for the kernel sources whose
 # hash is recorded with it; reported as null once those sources change.
-TRAFFIC = {"sources_sha256": "5ed94381a4ce68d56679b9d979bb9a3148acd5da62a532eb3e03e65efa3535d5", "bytes_per_launch": 251386669}
+TRAFFIC = {"sources_sha256": "5b6c513fa38e1a7638d6f444d8b883adfd7760a46f1af027964a206c94f3378d", "bytes_per_launch": 251416576}
 KERNEL_SOURCES = ["ipx_kernels.h", "ipx_batch.h", "ipx_math.h", "ipx_models.h", "weideman_coeffs.h", "cf_depth.h",
                   "minimax_coeffs.h"]
 
@@ -382,18 +382,21 @@ def bench_batched_fits(ipx, ctx, ntoys=512, plain_subset=64, seed=170601424):
                          "candidates": [[r[0]["workgroups"], r[0]["order"], r[0]["graph"], round(r[1], 1)] for r in rows]}}
 
 
-def bench_served(ipx, ctx, ndatasets=64, nclients=256, nreq=600, seed=170601425):
+SERVE_POLICY_NAMES = {0: "spread", 1: "oldest_first", 2: "fewest_first"}
+
+
+def bench_served(ipx, ctx, ndatasets=64, nclients=256, nreq=600, seed=170601425,
+                 policies=((0, (0.5, 0.8, None)),)):
     """Served likelihood: 64 resident datasets (models cycled 1, 2, 3; sizes
     log-uniform in [1e3, 5e6]; generated on the device), 256 clients (half
     random-walk chains asking NLL only, half minimisers asking NLL +
     gradient), Poisson arrivals at 0.5x and 0.8x the plain one-call-per-request
-    throughput.  Latency = submission to completion."""
+    throughput.  Latency = submission to completion.  The first claim policy
+    listed gives the main figures; the others, run on the same datasets and
+    the same arrival times, are reported beside them."""
     import numpy as np
     from paper_1706_01420_amd import workloads
     sizes, models, reqs = served_mix(ndatasets, nclients, nreq, seed)
-    # arrival times from their own stream (the original interleaved them with
-    # the mix's draws after the requests)
-    rng = np.random.default_rng(seed + 1)
     ds = []
     try:
         for j in range(ndatasets):
@@ -415,67 +418,177 @@ def bench_served(ipx, ctx, ndatasets=64, nclients=256, nreq=600, seed=170601425)
                "plain_evals_per_s": plain_rate,
                "plain_latency_us_p50": float(np.percentile(lat_plain, 50)),
                "plain_latency_us_p99": float(np.percentile(lat_plain, 99))}
-        srv = ipx.ipx_server_start(ctx, slots=64)
-        try:
-            # warm-up (untimed): the first launch of the device loop and every
-            # dataset's first request
-            warm = [ipx.ipx_submit(srv, ds[j], np.array(workloads.THETA_GEN[models[j]]), g)
-                    for j in range(ndatasets) for g in (False, True)]
-            for t in warm:
-                ipx.ipx_wait(srv, t, 60.0)
-            for frac in (0.5, 0.8, None):
-                key = "served_at_%.1fx" % frac if frac is not None else "served_saturated"
-                # one thread submits at the paced times, then collects: latencies
-                # are stamped inside the library (submission to completion), so no
-                # Python thread sits between a request and its result
-                tickets = []
-                results = []
-                errors = []
-                t_end = time.perf_counter() + 60.0   # the whole rate step is bounded
-                # the arrival process is paced by this Python loop: a collection of
-                # the interpreter's garbage (tens of ms with the objects of the
-                # earlier legs) would stall it and release a burst
-                gc.collect()
-                gc.disable()
-                t0 = time.perf_counter()
-                nxt = t0
-                t_sub = []
-                for j, th, g in reqs:
-                    if frac is not None:
-                        nxt += rng.exponential(1.0 / (frac * plain_rate))
-                        while time.perf_counter() < nxt:
-                            pass
-                    t_sub.append(time.perf_counter())
-                    tickets.append(ipx.ipx_submit(srv, ds[j], th, g))
-                try:
-                    for t in tickets:
-                        results.append(ipx.ipx_wait(srv, t, max(t_end - time.perf_counter(), 0.0)))
-                except ipx.IpxError as e:
-                    errors.append(str(e))
-                finally:
-                    gc.enable()
-                # from the first submission to the last completion (submission
-                # time + the library's latency stamp), not to the end of the
-                # collection loop
-                elapsed = (max(ts + r["latency_us"] * 1e-6 for ts, r in zip(t_sub, results)) - t0
-                           if len(results) == nreq else time.perf_counter() - t0)
-                if errors or len(results) < nreq:
-                    out[key] = {"error": errors[0] if errors else "incomplete", "completed": len(results),
-                                "server": ipx.ipx_server_stats_read(srv)}
-                    break
-                lat = np.array([r["latency_us"] for r in results])
-                out[key] = {"offered_per_s": None if frac is None else frac * plain_rate,
-                            "evals_per_s": nreq / elapsed,
-                            "latency_us_p50": float(np.percentile(lat, 50)),
-                            "latency_us_p99": float(np.percentile(lat, 99)),
-                            "all_ok": bool(all(r["status"] == 0 for r in results)),
-                            "server": ipx.ipx_server_stats_read(srv)}
-        finally:
-            ipx.ipx_server_stop(srv)
+        for i, (policy, rates) in enumerate(policies):
+            res = _served_rates(ipx, ctx, ds, models, reqs, plain_rate, policy, rates, seed)
+            if i == 0:
+                out["policy"] = SERVE_POLICY_NAMES[policy]
+                out.update(res)
+            else:
+                out.setdefault("other_policies", {})[SERVE_POLICY_NAMES[policy]] = res
         return out
     finally:
         for d in ds:
             ipx.ipx_dataset_destroy(ctx, d)
+
+
+def _served_rates(ipx, ctx, ds, models, reqs, plain_rate, policy, rates, seed):
+    import numpy as np
+    from paper_1706_01420_amd import workloads
+    nreq = len(reqs)
+    # arrival times from their own stream, the same for every policy
+    rng = np.random.default_rng(seed + 1)
+    out = {}
+    srv = ipx.ipx_server_start(ctx, slots=64, policy=policy)
+    try:
+        # warm-up (untimed): the first launch of the device loop and every
+        # dataset's first request
+        warm = [ipx.ipx_submit(srv, ds[j], np.array(workloads.THETA_GEN[models[j]]), g)
+                for j in range(len(ds)) for g in (False, True)]
+        for t in warm:
+            ipx.ipx_wait(srv, t, 60.0)
+        for frac in rates:
+            key = "served_at_%.1fx" % frac if frac is not None else "served_saturated"
+            # one thread submits at the paced times, then collects: latencies
+            # are stamped inside the library (submission to completion), so no
+            # Python thread sits between a request and its result
+            tickets = []
+            results = []
+            errors = []
+            t_end = time.perf_counter() + 60.0   # the whole rate step is bounded
+            # the arrival process is paced by this Python loop: a collection of
+            # the interpreter's garbage (tens of ms with the objects of the
+            # earlier legs) would stall it and release a burst
+            gc.collect()
+            gc.disable()
+            t0 = time.perf_counter()
+            nxt = t0
+            t_sub = []
+            for j, th, g in reqs:
+                if frac is not None:
+                    nxt += rng.exponential(1.0 / (frac * plain_rate))
+                    while time.perf_counter() < nxt:
+                        pass
+                t_sub.append(time.perf_counter())
+                tickets.append(ipx.ipx_submit(srv, ds[j], th, g))
+            try:
+                for t in tickets:
+                    results.append(ipx.ipx_wait(srv, t, max(t_end - time.perf_counter(), 0.0)))
+            except ipx.IpxError as e:
+                errors.append(str(e))
+            finally:
+                gc.enable()
+            # from the first submission to the last completion (submission
+            # time + the library's latency stamp), not to the end of the
+            # collection loop
+            elapsed = (max(ts + r["latency_us"] * 1e-6 for ts, r in zip(t_sub, results)) - t0
+                       if len(results) == nreq else time.perf_counter() - t0)
+            if errors or len(results) < nreq:
+                out[key] = {"error": errors[0] if errors else "incomplete", "completed": len(results),
+                            "server": ipx.ipx_server_stats_read(srv)}
+                break
+            lat = np.array([r["latency_us"] for r in results])
+            out[key] = {"offered_per_s": None if frac is None else frac * plain_rate,
+                        "evals_per_s": nreq / elapsed,
+                        "latency_us_p50": float(np.percentile(lat, 50)),
+                        "latency_us_p99": float(np.percentile(lat, 99)),
+                        "all_ok": bool(all(r["status"] == 0 for r in results)),
+                        "server": ipx.ipx_server_stats_read(srv)}
+    finally:
+        ipx.ipx_server_stop(srv)
+    return out
+
+
+def _timed_calls(call, steps, warmup, ipx=None, ctx=None):
+    """(seconds per call, seconds per timed kernel launch or None)."""
+    import torch
+    for _ in range(warmup):
+        call()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        call()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    if ipx is None:
+        return dt, None
+    ipx.ipx_timing_read(ctx, reset=True)
+    ipx.ipx_timing_enable(ctx, True)
+    for _ in range(steps):
+        call()
+    torch.cuda.synchronize()
+    ipx.ipx_timing_enable(ctx, False)
+    kms, launches = ipx.ipx_timing_read(ctx, reset=True)
+    return dt, (kms / launches / 1e3 if launches else None)
+
+
+def bench_next(ipx, ctx, steps, warmup):
+    """The extensions of the angular and mass paths: the tagged angular
+    model, the simultaneous fit over 6 KK-mass bins x 2 flavours, the Ipatia
+    model with its grid normalisation, and the binned path (smearing, binned
+    NLL, CL_s toys)."""
+    import numpy as np
+    import torch
+    from paper_1706_01420_amd import workloads
+    out = {}
+    n = workloads.WORKLOAD_SIZES[3]
+    # tagged angular model at the angular workload's size
+    c4, w4 = workloads.events(4, n)
+    d4 = ipx.ipx_dataset_create(ctx, 4, c4, w4)
+    th = np.array(workloads.THETA_GEN[4])
+    s, k = _timed_calls(lambda: ipx.nll_grad(ctx, d4, th), steps, warmup, ipx, ctx)
+    out["tagged_nll_grad"] = {"n_events": n, "evals_per_s": 1 / s, "kernel_us": k * 1e6,
+                              "events_per_s": n / s}
+    ipx.ipx_dataset_destroy(ctx, d4)
+    del c4, w4
+    # simultaneous fit: 12 categories sharing the 4e6 events
+    nbins, per = 6, n // 12
+    dss, bins = [], []
+    csp = [0.95, 0.81, 0.64, 0.52, 0.46, 0.39]
+    for b in range(nbins):
+        for q in (1.0, -1.0):
+            c, w = workloads.events(4, per, seed=workloads.BENCH_SEED + 40 + 2 * b + (q > 0), q=q)
+            d = ipx.ipx_dataset_create(ctx, 4, c, w)
+            ipx.ipx_dataset_set_angular(ctx, d, None, csp[b])
+            dss.append(d)
+            bins.append(b)
+    sim = ipx.ipx_sim_create(ctx, dss, bins, nbins)
+    g = workloads.THETA_GEN[3]
+    ths = np.array([g[0], g[1], g[3], g[4], g[6], g[7], g[8], g[9], g[10], g[11]] + [0.05, 0.35] * nbins)
+    s, k = _timed_calls(lambda: ipx.nll_sim(ctx, sim, ths, grad=True), steps, warmup)
+    out["sim_12cat_nll_grad"] = {"categories": 12, "n_events": per * 12, "nparams": int(ths.size),
+                                 "evals_per_s": 1 / s, "events_per_s": per * 12 / s}
+    ipx.ipx_sim_destroy(sim)
+    for d in dss:
+        ipx.ipx_dataset_destroy(ctx, d)
+    # Ipatia model at the mass workload's size
+    nm = workloads.WORKLOAD_SIZES[1]
+    c5, _ = workloads.events(5, nm)
+    d5 = ipx.ipx_dataset_create(ctx, 5, c5, None)
+    th5 = np.array(workloads.THETA_GEN[5])
+    s, k = _timed_calls(lambda: ipx.nll_eval(ctx, d5, th5), steps, warmup, ipx, ctx)
+    out["ipatia_nll_eval"] = {"n_events": nm, "grid_points": 16384, "evals_per_s": 1 / s,
+                              "us_per_eval": s * 1e6, "event_kernel_us": k * 1e6}
+    ipx.ipx_dataset_destroy(ctx, d5)
+    # binned path: 10^4 bins (CL_s workload)
+    nb_bins, lo, hi = 10_000, 5179.0, 5379.0
+    h = torch.rand(nb_bins, dtype=torch.float64, device="cuda")
+    s, _ = _timed_calls(lambda: ipx.ipx_smear(ctx, h, (hi - lo) / nb_bins, 2.0), steps, warmup)
+    out["smear_10k_bins"] = {"us_per_call": s * 1e6, "fma": nb_bins * nb_bins,
+                             "tflops": 2.0 * nb_bins * nb_bins / s / 1e12}
+    H = ipx.ipx_hist_create(ctx, nb_bins, lo, hi, 5279.0, 3.0, 2.0)
+    thb = (70.0, 50_000.0, 0.004)
+    ipx.ipx_hist_set_counts(ctx, H, ipx.ipx_binned_toy(ctx, H, thb, 7, 0, 0))
+    s, _ = _timed_calls(lambda: ipx.nll_binned(ctx, H, thb, grad=True), steps, warmup)
+    out["binned_nll_grad_10k_bins"] = {"evals_per_s": 1 / s, "us_per_eval": s * 1e6}
+    ntoys = 10_000
+    s, k = _timed_calls(lambda: ipx.cls_toys(ctx, H, thb, 2024, ntoys), max(steps // 10, 3),
+                        max(warmup // 10, 1), ipx, ctx)
+    r = ipx.cls_toys(ctx, H, thb, 2024, ntoys)
+    out["cls_10k_toys"] = {"bins": nb_bins, "toys_per_hypothesis": ntoys, "seconds_per_cls": s,
+                           "toy_kernel_ms": k * 1e3, "poisson_draws_per_s": 2 * ntoys * nb_bins / k,
+                           "cl_b": r["cl_b"], "cl_sb": r["cl_sb"], "cl_s": r["cl_s"]}
+    ipx.ipx_hist_destroy(ctx, H)
+    return out
 
 
 def bench_mass_batch(ipx, ctx, steps, warmup, nb=64):
@@ -540,6 +653,18 @@ def main():
     ds = ipx.ipx_dataset_create(ctx, model, cols, w)
     torch.cuda.synchronize()
 
+    # the GPU's clock rises over the first ~50 ms of work after it idled
+    # (the CPU baseline above, or a fresh process): the first calls, timed
+    # as they come, are reported as the cold start, and the timed steps then
+    # measure the steady state; the FP64 ceiling probe (75 ms of FMA loop,
+    # reported below) runs after them, since the GPU runs slower for a while
+    # after it
+    cold = None
+    if not args.profile:
+        ipx.nll_grad(ctx, ds, theta)
+        cold = []
+        for _ in range(10):
+            cold.append(_timed_calls(lambda: ipx.nll_grad(ctx, ds, theta), 25, 0)[0])
     step_s, kernel_s = timed_rate(ipx, ctx, ds, theta, args.steps, args.warmup, grad=True)
     value = 1.0 / step_s
     progress("angular nll_grad: %.4f ms per call, kernel %.1f us" % (step_s * 1e3, kernel_s * 1e6))
@@ -564,6 +689,10 @@ def main():
                                "12 free parameters, per-event weights U(0.8,1)",
                    "n_events": n, "parallelism": "single GPU"},
         "events_per_s": value * n,
+        "cold_start": None if cold is None else {
+            "ms_per_step_by_25": [round(c * 1e3, 4) for c in cold],
+            "note": "the first 250 steps after the process started (one untimed call first), in groups of 25, "
+                    "before the warm-up and timed steps: the GPU still reaching its steady clock"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": TRAFFIC["bytes_per_launch"] if TRAFFIC["sources_sha256"] == kernel_sources_hash() else None,
@@ -597,13 +726,15 @@ def main():
             ipx.ipx_dataset_destroy(ctx, d)
         extra["mass_nll_eval_batch64"] = bench_mass_batch(ipx, ctx, max(args.steps // 2, 5),
                                                           max(args.warmup // 2, 2))
+        extra.update(bench_next(ipx, ctx, max(args.steps // 2, 5), max(args.warmup // 2, 2)))
         out["extra"] = extra
         progress("secondary rates done")
     if not args.no_batched and not args.profile:
         out["batched"] = bench_batched_fits(ipx, ctx)
         progress("batched fits done")
     if not args.no_served and not args.profile:
-        out["served"] = bench_served(ipx, ctx)
+        # the library's default claim policy first, the other two beside it
+        out["served"] = bench_served(ipx, ctx, policies=((0, (0.5, 0.8, None)), (1, (0.5, 0.8)), (2, (0.5, 0.8))))
         progress("served leg done")
     ipx.ipx_destroy(ctx)
     if args.profile:
