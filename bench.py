@@ -569,6 +569,15 @@ def bench_next(ipx, ctx, steps, warmup):
     out["ipatia_nll_eval"] = {"n_events": nm, "grid_points": 16384, "evals_per_s": 1 / s,
                               "us_per_eval": s * 1e6, "event_kernel_us": k * 1e6}
     ipx.ipx_dataset_destroy(ctx, d5)
+    # and at the large sample size of the paper's Example 1 table (10^7 events)
+    nl = 10_000_000
+    c5, _ = workloads.events(5, nl)
+    d5 = ipx.ipx_dataset_create(ctx, 5, c5, None)
+    s, k = _timed_calls(lambda: ipx.nll_eval(ctx, d5, th5), steps, warmup, ipx, ctx)
+    out["ipatia_nll_eval_1e7"] = {"n_events": nl, "grid_points": 16384, "evals_per_s": 1 / s,
+                                  "us_per_eval": s * 1e6, "event_kernel_us": k * 1e6,
+                                  "events_per_s": nl / s}
+    ipx.ipx_dataset_destroy(ctx, d5)
     # binned path: 10^4 bins (CL_s workload)
     nb_bins, lo, hi = 10_000, 5179.0, 5379.0
     h = torch.rand(nb_bins, dtype=torch.float64, device="cuda")

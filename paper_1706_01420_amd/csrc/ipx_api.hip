@@ -2434,14 +2434,18 @@ struct ipx_hist {
 
 static constexpr int kHistMaxBins = 1 << 24;
 
-static size_t hist_work_doubles(int n, int nwg) {
-  // partials (kBinnedAcc x nwg) | totals (8) | tables: nu, em, kmax (2n each), L (n) | q_obs (1) | counters (2)
-  return (size_t)kBinnedAcc * nwg + 8 + 7 * (size_t)n + 1 + 2;
+// partials (kBinnedAcc x nwg) | totals (8) | tables: nu, em, kmax (2n each), L (n) | q_obs (1) |
+// counters (2) | (pad to 16 bytes) | CDF heads (2n x kCdfStride)
+static size_t hist_cdf_offset(int n, int nwg) {
+  const size_t o = (size_t)kBinnedAcc * nwg + 8 + 7 * (size_t)n + 1 + 2;
+  return (o + 1) & ~(size_t)1;
 }
+static size_t hist_work_doubles(int n, int nwg) { return hist_cdf_offset(n, nwg) + 2 * (size_t)n * kCdfStride; }
 
 static ToyTables hist_tables(const ipx_hist* H) {
   double* t = H->work + (size_t)kBinnedAcc * H->nwg + 8;
-  return ToyTables{t, t + 2 * (size_t)H->n, t + 4 * (size_t)H->n, t + 6 * (size_t)H->n};
+  return ToyTables{t, t + 2 * (size_t)H->n, t + 4 * (size_t)H->n, t + 6 * (size_t)H->n,
+                   H->work + hist_cdf_offset(H->n, H->nwg)};
 }
 static double* hist_qobs(const ipx_hist* H) { return H->work + (size_t)kBinnedAcc * H->nwg + 8 + 7 * (size_t)H->n; }
 static unsigned long long* hist_counters(const ipx_hist* H) { return (unsigned long long*)(hist_qobs(H) + 1); }
@@ -2702,27 +2706,36 @@ ipx_status cls_toys(ipx_ctx* ctx, ipx_hist* H, const double* theta, uint64_t see
   if (ntoys < 1 || ntoys > (1 << 24)) return fail(IPX_EINVAL, "cls_toys: %d toys", ntoys);
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
+  // q (2 x ntoys) | block partials of the toys (2 x nblk x ntoys) | of the observed counts (nblk)
+  const int nblk = ((H->n + 3) / 4 + kClsQuads - 1) / kClsQuads;
   if (H->q_cap < ntoys) {
     if (H->q) (void)hipFree(H->q);
     H->q = nullptr;
     H->q_cap = 0;
-    HIP_TRY(hipMalloc(&H->q, 2 * (size_t)ntoys * sizeof(double)));
+    HIP_TRY(hipMalloc(&H->q, (2 * (size_t)ntoys * (1 + (size_t)nblk) + nblk) * sizeof(double)));
     H->q_cap = ntoys;
   }
+  double* part = H->q + 2 * (size_t)ntoys;
+  double* part_obs = part + 2 * (size_t)nblk * ntoys;
   BinnedConst c;
   ipx_status st = toy_tables(ctx, H, theta, &c, s, "cls_toys");
   if (st != IPX_OK) return st;
   const double S = c.ns * H->sig_sum;
   const ToyTables tb = hist_tables(H);
-  hipLaunchKernelGGL(k_q_counts, dim3(1), dim3(kThreads), 0, s, H->cnt, tb.L, H->n, S, hist_qobs(H));
+  hipLaunchKernelGGL(k_cls_block, dim3((unsigned)nblk, 1, 1), dim3(kThreads), 0, s, tb, H->n, seed, 1,
+                     (const double*)H->cnt, part_obs);
+  hipLaunchKernelGGL(k_cls_q, dim3(1, 1), dim3(kThreads), 0, s, part_obs, nblk, 1, S, hist_qobs(H));
   HIP_TRY(hipGetLastError());
   st = timing_begin(ctx, s);
   if (st != IPX_OK) return st;
-  hipLaunchKernelGGL(k_cls_toys, dim3((unsigned)ntoys, 2), dim3(kThreads), 0, s, tb, H->n, S, seed, (uint64_t)0, ntoys,
-                     H->q);
+  hipLaunchKernelGGL(k_cls_block, dim3((unsigned)nblk, (unsigned)((ntoys + kClsToys - 1) / kClsToys), 2),
+                     dim3(kThreads), 0, s, tb, H->n, seed, ntoys, (const double*)nullptr, part);
   HIP_TRY(hipGetLastError());
   st = timing_end(ctx, s);
   if (st != IPX_OK) return st;
+  hipLaunchKernelGGL(k_cls_q, dim3((unsigned)((ntoys + kThreads - 1) / kThreads), 2), dim3(kThreads), 0, s, part,
+                     nblk, ntoys, S, H->q);
+  HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemsetAsync(hist_counters(H), 0, 2 * sizeof(unsigned long long), s));
   hipLaunchKernelGGL(k_count_ge, dim3((unsigned)((ntoys + kThreads - 1) / kThreads), 2), dim3(kThreads), 0, s, H->q,
                      ntoys, hist_qobs(H), hist_counters(H));

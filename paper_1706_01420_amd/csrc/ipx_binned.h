@@ -124,8 +124,16 @@ __global__ __launch_bounds__(kThreads) void k_smear_sum(const double* __restrict
                                                         int n, int nc) {
   const int b = blockIdx.x * kThreads + threadIdx.x;
   if (b >= n) return;
+  // eight loads in flight, added in chunk order
   double s = 0.0;
-  for (int c = 0; c < nc; ++c) s += part[(size_t)c * n + b];
+  for (int c0 = 0; c0 < nc; c0 += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = c0 + u < nc ? part[(size_t)(c0 + u) * n + b] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (c0 + u < nc) s += v[u];
+  }
   out[b] = s;
 }
 
@@ -202,13 +210,64 @@ __global__ __launch_bounds__(kThreads) void k_binned_nll(BinnedConst c, const do
 }
 
 // Per bin and hypothesis h (0: background only, 1: signal + background):
-// nu, e^{-nu}, k_max; and L_b = ln(1 + s_b / b_b).
+// nu, e^{-nu}, k_max; L_b = ln(1 + s_b / b_b); and the first kCdf steps of
+// the inversion's recurrence, F(0) .. F(kCdf - 1) and p_{kCdf - 1}, computed
+// once per call with the same operations as the search itself (every toy
+// of a bin walks the same sequence; only u differs).
+constexpr int kCdf = 16;
+constexpr int kCdfStride = kCdf + 2;   // F(0 .. kCdf - 1), p_{kCdf - 1}, pad (16-byte rows)
 struct ToyTables {
   double* nu;     // [2][n]
   double* em;     // [2][n]
   double* kmax;   // [2][n]
   double* L;      // [n]
+  double* cdf;    // [2][n][kCdfStride]
 };
+
+// Poisson inversion in the order of the conventions above.
+#pragma clang fp contract(off)
+// The first kCdf states (F(k), and p at the last) of the recurrence above.
+__device__ __forceinline__ void poisson_cdf_head(double nu, double em, double* __restrict__ row) {
+  double k = 0.0, p = em, F = em;
+  row[0] = F;
+  for (int i = 1; i < kCdf; ++i) {
+    k += 1.0;
+    p = p * nu / k;
+    F = F + p;
+    row[i] = F;
+  }
+  row[kCdf] = p;
+  row[kCdf + 1] = 0.0;
+}
+
+// The inversion: the smallest k with u <= F(k), stepping p_k = p_{k-1} nu / k,
+// F(k) = F(k-1) + p_k from p_0 = F(0) = e^{-nu}, stopping at k_max.  Its
+// first kCdf steps are read from the table row (k_max >= 60 > kCdf, so the
+// cap cannot stop the search there); past the row the recurrence continues
+// from (kCdf - 1, p_{kCdf - 1}, F(kCdf - 1)), the state it would have
+// reached, so the result is that of the plain recurrence from k = 0.
+__device__ __forceinline__ double poisson_inverse_cached(double u, double nu, double kmax,
+                                                         const double* __restrict__ row) {
+  // F is non-decreasing, so the steps with u > F(k) are a prefix of the row
+  // and their count is the first k with u <= F(k): the whole row is loaded
+  // at once and counted without branches
+  const double2* r2 = reinterpret_cast<const double2*>(row);
+  double2 f[kCdf / 2];
+#pragma unroll
+  for (int i = 0; i < kCdf / 2; ++i) f[i] = r2[i];
+  int c = 0;
+#pragma unroll
+  for (int i = 0; i < kCdf / 2; ++i) c += (u > f[i].x) + (u > f[i].y);
+  if (c < kCdf) return (double)c;
+  double k = (double)(kCdf - 1), p = row[kCdf], F = f[kCdf / 2 - 1].y;
+  while (u > F && k < kmax) {
+    k += 1.0;
+    p = p * nu / k;
+    F = F + p;
+  }
+  return k;
+}
+#pragma clang fp contract(on)
 
 __global__ __launch_bounds__(kThreads) void k_toy_tables(BinnedConst c, const double* __restrict__ sig,
                                                          ToyTables tb) {
@@ -220,25 +279,15 @@ __global__ __launch_bounds__(kThreads) void k_toy_tables(BinnedConst c, const do
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const double nu = nus[h];
+    const double em = exp(-nu);
     tb.nu[h * c.n + b] = nu;
-    tb.em[h * c.n + b] = exp(-nu);
+    tb.em[h * c.n + b] = em;
     tb.kmax[h * c.n + b] = floor(nu + 30.0 * sqrt(nu + 1.0) + 30.0);
+    poisson_cdf_head(nu, em, tb.cdf + ((size_t)h * c.n + b) * kCdfStride);
   }
   tb.L[b] = log1p(s / bk);
 }
 
-// Poisson inversion in the order of the conventions above.
-#pragma clang fp contract(off)
-__device__ __forceinline__ double poisson_inverse(double u, double nu, double em, double kmax) {
-  double k = 0.0, p = em, F = em;
-  while (u > F && k < kmax) {
-    k += 1.0;
-    p = p * nu / k;
-    F = F + p;
-  }
-  return k;
-}
-#pragma clang fp contract(on)
 
 // Counts of one toy of hypothesis h: the lane that handles bins 4i .. 4i + 3
 // draws them from one Philox block.
@@ -248,44 +297,99 @@ __device__ __forceinline__ void toy_block(const ToyTables& tb, int n, int h, uin
 #pragma unroll
   for (int w = 0; w < 4; ++w) {
     const int b = 4 * i + w;
-    cnt[w] = b < n ? poisson_inverse(u01(r.x[w]), tb.nu[h * n + b], tb.em[h * n + b], tb.kmax[h * n + b]) : 0.0;
+    cnt[w] = b < n ? poisson_inverse_cached(u01(r.x[w]), tb.nu[h * n + b], tb.kmax[h * n + b],
+                                            tb.cdf + ((size_t)h * n + b) * kCdfStride)
+                   : 0.0;
   }
 }
 
-// q of each toy: grid (toys, 2 hypotheses), one workgroup per toy.  The sum
-// of n_b L_b runs over the lane's bin blocks i = t, t + 256, ... in
-// increasing order, then block_sum; q = 2 (S - sum).
-__global__ __launch_bounds__(kThreads) void k_cls_toys(ToyTables tb, int n, double S, uint64_t seed,
-                                                       uint64_t toy0, int ntoys, double* __restrict__ q) {
-  __shared__ double lds4[kThreads / 64];
+// CL_s toys, blocked by bins.  Workgroup (x, y, h) takes bin block x (quads
+// 64 x .. 64 x + 63, four bins each) for the toys kClsToys y .. of
+// hypothesis h: it stages the block's CDF heads in LDS as T[w][k][quad] (w
+// the bin within its quad), so that the lanes, one quad each, read
+// consecutive addresses at every k (35 KB: four workgroups per compute
+// unit); each wave takes one toy at a time (wave i the toys i, i + 4, ...).
+// Per toy a lane adds n_b L_b over its four bins in order, the wave adds its
+// lanes (butterfly), and the block's sum goes to part[(h nblk + x) ntoys +
+// toy].  k_cls_q adds the blocks in order.  With obs != nullptr the counts
+// are obs[b] instead of a toy's (grid (nblk, 1, 1), one "toy"), which gives
+// q_obs in the same order.
+constexpr int kClsQuads = 64;
+constexpr int kClsToys = 256;
+constexpr int kClsRows = kCdf + 1;   // F(0 .. kCdf - 1), then p_{kCdf - 1}
+
+#pragma clang fp contract(off)
+__device__ __forceinline__ double poisson_inverse_lds(double u, const double (*Tw)[kClsQuads], int qi,
+                                                      const ToyTables& tb, int h, int n, int b) {
+  int c = 0;
+#pragma unroll
+  for (int k = 0; k < kCdf; ++k) c += (u > Tw[k][qi]);
+  if (c < kCdf) return (double)c;
+  double k = (double)(kCdf - 1), p = Tw[kCdf][qi], F = Tw[kCdf - 1][qi];
+  const double nu = tb.nu[h * n + b], kmax = tb.kmax[h * n + b];
+  while (u > F && k < kmax) {
+    k += 1.0;
+    p = p * nu / k;
+    F = F + p;
+  }
+  return k;
+}
+#pragma clang fp contract(on)
+
+__global__ __launch_bounds__(kThreads) void k_cls_block(ToyTables tb, int n, uint64_t seed, int ntoys,
+                                                        const double* __restrict__ obs, double* __restrict__ part) {
+  static_assert(kClsQuads == 64, "one wave per toy");
+  __shared__ double T[4][kClsRows][kClsQuads];
+  const int h = blockIdx.z;
+  const int nq = (n + 3) / 4, nblk = gridDim.x;
+  const int q0 = blockIdx.x * kClsQuads;
+  const int qi = threadIdx.x % kClsQuads, slot = threadIdx.x / kClsQuads;   // slot: the wave
+  const int q = q0 + qi;
+  if (!obs) {
+    for (int e = threadIdx.x; e < 4 * kClsRows * kClsQuads; e += kThreads) {
+      const int qq = e % kClsQuads, k = (e / kClsQuads) % kClsRows, w = e / (kClsQuads * kClsRows);
+      const int b = 4 * (q0 + qq) + w;
+      T[w][k][qq] = b < n ? tb.cdf[((size_t)h * n + b) * kCdfStride + k] : 0.0;
+    }
+  }
+  double L[4];
+#pragma unroll
+  for (int w = 0; w < 4; ++w) L[w] = (q < nq && 4 * q + w < n) ? tb.L[4 * q + w] : 0.0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int tend = obs ? 1 : kClsToys;
+  for (int tt = 0; tt < tend; tt += kThreads / kClsQuads) {
+    const int toy = blockIdx.y * kClsToys + tt + slot;
+    double v = 0.0;
+    if (q < nq && (obs ? toy == 0 : toy < ntoys)) {
+      double cnt[4];
+      if (obs) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) cnt[w] = 4 * q + w < n ? obs[4 * q + w] : 0.0;
+      } else {
+        const Philox4 r = philox4x64_10((uint64_t)q, (uint64_t)toy, (uint64_t)h, 0, seed, kBinnedKey);
+#pragma unroll
+        for (int w = 0; w < 4; ++w)
+          cnt[w] = 4 * q + w < n ? poisson_inverse_lds(u01(r.x[w]), T[w], qi, tb, h, n, 4 * q + w) : 0.0;
+      }
+#pragma unroll
+      for (int w = 0; w < 4; ++w) v += cnt[w] * L[w];
+    }
+    v = wave_sum(v);
+    if (lane == 0 && (obs ? toy == 0 : toy < ntoys)) part[((size_t)h * nblk + blockIdx.x) * (obs ? 1 : ntoys) + toy] = v;
+  }
+}
+
+// q[h ntoys + toy] = 2 (S - sum over the bin blocks, in order, of part);
+// grid (ceil(ntoys / kThreads), hypotheses).
+__global__ __launch_bounds__(kThreads) void k_cls_q(const double* __restrict__ part, int nblk, int ntoys, double S,
+                                                    double* __restrict__ q) {
+  const int toy = blockIdx.x * kThreads + threadIdx.x;
   const int h = blockIdx.y;
-  const uint64_t toy = toy0 + blockIdx.x;
-  const int nblk = (n + 3) / 4;
-  double sum = 0.0;
-  for (int i = threadIdx.x; i < nblk; i += kThreads) {
-    double cnt[4];
-    toy_block(tb, n, h, seed, toy, i, cnt);
-#pragma unroll
-    for (int w = 0; w < 4; ++w)
-      if (4 * i + w < n) sum += cnt[w] * tb.L[4 * i + w];
-  }
-  const double t = block_sum(sum, lds4);
-  if (threadIdx.x == 0) q[(int64_t)h * ntoys + blockIdx.x] = 2.0 * (S - t);
-}
-
-// q of given counts, in the order of k_cls_toys (one workgroup).
-__global__ __launch_bounds__(kThreads) void k_q_counts(const double* __restrict__ cnt, const double* __restrict__ L,
-                                                       int n, double S, double* __restrict__ q) {
-  __shared__ double lds4[kThreads / 64];
-  const int nblk = (n + 3) / 4;
-  double sum = 0.0;
-  for (int i = threadIdx.x; i < nblk; i += kThreads) {
-#pragma unroll
-    for (int w = 0; w < 4; ++w)
-      if (4 * i + w < n) sum += cnt[4 * i + w] * L[4 * i + w];
-  }
-  const double t = block_sum(sum, lds4);
-  if (threadIdx.x == 0) q[0] = 2.0 * (S - t);
+  if (toy >= ntoys) return;
+  double s = 0.0;
+  for (int x = 0; x < nblk; ++x) s += part[((size_t)h * nblk + x) * ntoys + toy];
+  q[(size_t)h * ntoys + toy] = 2.0 * (S - s);
 }
 
 // ge[h] = number of toys of hypothesis h with q >= q_obs (integer counts).
