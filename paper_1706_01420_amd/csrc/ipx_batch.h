@@ -131,8 +131,10 @@ __device__ __forceinline__ void tile_angtime(const SegInfo& S, const AngTimeCons
     }
   }
   if constexpr (GRAD) {
-    const unsigned g = lane & 7u, b = lane >> 3;
-    if (g < 5) red.wsum[threadIdx.x >> 6][kAngOuter0 + 4 * (5 * (b >> 2) + g) + (b & 3u)] = outer;
+    unsigned tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));  // the address is derived here, not kept live through the loop
+    const unsigned g = tid & 7u, b = (tid & 63u) >> 3;
+    if (g < 5) red.wsum[tid >> 6][kAngOuter0 + 4 * (5 * (b >> 2) + g) + (b & 3u)] = outer;
     tile_store<NACC, COH, CAP, kAccAngTime>(acc, S.partials, tile, S.n_tiles, red);
   } else {
     tile_store<NACC, COH, CAP>(acc, S.partials, tile, S.n_tiles, red);
@@ -177,7 +179,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(WPE > 
     const TileRef tr = tiles[g];
     if (!active[tr.seg]) continue;
     const AngTimeConst& k = consts[tr.seg];
-    if (threadIdx.x < 40) sC[threadIdx.x] = (&k.C[0][0])[threadIdx.x];
+    unsigned tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));  // (the address is derived per tile, not kept live across tiles)
+    if (tid < 40) sC[tid] = (&k.C[0][0])[tid];
     __syncthreads();
     tile_angtime<GRAD, false, kCap, TAG>(segs[tr.seg], k, sC, tr.tile, red);
   }

@@ -79,8 +79,13 @@ __device__ __forceinline__ void tile_store(const double (&acc)[NACC], double* __
                                            int64_t tile, int64_t n_tiles, RedBuf<CAP>& red) {
   static_assert(NTOT >= NACC && NTOT <= kAccMax, "wave totals live in wsum");
   constexpr int kChunk = NACC < CAP ? NACC : CAP;
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  // the lane's LDS addresses are derived here, from an opaque copy of the
+  // thread index: computed once at kernel entry they would stay live through
+  // the caller's event loop (and the angular gradient kernel would spill them)
+  int tid = (int)threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
 #pragma unroll
   for (int c0 = 0; c0 < NACC; c0 += kChunk) {
 #pragma unroll
