@@ -231,7 +231,7 @@ def _noop(_):
     return None
 
 
-def cpu_baseline(cols, w, theta, reps=3, ntoys=16, nreq=16):
+def cpu_baseline(cols, w, theta, reps=5, ntoys=16, nreq=16):
     """The oracle (numpy/scipy FP64, exactly rounded sums, dual-number
     gradient) timed on the host's cores: worker processes forked before this
     process touches the GPU, each running the oracle single-threaded on its
@@ -262,11 +262,19 @@ def cpu_baseline(cols, w, theta, reps=3, ntoys=16, nreq=16):
             times.append(time.perf_counter() - t0)
     med = float(np.median(times))
     progress("cpu baseline: full-sample evaluations %s s" % ", ".join("%.2f" % t for t in times))
+    # one thread: two of the chunks in this process, scaled to the full sample
+    t0 = time.perf_counter()
+    for c in (0, 1):
+        _cpu_eval_chunk(c)
+    t_one = (time.perf_counter() - t0) / 2 * (len(edges) - 1)
     out = {"value": 1.0 / med, "unit": "NLL+grad evals/s", "cores": workers, "kind": "oracle",
            "sample": "oracle nll_grad over all %d events of the angular workload, split into %d chunks over %d "
                      "single-threaded worker processes; median of %d repetitions (%s s)"
                      % (n, len(edges) - 1, workers, reps, ", ".join("%.2f" % t for t in times)),
-           "host": {"cpu_model": _cpu_model(), "nproc": os.cpu_count(), "workers": workers}}
+           "host": {"cpu_model": _cpu_model(), "nproc": os.cpu_count(), "workers": workers},
+           "single_thread": {"evals_per_s": 1.0 / t_one,
+                             "sample": "chunks 0 and 1 of the %d on one thread, scaled to the full sample"
+                                       % (len(edges) - 1)}}
 
     # batched-toy fits: the same toys (seed, ids, sizes) and start points
     seed = 170601424
