@@ -10,7 +10,6 @@
 //   4. copies the (1 + K) sums to pinned host memory and synchronises;
 //   5. for the gradient, applies the Jacobian of step 1 on the host.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <cmath>
 #include <cstdarg>
@@ -35,6 +34,7 @@
 #include "ipx_batch.h"
 #include "ipx_serve.h"
 #include "ipx_binned.h"
+#include "ipx_scan.h"
 #include "ipx_ipatia.h"
 
 using namespace ipx;
@@ -145,30 +145,26 @@ static ipx_status sort_events(ipx_dataset* d, hipStream_t s) {
   const int tcol = d->model == 2 ? 1 : 3;
   const int scol = d->model == 2 ? 2 : 4;
   unsigned long long* keys = nullptr;
-  unsigned long long* keys_out = nullptr;
+  unsigned long long* keys_tmp = nullptr;
   double* tmp = nullptr;
-  int* perm_in = nullptr;
   int* perm = nullptr;
-  void* scratch = nullptr;
-  size_t scratch_bytes = 0;
+  int* perm_tmp = nullptr;
+  int* scratch = nullptr;
   hipError_t e = hipMalloc(&keys, (size_t)n * sizeof(unsigned long long));
-  if (e == hipSuccess) e = hipMalloc(&keys_out, (size_t)n * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMalloc(&keys_tmp, (size_t)n * sizeof(unsigned long long));
   if (e == hipSuccess) e = hipMalloc(&tmp, (size_t)n * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc(&perm_in, (size_t)n * sizeof(int));
   if (e == hipSuccess) e = hipMalloc(&perm, (size_t)n * sizeof(int));
-  if (e == hipSuccess)
-    e = hipcub::DeviceRadixSort::SortPairs(nullptr, scratch_bytes, keys, keys_out, perm_in, perm, n, 0, 64, s);
-  if (e == hipSuccess) e = hipMalloc(&scratch, scratch_bytes);
+  if (e == hipSuccess) e = hipMalloc(&perm_tmp, (size_t)n * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc(&scratch, radix_temp_ints(n) * sizeof(int));
   if (e == hipSuccess) {
     const unsigned blocks = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(k_iota, dim3(blocks), dim3(256), 0, s, perm_in, n);
+    hipLaunchKernelGGL(k_iota, dim3(blocks), dim3(256), 0, s, perm, n);
     e = hipGetLastError();
     if (e == hipSuccess) {
       hipLaunchKernelGGL(k_band_key, dim3(blocks), dim3(256), 0, s, keys, d->cols[tcol], d->cols[scol], n);
       e = hipGetLastError();
     }
-    if (e == hipSuccess)
-      e = hipcub::DeviceRadixSort::SortPairs(scratch, scratch_bytes, keys, keys_out, perm_in, perm, n, 0, 64, s);
+    if (e == hipSuccess) e = radix_sort_pairs(keys, perm, keys_tmp, perm_tmp, n, scratch, s);
     const int nstore = d->ncols + (d->w ? 1 : 0);
     for (int c = 0; c < nstore && e == hipSuccess; ++c) {
       double* col = const_cast<double*>(c < d->ncols ? d->cols[c] : d->w);
@@ -179,10 +175,10 @@ static ipx_status sort_events(ipx_dataset* d, hipStream_t s) {
     if (e == hipSuccess) e = hipStreamSynchronize(s);
   }
   (void)hipFree(keys);
-  (void)hipFree(keys_out);
+  (void)hipFree(keys_tmp);
   (void)hipFree(tmp);
-  (void)hipFree(perm_in);
   (void)hipFree(perm);
+  (void)hipFree(perm_tmp);
   (void)hipFree(scratch);
   if (e != hipSuccess) return fail(IPX_EDEVICE, "ipx_dataset_create: ordering the events failed: %s", hipGetErrorString(e));
   d->sorted = true;
@@ -654,8 +650,7 @@ static ipx_status gen_batch(const GenConst& g, GenScratch& sc, uint64_t c0, int6
   hipLaunchKernelGGL((k_gen_flags<MODEL>), dim3(blocks), dim3(256), 0, s, g, (const double*)sc.C, c0, count,
                      sc.flags, sc.counters);
   HIP_TRY(hipGetLastError());
-  size_t bytes = sc.scan_bytes;
-  HIP_TRY(hipcub::DeviceScan::ExclusiveSum(sc.scan, bytes, sc.flags, sc.rank, (int)count, s));
+  HIP_TRY(scan_exclusive(sc.flags, sc.rank, count, (int*)sc.scan, s));
   hipLaunchKernelGGL((k_gen_write<MODEL>), dim3(blocks), dim3(256), 0, s, g, (const double*)sc.C, c0, count,
                      (const int*)sc.flags, (const int*)sc.rank, got, need, (double* const*)sc.colp, wout,
                      sc.counters + 1);
@@ -735,7 +730,7 @@ extern "C" ipx_status toy_generate(ipx_ctx* ctx, int model, const double* theta,
     if (e == hipSuccess) e = hipMalloc(&sc.C, 40 * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&sc.colp, 6 * sizeof(double*));
     if (e == hipSuccess) e = hipMalloc(&sc.tail, 2 * sizeof(int));
-    if (e == hipSuccess) e = hipcub::DeviceScan::ExclusiveSum(nullptr, sc.scan_bytes, sc.flags, sc.rank, (int)cap, s);
+    sc.scan_bytes = scan_temp_ints(cap) * sizeof(int);
     if (e == hipSuccess) e = hipMalloc(&sc.scan, sc.scan_bytes);
     unsigned long long zero2[2] = {0ull, 0ull};
     if (e == hipSuccess) e = hipMemcpyAsync(sc.counters, zero2, sizeof zero2, hipMemcpyHostToDevice, s);
@@ -819,8 +814,7 @@ static ipx_status gen_round(const GenConst& g, GenBatchScratch& sc, int nseg, in
   hipLaunchKernelGGL((k_gen_flags_batch<MODEL>), dim3(blocks), dim3(256), 0, s, g, (const double*)sc.C,
                      (const GenSeg*)sc.segs, nseg, total, sc.flags, sc.viol);
   HIP_TRY(hipGetLastError());
-  size_t bytes = sc.scan_bytes;
-  HIP_TRY(hipcub::DeviceScan::ExclusiveSum(sc.scan, bytes, sc.flags, sc.rank, (int)total, s));
+  HIP_TRY(scan_exclusive(sc.flags, sc.rank, total, (int*)sc.scan, s));
   hipLaunchKernelGGL((k_gen_write_batch<MODEL>), dim3(blocks), dim3(256), 0, s, g, (const double*)sc.C,
                      (const GenSeg*)sc.segs, nseg, total, (const int*)sc.flags, (const int*)sc.rank, sc.last);
   HIP_TRY(hipGetLastError());
@@ -883,7 +877,7 @@ extern "C" ipx_status toy_generate_batch(ipx_ctx* ctx, int model, const double* 
     if (e == hipSuccess) e = hipMalloc(&sc.viol, (size_t)ntoys * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMalloc(&sc.last, (size_t)ntoys * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMalloc(&sc.acc, (size_t)ntoys * sizeof(int64_t));
-    if (e == hipSuccess) e = hipcub::DeviceScan::ExclusiveSum(nullptr, sc.scan_bytes, sc.flags, sc.rank, (int)cap, s);
+    sc.scan_bytes = scan_temp_ints(cap) * sizeof(int);
     if (e == hipSuccess) e = hipMalloc(&sc.scan, sc.scan_bytes);
     if (e == hipSuccess) e = hipMemcpyAsync(sc.C, h.C, sizeof h.C, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(sc.viol, viol.data(), viol.size() * sizeof(unsigned long long), hipMemcpyHostToDevice, s);
