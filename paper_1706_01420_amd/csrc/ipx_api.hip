@@ -117,71 +117,138 @@ constexpr int kModelIpatia = 5;
 // tail of a launch short.  The NLL is a sum over events: the order only
 // changes the rounding of the sum.
 // ---------------------------------------------------------------------------
-__global__ void k_iota(int* __restrict__ v, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) v[i] = i;
-}
-__global__ void k_gather(double* __restrict__ dst, const double* __restrict__ src, const int* __restrict__ perm,
-                         int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = src[perm[i]];
-}
 constexpr int kBands = 21;   // bands 0 .. 20 of 2 t / sigma_t (5 bits)
 
 // key = band << 58 | (2^63 - 1 - bits of sigma_t) >> 6; sigma_t > 0, so its
 // bit pattern orders as its value (decreasing here)
-__global__ void k_band_key(unsigned long long* __restrict__ key, const double* __restrict__ t,
-                           const double* __restrict__ sig, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double r = 2.0 * t[i] / sig[i];
+__device__ __forceinline__ unsigned long long band_key(double t, double sig) {
+  const double r = 2.0 * t / sig;
   const double b = r > 0.0 ? fmin(floor(r), (double)kBands - 1.0) : 0.0;  // NaN -> 0
-  key[i] = ((unsigned long long)b << 58) |
-           ((0x7fffffffffffffffull - (unsigned long long)__double_as_longlong(sig[i])) >> 6);
+  return ((unsigned long long)b << 58) | ((0x7fffffffffffffffull - (unsigned long long)__double_as_longlong(sig)) >> 6);
 }
 
-static ipx_status sort_events(ipx_dataset* d, hipStream_t s) {
-  const int n = (int)d->n;
-  const int tcol = d->model == 2 ? 1 : 3;
-  const int scol = d->model == 2 ? 2 : 4;
+// One dataset of a joint ordering: its ordering columns and every column to
+// permute (the observables, then the weights), its first key in the
+// concatenation of all keys.
+struct SortSeg {
+  const double* t;
+  const double* sig;
+  double* cols[8];
+  int ncols;
+  int64_t off;
+};
+
+__global__ __launch_bounds__(kScanThreads) void k_seg_keys(const RadixTile* __restrict__ tiles,
+                                                           const SortSeg* __restrict__ segs,
+                                                           unsigned long long* __restrict__ keys, int* __restrict__ vals) {
+  const RadixTile tl = tiles[blockIdx.x];
+  const SortSeg& sg = segs[tl.seg];
+  for (int i = (int)threadIdx.x; i < tl.count; i += kScanThreads) {
+    const int64_t g = tl.start + i;
+    const int64_t k = g - sg.off;
+    keys[g] = band_key(sg.t[k], sg.sig[k]);
+    vals[g] = (int)k;
+  }
+}
+
+// tmp[g] = column c of the key's dataset at the sorted index vals[g].
+__global__ __launch_bounds__(kScanThreads) void k_seg_gather(const RadixTile* __restrict__ tiles,
+                                                             const SortSeg* __restrict__ segs,
+                                                             const int* __restrict__ vals, int c,
+                                                             double* __restrict__ tmp) {
+  const RadixTile tl = tiles[blockIdx.x];
+  const SortSeg& sg = segs[tl.seg];
+  if (c >= sg.ncols) return;
+  const double* __restrict__ src = sg.cols[c];
+  for (int i = (int)threadIdx.x; i < tl.count; i += kScanThreads) tmp[tl.start + i] = src[vals[tl.start + i]];
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_seg_put(const RadixTile* __restrict__ tiles,
+                                                          const SortSeg* __restrict__ segs, int c,
+                                                          const double* __restrict__ tmp) {
+  const RadixTile tl = tiles[blockIdx.x];
+  const SortSeg& sg = segs[tl.seg];
+  if (c >= sg.ncols) return;
+  double* __restrict__ dst = sg.cols[c];
+  for (int i = (int)threadIdx.x; i < tl.count; i += kScanThreads) dst[tl.start + i - sg.off] = tmp[tl.start + i];
+}
+
+// Puts the events of every dataset of ds (models with a decay time) in
+// resolution-band order, all datasets in one set of launches.
+static ipx_status sort_events(ipx_dataset* const* ds, int nds, hipStream_t s) {
+  std::vector<SortSeg> segs;
+  std::vector<RadixTile> tiles;
+  int64_t total = 0, nhist = 0;
+  int maxcols = 0;
+  for (int j = 0; j < nds; ++j) {
+    ipx_dataset* d = ds[j];
+    if (!d || d->n < 2) continue;
+    const int tcol = d->model == 2 ? 1 : 3;
+    const int scol = d->model == 2 ? 2 : 4;
+    SortSeg sg{};
+    sg.t = d->cols[tcol];
+    sg.sig = d->cols[scol];
+    sg.ncols = d->ncols + (d->w ? 1 : 0);
+    for (int c = 0; c < sg.ncols; ++c) sg.cols[c] = const_cast<double*>(c < d->ncols ? d->cols[c] : d->w);
+    sg.off = total;
+    maxcols = std::max(maxcols, sg.ncols);
+    const int nt = (int)((d->n + kScanTile - 1) / kScanTile);
+    for (int lt = 0; lt < nt; ++lt)
+      tiles.push_back(RadixTile{total + (int64_t)lt * kScanTile,
+                                (int)std::min<int64_t>(kScanTile, d->n - (int64_t)lt * kScanTile), (int)segs.size(),
+                                (int)(nhist + lt), nt});
+    nhist += 256 * (int64_t)nt;
+    total += d->n;
+    segs.push_back(sg);
+  }
+  if (segs.empty()) return IPX_OK;
+  if (nhist + (int64_t)scan_temp_ints(nhist) > 0x7fffffff)
+    return fail(IPX_EINVAL, "ordering the events: too many tiles (%lld)", (long long)tiles.size());
   unsigned long long* keys = nullptr;
   unsigned long long* keys_tmp = nullptr;
   double* tmp = nullptr;
   int* perm = nullptr;
   int* perm_tmp = nullptr;
   int* scratch = nullptr;
-  hipError_t e = hipMalloc(&keys, (size_t)n * sizeof(unsigned long long));
-  if (e == hipSuccess) e = hipMalloc(&keys_tmp, (size_t)n * sizeof(unsigned long long));
-  if (e == hipSuccess) e = hipMalloc(&tmp, (size_t)n * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc(&perm, (size_t)n * sizeof(int));
-  if (e == hipSuccess) e = hipMalloc(&perm_tmp, (size_t)n * sizeof(int));
-  if (e == hipSuccess) e = hipMalloc(&scratch, radix_temp_ints(n) * sizeof(int));
+  RadixTile* d_tiles = nullptr;
+  SortSeg* d_segs = nullptr;
+  hipError_t e = hipMalloc(&keys, (size_t)total * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMalloc(&keys_tmp, (size_t)total * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMalloc(&tmp, (size_t)total * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&perm, (size_t)total * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc(&perm_tmp, (size_t)total * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc(&scratch, ((size_t)nhist + scan_temp_ints(nhist)) * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc(&d_tiles, tiles.size() * sizeof(RadixTile));
+  if (e == hipSuccess) e = hipMalloc(&d_segs, segs.size() * sizeof(SortSeg));
+  if (e == hipSuccess) e = hipMemcpyAsync(d_tiles, tiles.data(), tiles.size() * sizeof(RadixTile), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_segs, segs.data(), segs.size() * sizeof(SortSeg), hipMemcpyHostToDevice, s);
+  const unsigned nt = (unsigned)tiles.size();
   if (e == hipSuccess) {
-    const unsigned blocks = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(k_iota, dim3(blocks), dim3(256), 0, s, perm, n);
+    hipLaunchKernelGGL(k_seg_keys, dim3(nt), dim3(kScanThreads), 0, s, (const RadixTile*)d_tiles,
+                       (const SortSeg*)d_segs, keys, perm);
     e = hipGetLastError();
-    if (e == hipSuccess) {
-      hipLaunchKernelGGL(k_band_key, dim3(blocks), dim3(256), 0, s, keys, d->cols[tcol], d->cols[scol], n);
-      e = hipGetLastError();
-    }
-    if (e == hipSuccess) e = radix_sort_pairs(keys, perm, keys_tmp, perm_tmp, n, scratch, s);
-    const int nstore = d->ncols + (d->w ? 1 : 0);
-    for (int c = 0; c < nstore && e == hipSuccess; ++c) {
-      double* col = const_cast<double*>(c < d->ncols ? d->cols[c] : d->w);
-      hipLaunchKernelGGL(k_gather, dim3(blocks), dim3(256), 0, s, tmp, col, perm, n);
-      e = hipGetLastError();
-      if (e == hipSuccess) e = hipMemcpyAsync(col, tmp, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s);
-    }
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
   }
+  if (e == hipSuccess)
+    e = radix_sort_pairs(keys, perm, keys_tmp, perm_tmp, total, d_tiles, (int)nt, nhist, scratch, s);
+  for (int c = 0; c < maxcols && e == hipSuccess; ++c) {
+    hipLaunchKernelGGL(k_seg_gather, dim3(nt), dim3(kScanThreads), 0, s, (const RadixTile*)d_tiles,
+                       (const SortSeg*)d_segs, (const int*)perm, c, tmp);
+    hipLaunchKernelGGL(k_seg_put, dim3(nt), dim3(kScanThreads), 0, s, (const RadixTile*)d_tiles,
+                       (const SortSeg*)d_segs, c, (const double*)tmp);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(keys);
   (void)hipFree(keys_tmp);
   (void)hipFree(tmp);
   (void)hipFree(perm);
   (void)hipFree(perm_tmp);
   (void)hipFree(scratch);
-  if (e != hipSuccess) return fail(IPX_EDEVICE, "ipx_dataset_create: ordering the events failed: %s", hipGetErrorString(e));
-  d->sorted = true;
+  (void)hipFree(d_tiles);
+  (void)hipFree(d_segs);
+  if (e != hipSuccess) return fail(IPX_EDEVICE, "ordering the events failed: %s", hipGetErrorString(e));
+  for (int j = 0; j < nds; ++j)
+    if (ds[j] && ds[j]->n >= 2) ds[j]->sorted = true;
   return IPX_OK;
 }
 
@@ -301,7 +368,7 @@ ipx_status ipx_dataset_create(ipx_ctx* ctx, int model, int64_t n, const double* 
       return fail(IPX_EDEVICE, "ipx_dataset_create: copy failed: %s", hipGetErrorString(e));
     }
     if (time_model(model) && !(flags & IPX_KEEP_ORDER) && n >= 2 && n <= 0x7fffffff) {
-      ipx_status st = sort_events(d, ctx->stream);
+      ipx_status st = sort_events(&d, 1, ctx->stream);
       if (st != IPX_OK) {
         free_dataset(d);
         return st;
@@ -774,7 +841,7 @@ extern "C" ipx_status toy_generate(ipx_ctx* ctx, int model, const double* theta,
     candidates = cnt[1];
   }
   if (model >= 2 && !(flags & IPX_KEEP_ORDER) && n >= 2) {
-    ipx_status st = sort_events(d, s);
+    ipx_status st = sort_events(&d, 1, s);
     if (st != IPX_OK) {
       free_dataset(d);
       return st;
@@ -964,13 +1031,11 @@ extern "C" ipx_status toy_generate_batch(ipx_ctx* ctx, int model, const double* 
     }
   }
   if (model >= 2 && !(flags & IPX_KEEP_ORDER)) {
-    for (int j = 0; j < ntoys; ++j) {
-      if (n[j] < 2) continue;
-      ipx_status st = sort_events(out[j], s);
-      if (st != IPX_OK) {
-        release();
-        return st;
-      }
+    // every toy in one joint ordering (each toy's events among themselves)
+    ipx_status st = sort_events(out, ntoys, s);
+    if (st != IPX_OK) {
+      release();
+      return st;
     }
   }
   if (stats)

@@ -9,10 +9,11 @@
 // are 32-bit counts whose total fits in an int.
 //
 // Sort: least-significant digit first, 8-bit digits, eight passes over the
-// 64-bit keys.  A pass counts the digits of each tile of kScanTile keys
-// (k_radix_hist, digit-major counts), scans the counts in digit-major order
-// (the digit's base over all tiles, then the tile's base within the digit),
-// and moves every key and value to its place (k_radix_scatter).  Within a
+// 64-bit keys, for one array or several at once (segments, each sorted on
+// its own).  A pass counts the digits of each tile of kScanTile keys
+// (k_radix_hist, digit-major counts per segment), scans the counts (the
+// segment's base, the digit's base within it, then the tile's base within
+// the digit), and moves every key and value to its place (k_radix_scatter).  Within a
 // tile the keys go in index order: 16 rounds of 256 keys; in a round each
 // wave finds the lanes that share a lane's digit (eight ballots) and the
 // lane's rank among them, and the waves take their places in wave order.
@@ -117,43 +118,59 @@ inline hipError_t scan_exclusive(const int* in, int* out, int64_t n, int* tmp, h
   return hipGetLastError();
 }
 
-// Digit counts of each tile: hist[d * nblk + tile].
-__global__ __launch_bounds__(kScanThreads) void k_radix_hist(const unsigned long long* __restrict__ keys, int n,
-                                                             int shift, int* __restrict__ hist, int nblk) {
+// A tile of the sort: up to kScanTile consecutive keys [start, start +
+// count) of one segment; its count of digit d goes to hist[hidx + d hstride].
+// Segments (several arrays sorted at once, each on its own) are laid out
+// end to end, each with its own digit-major block of counts, hidx = the
+// segment's block + the tile's index within the segment, hstride = the
+// segment's tile count; the scan of all counts then gives every key its
+// place in the concatenation (the segment's start + its place within it).
+struct RadixTile {
+  int64_t start;
+  int count;
+  int seg;
+  int hidx;
+  int hstride;
+};
+
+__global__ __launch_bounds__(kScanThreads) void k_radix_hist(const unsigned long long* __restrict__ keys,
+                                                             const RadixTile* __restrict__ tiles, int shift,
+                                                             int* __restrict__ hist) {
   __shared__ int cnt[256];
+  const RadixTile tl = tiles[blockIdx.x];
   cnt[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kScanTile;
 #pragma unroll 4
   for (int r = 0; r < kScanItems; ++r) {
-    const int64_t j = base + (int64_t)r * kScanThreads + threadIdx.x;
-    if (j < n) atomicAdd(&cnt[(int)((keys[j] >> shift) & 255ull)], 1);
+    const int i = r * kScanThreads + (int)threadIdx.x;
+    if (i < tl.count) atomicAdd(&cnt[(int)((keys[tl.start + i] >> shift) & 255ull)], 1);
   }
   __syncthreads();
-  hist[(size_t)threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
+  hist[(size_t)tl.hidx + (size_t)threadIdx.x * tl.hstride] = cnt[threadIdx.x];
 }
 
-// Moves the tile's keys and values to offs[d * nblk + tile] + their rank
+// Moves the tile's keys and values to offs[hidx + d hstride] + their rank
 // among the tile's keys of digit d (in index order).
 __global__ __launch_bounds__(kScanThreads) void k_radix_scatter(const unsigned long long* __restrict__ kin,
                                                                 const int* __restrict__ vin,
                                                                 unsigned long long* __restrict__ kout,
-                                                                int* __restrict__ vout, int n, int shift,
-                                                                const int* __restrict__ offs, int nblk) {
+                                                                int* __restrict__ vout, int64_t total,
+                                                                const RadixTile* __restrict__ tiles, int shift,
+                                                                const int* __restrict__ offs) {
   __shared__ int base[256];
   __shared__ int wcnt[kScanThreads / 64][256];
+  const RadixTile tl = tiles[blockIdx.x];
   const int t = (int)threadIdx.x, lane = t & 63, wave = t >> 6;
-  base[t] = offs[(size_t)t * nblk + blockIdx.x];
+  base[t] = offs[(size_t)tl.hidx + (size_t)t * tl.hstride];
 #pragma unroll
   for (int w = 0; w < kScanThreads / 64; ++w) wcnt[w][t] = 0;
   __syncthreads();
-  const int64_t tile = (int64_t)blockIdx.x * kScanTile;
   const unsigned long long below = (1ull << lane) - 1ull;
   for (int r = 0; r < kScanItems; ++r) {
-    const int64_t j = tile + (int64_t)r * kScanThreads + t;
-    const bool valid = j < n;
-    const unsigned long long key = valid ? kin[j] : 0ull;
-    const int val = valid ? vin[j] : 0;
+    const int i = r * kScanThreads + t;
+    const bool valid = i < tl.count;
+    const unsigned long long key = valid ? kin[tl.start + i] : 0ull;
+    const int val = valid ? vin[tl.start + i] : 0;
     const int d = (int)((key >> shift) & 255ull);
     unsigned long long peers = __ballot(valid);
 #pragma unroll
@@ -176,8 +193,8 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_scatter(const unsigned l
       base[t] = p;
     }
     __syncthreads();
-    const int pos = wcnt[wave][d] + rank;
-    if (valid && pos >= 0 && pos < n) {   // (always, with correct offsets)
+    const int64_t pos = (int64_t)wcnt[wave][d] + rank;
+    if (valid && pos >= 0 && pos < total) {   // (always, with correct offsets)
       kout[pos] = key;
       vout[pos] = val;
     }
@@ -188,33 +205,27 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_scatter(const unsigned l
   }
 }
 
-// Temporary storage of radix_sort_pairs for n keys, in ints: the digit
-// counts (256 per tile) and their scan's temporary.
-inline size_t radix_temp_ints(int n) {
-  const size_t nblk = (size_t)((n + kScanTile - 1) / kScanTile);
-  return 256 * nblk + scan_temp_ints((int64_t)(256 * nblk));
-}
-
-// Stable sort of (keys[i], vals[i]), i < n, by key; keys_tmp / vals_tmp are
-// ping-pong buffers of n entries, tmp holds radix_temp_ints(n) ints.  The
-// result is in keys / vals (eight passes).  Stream-ordered.
+// Stable sort of (keys[i], vals[i]) within every segment of the tile table
+// (ntiles tiles, nhist digit counts in all), by key; keys_tmp / vals_tmp are
+// ping-pong buffers of total entries, tmp holds nhist + scan_temp_ints(nhist)
+// ints.  The result is in keys / vals (eight passes).  Stream-ordered.
 inline hipError_t radix_sort_pairs(unsigned long long* keys, int* vals, unsigned long long* keys_tmp, int* vals_tmp,
-                                   int n, int* tmp, hipStream_t s) {
-  if (n <= 1) return hipSuccess;
-  const int nblk = (n + kScanTile - 1) / kScanTile;
+                                   int64_t total, const RadixTile* tiles, int ntiles, int64_t nhist, int* tmp,
+                                   hipStream_t s) {
+  if (total <= 1 || ntiles <= 0) return hipSuccess;
   int* hist = tmp;
-  int* stmp = tmp + (size_t)256 * nblk;
+  int* stmp = tmp + nhist;
   unsigned long long *ka = keys, *kb = keys_tmp;
   int *va = vals, *vb = vals_tmp;
   for (int pass = 0; pass < 8; ++pass) {
     const int shift = 8 * pass;
-    hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kScanThreads), 0, s, (const unsigned long long*)ka, n, shift,
-                       hist, nblk);
+    hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(kScanThreads), 0, s, (const unsigned long long*)ka, tiles,
+                       shift, hist);
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = scan_exclusive(hist, hist, (int64_t)256 * nblk, stmp, s);
+    if (e == hipSuccess) e = scan_exclusive(hist, hist, nhist, stmp, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(kScanThreads), 0, s, (const unsigned long long*)ka,
-                       (const int*)va, kb, vb, n, shift, (const int*)hist, nblk);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(ntiles), dim3(kScanThreads), 0, s, (const unsigned long long*)ka,
+                       (const int*)va, kb, vb, total, tiles, shift, (const int*)hist);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     unsigned long long* kt = ka;
