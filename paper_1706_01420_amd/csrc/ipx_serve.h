@@ -8,27 +8,30 @@
 //   poller  the only workgroup that reads host memory.  When gen changes it
 //           reads every mail word; for each slot with a new sequence number it
 //           copies desc[s] into device memory, clears the slot's completion
-//           counters, writes lim[s] = (seq << 32) | items, then publishes
+//           counters, writes lim[s] = (seq << 32) | claims, then publishes
 //           claim[s] = seq << 32 and sets the slot's bit in the claimable-slot
-//           mask.
-//   workers take one item at a time with one atomic add on claim[s] of a
+//           mask.  A claim is a run of serve_chunk(items, workers) consecutive
+//           tiles (one tile for requests smaller than twice the workers).
+//   workers take one claim at a time with one atomic add on claim[s] of a
 //           slot in the mask: each workgroup from its own starting slot
 //           (policy 0, requests spread over the workers), the oldest opened
 //           request first (policy 1: the first wave reads the open stamps of
 //           the claimable slots and picks the smallest), or the request with
-//           the fewest unclaimed items first (policy 2: the first wave reads
-//           the claim and limit words of the claimable slots); the returned word
-//           names the request (high half) and the item (low half).  The item is valid if lim[s] names the same
-//           request and the item is below its count; any other increment is a
-//           late claim on a finished request and is dropped, so no request
-//           can lose an item.  The worker that takes a slot's last item
-//           clears its mask bit.  The worker that completes a request's last item sums
-//           every component's tile partials in index order (the order of the
-//           other entry points), writes out[s], then fin[s] = seq.
+//           the fewest unclaimed claims first (policy 2: the first wave reads
+//           the claim and limit words of the claimable slots); the returned
+//           word names the request (high half) and the claim (low half).  The
+//           claim is valid if lim[s] names the same request and the claim is
+//           below its count; any other increment is a late claim on a
+//           finished request and is dropped, so no request can lose a tile.
+//           The worker that takes a slot's last claim clears its mask bit.
+//           After a claim's tiles, done[s] += 1; the worker that completes a
+//           request's last claim sums every component's tile partials in
+//           index order (the order of the other entry points), writes out[s],
+//           then fin[s] = seq.
 //   exit    the poller counts its polls that find neither a new request nor
 //           a claimable item; after `idle_limit` of them in a row it sets quit
 //           and opens no more requests.  Workers leave on quit or stop (after
-//           finishing the item they hold) and count themselves out of `live`;
+//           finishing the claim they hold) and count themselves out of `live`;
 //           the poller leaves when no worker is left, or at once on stop.
 //           Workers never leave on their own, so a loop that is running has
 //           all its workgroups (a request arriving after quit waits for the
@@ -92,6 +95,21 @@ struct ServeCtl {                  // device memory
 // Claim policies of the workers.
 enum : int { kServeSpread = 0, kServeOldestFirst = 1, kServeFewestFirst = 2 };
 
+// Tiles per claim of a request of `items` tiles with `workers` worker
+// workgroups: about two claims per worker for large requests (each claim is
+// one atomic on the slot's claim word and one on its done count, and every
+// worker of the loop would otherwise contend for them once per tile), one
+// tile per claim for requests smaller than twice the workers, at most 16.
+__host__ __device__ __forceinline__ unsigned serve_chunk(unsigned items, unsigned workers) {
+  const unsigned w2 = 2u * (workers > 0u ? workers : 1u);
+  const unsigned k = (items + w2 - 1u) / w2;
+  return k < 1u ? 1u : (k > 16u ? 16u : k);
+}
+__host__ __device__ __forceinline__ unsigned serve_claims(unsigned items, unsigned workers) {
+  const unsigned k = serve_chunk(items, workers);
+  return (items + k - 1u) / k;
+}
+
 struct ServeShared {               // fine-grained host memory
   unsigned long long gen;          // bumped by the host after each publication
   unsigned long long stop;
@@ -141,13 +159,13 @@ __device__ __forceinline__ void serve_open(ServeShared* hs, ServeCtl* ctl, Serve
   wait_mem();
   __syncthreads();
   if (threadIdx.x == 0) {
-    const unsigned items = (unsigned)load_dev(&dd[s].items);
+    const unsigned claims = serve_claims((unsigned)load_dev(&dd[s].items), gridDim.x - 1u);
     const unsigned long long stamp = load_dev(&ctl->opened) + 1ull;
     store_dev(&ctl->opened, stamp);
     store_dev(&st[s].stamp, stamp);
     store_dev(&st[s].open, seq);
     store_dev(&st[s].done, 0u);
-    store_dev(&st[s].lim, (seq << 32) | (unsigned long long)items);
+    store_dev(&st[s].lim, (seq << 32) | (unsigned long long)claims);
     wait_mem();
     store_dev(&st[s].claim, seq << 32);
     wait_mem();
@@ -222,12 +240,48 @@ __device__ __forceinline__ bool serve_claim(ServeCtl* ctl, ServeSlot* __restrict
   return true;
 }
 
+// The totals of components c0 .. c0 + 7 (those below nacc) of a request's
+// tile partials (component-major, nt per component), each added in exactly
+// the order of reduce_component: thread t sums tiles t, t + 256, ... in
+// index order, the wave adds its lanes by the xor butterfly, the four wave
+// totals are added as (w0 + w1) + (w2 + w3).  The eight components share the
+// memory round trips (the partials' loads of one stride step are in flight
+// together) instead of taking one reduction each.  Result in tot (LDS).
+constexpr int kServeReduceGroup = 8;
+__device__ __forceinline__ void serve_reduce_group(const double* __restrict__ partials, int64_t nt, int c0, int nacc,
+                                                   double* tot) {
+  __shared__ double wl[kServeReduceGroup][kThreads / 64];
+  double sum[kServeReduceGroup];
+#pragma unroll
+  for (int k = 0; k < kServeReduceGroup; ++k) sum[k] = 0.0;
+  for (int64_t i = threadIdx.x; i < nt; i += kThreads) {
+    double v[kServeReduceGroup];
+#pragma unroll
+    for (int k = 0; k < kServeReduceGroup; ++k)
+      v[k] = c0 + k < nacc ? ldg<true>(partials + (int64_t)(c0 + k) * nt + i, 0u) : 0.0;
+#pragma unroll
+    for (int k = 0; k < kServeReduceGroup; ++k) sum[k] += v[k];
+  }
+#pragma unroll
+  for (int k = 0; k < kServeReduceGroup; ++k) sum[k] = wave_sum(sum[k]);
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < kServeReduceGroup; ++k) wl[k][threadIdx.x >> 6] = sum[k];
+  __syncthreads();
+  if (threadIdx.x < kServeReduceGroup) {
+    const int k = threadIdx.x;
+    tot[k] = (wl[k][0] + wl[k][1]) + (wl[k][2] + wl[k][3]);
+  }
+  __syncthreads();
+}
+
 __device__ __forceinline__ void serve_work(ServeShared* hs, ServeCtl* ctl, ServeDesc* __restrict__ dd,
                                            ServeSlot* __restrict__ st, int policy) {
   __shared__ ServeDesc sd;          // the current item's request
   __shared__ RedBuf<kOuterCapTag> red;
   __shared__ int cmd, cslot, citem;
   __shared__ int last;
+  __shared__ double red_totals[kServeReduceGroup];
   const unsigned rot = blockIdx.x & 63u;  // spreads the workers' first choice over the slots
   for (;;) {
     if (policy != kServeSpread) {
@@ -239,9 +293,12 @@ __device__ __forceinline__ void serve_work(ServeShared* hs, ServeCtl* ctl, Serve
         const unsigned lane = threadIdx.x;
         int ex = 0;
         unsigned long long m = 0ull;
-        if (lane == 0) {
-          ex = load_dev(&ctl->stop) || load_dev(&ctl->quit);
-          if (!ex) m = load_dev(&ctl->mask);
+        if (lane == 0) {  // the three control words in one round trip
+          const unsigned long long stop = load_dev(&ctl->stop);
+          const unsigned int quit = load_dev(&ctl->quit);
+          const unsigned long long mask = load_dev(&ctl->mask);
+          ex = stop || quit;
+          if (!ex) m = mask;
         }
         ex = __shfl(ex, 0, 64);
         m = __shfl(m, 0, 64);
@@ -280,10 +337,13 @@ __device__ __forceinline__ void serve_work(ServeShared* hs, ServeCtl* ctl, Serve
       }
     } else if (threadIdx.x == 0) {
       cmd = kCmdIdle;
-      if (load_dev(&ctl->stop) || load_dev(&ctl->quit)) {
+      // the three control words in one round trip
+      const unsigned long long stop = load_dev(&ctl->stop);
+      const unsigned int quit = load_dev(&ctl->quit);
+      unsigned long long m = load_dev(&ctl->mask);
+      if (stop || quit) {
         cmd = kCmdExit;
       } else {
-        unsigned long long m = load_dev(&ctl->mask);
         m = rot ? (m >> rot) | (m << (64u - rot)) : m;
         while (m != 0ull && cmd == kCmdIdle) {
           const int s = (int)((__builtin_ctzll(m) + rot) & 63u);
@@ -310,36 +370,42 @@ __device__ __forceinline__ void serve_work(ServeShared* hs, ServeCtl* ctl, Serve
     copy_dev_to_lds((unsigned long long*)&sd, (const unsigned long long*)&dd[s],
                     (int)(sizeof(ServeDesc) / sizeof(unsigned long long)));
     __syncthreads();
-    const int tile = citem;
-    if (sd.model == 1) {
-      if (sd.grad) tile_nll<1, true, true>(sd.seg, sd.k.m1, tile, red);
-      else tile_nll<1, false, true>(sd.seg, sd.k.m1, tile, red);
-    } else if (sd.model == 2) {
-      if (sd.grad) tile_nll<2, true, true>(sd.seg, sd.k.m2, tile, red);
-      else tile_nll<2, false, true>(sd.seg, sd.k.m2, tile, red);
-    } else if (sd.model == 3) {
-      if (sd.grad) tile_angtime<true, true, kOuterCapTag>(sd.seg, sd.k.m3, &sd.k.m3.C[0][0], tile, red);
-      else tile_angtime<false, true, kOuterCapTag>(sd.seg, sd.k.m3, &sd.k.m3.C[0][0], tile, red);
-    } else {
-      if (sd.grad) tile_angtime<true, true, kOuterCapTag, true>(sd.seg, sd.k.m3, &sd.k.m3.C[0][0], tile, red);
-      else tile_angtime<false, true, kOuterCapTag, true>(sd.seg, sd.k.m3, &sd.k.m3.C[0][0], tile, red);
+    // claim citem covers the tiles chunk x citem .. (the request's last tile)
+    const unsigned chunk = serve_chunk((unsigned)sd.items, gridDim.x - 1u);
+    const int t0 = citem * (int)chunk;
+    const int t1 = min(t0 + (int)chunk, sd.items);
+    for (int tile = t0; tile < t1; ++tile) {
+      if (sd.model == 1) {
+        if (sd.grad) tile_nll<1, true, true>(sd.seg, sd.k.m1, tile, red);
+        else tile_nll<1, false, true>(sd.seg, sd.k.m1, tile, red);
+      } else if (sd.model == 2) {
+        if (sd.grad) tile_nll<2, true, true>(sd.seg, sd.k.m2, tile, red);
+        else tile_nll<2, false, true>(sd.seg, sd.k.m2, tile, red);
+      } else if (sd.model == 3) {
+        if (sd.grad) tile_angtime<true, true, kOuterCapTag>(sd.seg, sd.k.m3, &sd.k.m3.C[0][0], tile, red);
+        else tile_angtime<false, true, kOuterCapTag>(sd.seg, sd.k.m3, &sd.k.m3.C[0][0], tile, red);
+      } else {
+        if (sd.grad) tile_angtime<true, true, kOuterCapTag, true>(sd.seg, sd.k.m3, &sd.k.m3.C[0][0], tile, red);
+        else tile_angtime<false, true, kOuterCapTag, true>(sd.seg, sd.k.m3, &sd.k.m3.C[0][0], tile, red);
+      }
     }
-    // every lane's stores of this item (its tile partials) complete before
-    // the item is counted as done
+    // every lane's stores of this claim's tiles (their partials) complete
+    // before the claim is counted as done
     wait_mem();
     __syncthreads();
     if (threadIdx.x == 0) {
       const unsigned int prev = __hip_atomic_fetch_add(&st[s].done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      last = prev + 1 == (unsigned)sd.items ? 1 : 0;
+      last = prev + 1 == serve_claims((unsigned)sd.items, gridDim.x - 1u) ? 1 : 0;
       wait_mem();  // the partials are read after the count
     }
     __syncthreads();
     if (last) {
-      // every item of the request is complete: fixed-order reduction
-      for (int comp = 0; comp < sd.nacc; ++comp) {
-        const double total =
-            reduce_component<true>(sd.seg.partials + (int64_t)comp * sd.seg.n_tiles, sd.seg.n_tiles);
-        if (threadIdx.x == 0) store_sys(&hs->out[s][comp], total);
+      // every item of the request is complete: fixed-order reduction, eight
+      // components at a time
+      for (int c0 = 0; c0 < sd.nacc; c0 += kServeReduceGroup) {
+        serve_reduce_group(sd.seg.partials, sd.seg.n_tiles, c0, sd.nacc, red_totals);
+        if (threadIdx.x < kServeReduceGroup && c0 + (int)threadIdx.x < sd.nacc)
+          store_sys(&hs->out[s][c0 + threadIdx.x], red_totals[threadIdx.x]);
         __syncthreads();
       }
       if (threadIdx.x == 0) {

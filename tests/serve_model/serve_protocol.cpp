@@ -9,14 +9,16 @@
 //            copies desc[s] to the device copy dd[s], stamps the opening
 //            order, sets open/done/lim, publishes claim[s] = seq << 32
 //            (release) and the slot's bit in the mask.
-//   workers  take one item with one fetch_add on claim[s] of a slot in the
+//   workers  take one claim (a run of consecutive items, chunk_of) with one
+//            fetch_add on claim[s] of a slot in the
 //            mask (from a per-worker starting slot, oldest stamp first, or
-//            fewest unclaimed items first, read from the claim and lim words);
-//            the item is valid iff lim[s] names the same sequence number and
-//            the item is below its count; the last valid item clears the
-//            mask bit; after the item, done[s] += 1 (acq_rel), and the worker
-//            completing the last item sums the partials in item order, writes
-//            out[s] and fin[s] = seq (release).
+//            fewest unclaimed claims first, read from the claim and lim
+//            words); the claim is valid iff lim[s] names the same sequence
+//            number and the claim is below the request's claim count; the
+//            last valid claim clears the mask bit; after a claim's items,
+//            done[s] += 1 (acq_rel), and the worker completing the last claim
+//            sums the partials in item order, writes out[s] and fin[s] = seq
+//            (release).
 // The device code gets the release/acquire pairs above from relaxed
 // device-coherent atomics with the writer waiting for its stores to complete
 // before the publishing atomic and the reader issuing its loads after the
@@ -34,6 +36,7 @@
 // Built with -DOLD_PROTOCOL the claim is validated against the sequence
 // number read before the fetch_add (the earlier, faulty rule): the forced
 // interleaving then loses an item and the request never completes (exit 3).
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cstdint>
@@ -74,7 +77,8 @@ struct Request {
 
 struct Model {
   int nslots = 4;
-  int policy = 0;            // 0 spread, 1 oldest first, 2 fewest unclaimed items first
+  int policy = 0;            // 0 spread, 1 oldest first, 2 fewest unclaimed claims first
+  int nworkers = 1;          // the device loop's chunk rule depends on it
   // host <-> device words
   std::atomic<uint64_t> gen{0}, stop{0};
   std::atomic<uint64_t> mail[kMaxSlots];
@@ -100,6 +104,18 @@ struct Model {
 
 double item_value(int req, int item) { return 1.0 + req * 0.001 + item * 1e-6; }
 
+// The device loop's claim size: a claim is a run of chunk_of(items, workers)
+// consecutive items (about two claims per worker, at most 16 items).
+int chunk_of(int items, int workers) {
+  const int w2 = 2 * std::max(workers, 1);
+  const int k = (items + w2 - 1) / w2;
+  return std::min(std::max(k, 1), 16);
+}
+int claims_of(int items, int workers) {
+  const int k = chunk_of(items, workers);
+  return (items + k - 1) / k;
+}
+
 // Poller: open slot s for seq.
 void poller_open(Model& M, int s, uint64_t seq) {
   M.dd[s] = M.desc[s];                       // ordered after the acquire of mail[s]
@@ -108,7 +124,7 @@ void poller_open(Model& M, int s, uint64_t seq) {
   M.st[s].stamp.store(stamp, std::memory_order_relaxed);
   M.st[s].open.store(seq, std::memory_order_relaxed);
   M.st[s].done.store(0, std::memory_order_relaxed);
-  M.st[s].lim.store((seq << 32) | (uint64_t)M.dd[s].items, std::memory_order_release);
+  M.st[s].lim.store((seq << 32) | (uint64_t)claims_of(M.dd[s].items, M.nworkers), std::memory_order_release);
   M.st[s].claim.store(seq << 32, std::memory_order_release);
   M.mask.fetch_or(1ull << s, std::memory_order_acq_rel);
 }
@@ -222,10 +238,14 @@ void worker(Model& M, int id) {
     }
     const Desc d = M.dd[s];                  // ordered after the claim's acquire
     Request& R = (*M.reqs)[d.req];
-    R.processed[item].fetch_add(1, std::memory_order_relaxed);
-    R.partial[item] = item_value(d.req, item);
+    // claim `item` covers the items chunk x item .. (the request's last)
+    const int chunk = chunk_of(d.items, M.nworkers);
+    for (int i = item * chunk; i < std::min(item * chunk + chunk, d.items); ++i) {
+      R.processed[i].fetch_add(1, std::memory_order_relaxed);
+      R.partial[i] = item_value(d.req, i);
+    }
     const uint32_t prev = M.st[s].done.fetch_add(1, std::memory_order_acq_rel);
-    if ((int)prev + 1 == d.items) {
+    if ((int)prev + 1 == claims_of(d.items, M.nworkers)) {
       double tot = 0.0;
       for (int i = 0; i < d.items; ++i) tot += R.partial[i];
       M.out[s] = tot;
@@ -240,6 +260,7 @@ int run(int policy, int nreq, int nworkers, int nslots, unsigned seed, bool late
   Model M;
   M.nslots = nslots;
   M.policy = policy;
+  M.nworkers = nworkers;
   std::vector<Request> reqs(nreq);
   M.reqs = &reqs;
   std::mt19937 rng(seed);
