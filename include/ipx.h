@@ -45,7 +45,8 @@ typedef enum {
   IPX_EBUSY = -4,     /* resource busy (queue full, result not ready) */
   IPX_ENOTFOUND = -5, /* unknown handle or ticket */
   IPX_ETIMEOUT = -6,  /* wait timed out */
-  IPX_EDOMAIN = -7    /* parameters outside the domain, or a non-finite likelihood */
+  IPX_EDOMAIN = -7,   /* parameters outside the domain, or a non-finite likelihood */
+  IPX_ECANCELED = -8  /* a served request cancelled before it reached the device */
 } ipx_status;
 
 /*
@@ -355,6 +356,11 @@ IPX_API ipx_status ipx_plan_autotune(ipx_ctx *ctx, ipx_plan *plan, const double 
  *   requests are already waiting; IPX_ENOMEM if the request alone exceeds the
  *   scratch budget).  Results are taken once, with ipx_poll (IPX_EBUSY while
  *   running) or ipx_wait (IPX_ETIMEOUT after timeout_ns; < 0 waits forever).
+ *   ipx_cancel withdraws a request that is still waiting for a slot: its
+ *   result becomes available at once with status IPX_ECANCELED (nll = +inf)
+ *   and must still be taken with ipx_poll / ipx_wait.  A request already on
+ *   the device, or finished, cannot be cancelled (IPX_EBUSY; it completes
+ *   normally); an unknown ticket gives IPX_ENOTFOUND.
  *   ipx_server_drain blocks until every request submitted before it has
  *   finished (submissions during the drain return IPX_EBUSY); their results
  *   stay available to ipx_poll / ipx_wait, and the server accepts requests
@@ -404,6 +410,7 @@ IPX_API ipx_status ipx_server_start(ipx_ctx *ctx, const ipx_server_cfg *cfg, ipx
 IPX_API ipx_status ipx_submit(ipx_server *srv, const ipx_request *req, uint64_t *ticket);
 IPX_API ipx_status ipx_poll(ipx_server *srv, uint64_t ticket, ipx_result *out);
 IPX_API ipx_status ipx_wait(ipx_server *srv, uint64_t ticket, int64_t timeout_ns, ipx_result *out);
+IPX_API ipx_status ipx_cancel(ipx_server *srv, uint64_t ticket);
 IPX_API ipx_status ipx_server_drain(ipx_server *srv);
 IPX_API ipx_status ipx_server_stop(ipx_server *srv);
 /* Host-side counters of a running server (monitoring). */
@@ -413,6 +420,7 @@ typedef struct {
   uint64_t launches;       /* launches of the device loop */
   uint64_t pending;        /* waiting for a slot or scratch now */
   uint64_t in_flight;      /* in device slots now */
+  uint64_t cancelled;      /* requests withdrawn by ipx_cancel */
 } ipx_server_stats;
 IPX_API ipx_status ipx_server_stats_read(ipx_server *srv, ipx_server_stats *out);
 

@@ -1932,6 +1932,31 @@ extern "C" ipx_status ipx_wait(ipx_server* S, uint64_t ticket, int64_t timeout_n
   return take_result(S, S->reqs.find(ticket), out);
 }
 
+extern "C" ipx_status ipx_cancel(ipx_server* S, uint64_t ticket) {
+  if (!S) return fail(IPX_EINVAL, "ipx_cancel: NULL server");
+  ServerUse use(S);
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) return fail(IPX_ENOTFOUND, "ipx_cancel: unknown ticket %llu", (unsigned long long)ticket);
+  ServeReq* r = it->second;
+  auto p = std::find(S->pending.begin(), S->pending.end(), r);
+  if (r->done || p == S->pending.end())
+    return fail(IPX_EBUSY, "ipx_cancel: ticket %llu is %s", (unsigned long long)ticket,
+                r->done ? "finished" : "on the device");
+  // still waiting: it holds no slot and no scratch
+  S->pending.erase(p);
+  S->n_pending.store((int)S->pending.size(), std::memory_order_relaxed);
+  r->res.status = IPX_ECANCELED;
+  r->res.np = r->np;
+  r->res.nll = std::numeric_limits<double>::infinity();
+  r->t_done = std::chrono::steady_clock::now();
+  r->res.latency_us = std::chrono::duration<double, std::micro>(r->t_done - r->t_submit).count();
+  r->done = true;
+  ++S->stats.cancelled;
+  S->cv.notify_all();
+  return IPX_OK;
+}
+
 extern "C" ipx_status ipx_server_stats_read(ipx_server* S, ipx_server_stats* out) {
   if (!S || !out) return fail(IPX_EINVAL, "ipx_server_stats_read: NULL argument");
   ServerUse use(S);

@@ -24,8 +24,9 @@ IPX_EBUSY = -4
 IPX_ENOTFOUND = -5
 IPX_ETIMEOUT = -6
 IPX_EDOMAIN = -7
+IPX_ECANCELED = -8
 STATUS_NAMES = {0: "IPX_OK", -1: "IPX_EINVAL", -2: "IPX_ENOMEM", -3: "IPX_EDEVICE", -4: "IPX_EBUSY",
-                -5: "IPX_ENOTFOUND", -6: "IPX_ETIMEOUT", -7: "IPX_EDOMAIN"}
+                -5: "IPX_ENOTFOUND", -6: "IPX_ETIMEOUT", -7: "IPX_EDOMAIN", -8: "IPX_ECANCELED"}
 
 IPX_MODEL_MASS = 1
 IPX_MODEL_MASSTIME = 2
@@ -87,6 +88,7 @@ _SIGNATURES = [
     ("ipx_poll", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
     ("ipx_wait", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64, ctypes.c_void_p]),
     ("ipx_server_drain", ctypes.c_int, [ctypes.c_void_p]),
+    ("ipx_cancel", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
     ("ipx_server_stop", ctypes.c_int, [ctypes.c_void_p]),
     ("ipx_server_stats_read", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     ("toy_generate", ctypes.c_int,
@@ -521,7 +523,7 @@ def ipx_poll(srv, ticket):
     st = _lib.ipx_poll(srv, ctypes.c_uint64(ticket), ctypes.byref(r))
     if st == IPX_EBUSY:
         return None
-    if st not in (IPX_OK, IPX_EDOMAIN, IPX_ETIMEOUT):
+    if st not in (IPX_OK, IPX_EDOMAIN, IPX_ETIMEOUT, IPX_ECANCELED):
         _check(st)
     return _result_dict(r)
 
@@ -529,9 +531,16 @@ def ipx_poll(srv, ticket):
 def ipx_wait(srv, ticket, timeout_s=-1.0):
     r = _Result()
     st = _lib.ipx_wait(srv, ctypes.c_uint64(ticket), int(timeout_s * 1e9) if timeout_s >= 0 else -1, ctypes.byref(r))
-    if st not in (IPX_OK, IPX_EDOMAIN):
+    if st not in (IPX_OK, IPX_EDOMAIN, IPX_ECANCELED):
         _check(st)
     return _result_dict(r)
+
+
+def ipx_cancel(srv, ticket):
+    """Withdraw a request still waiting for a slot (its result, status
+    IPX_ECANCELED, is then taken as usual); IpxError with IPX_EBUSY if it is
+    on the device or finished."""
+    _check(_lib.ipx_cancel(srv, ctypes.c_uint64(ticket)))
 
 
 def ipx_server_drain(srv):
@@ -546,7 +555,7 @@ def ipx_server_stop(srv):
 
 class _ServerStats(ctypes.Structure):
     _fields_ = [("published", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("launches", ctypes.c_uint64),
-                ("pending", ctypes.c_uint64), ("in_flight", ctypes.c_uint64)]
+                ("pending", ctypes.c_uint64), ("in_flight", ctypes.c_uint64), ("cancelled", ctypes.c_uint64)]
 
 
 def ipx_server_stats_read(srv):

@@ -7,7 +7,13 @@ Events: toy_generate_batch with key (seed, toy_id = j) for toy j.
 Fits: fit.bfgs either through one nll_eval_batch per round (batched, graph
 replay, launch schedule from the autotuner) or through nll_grad per toy (plain
 loop); the per-toy arithmetic is the same, so both give the same minima.
+Studies: `study` fits toys in batches and appends one JSON record per toy to
+a file; a study started again on the same file skips the toys it already
+holds (checkpoint and resume).
 """
+import json
+import os
+
 import numpy as np
 
 from . import fit
@@ -89,3 +95,78 @@ def fit_plain(ipx, ctx, model, datasets, theta0, steps, **kw):
                                                            "evals")}
     out["rounds"] = max(r["rounds"] for r in res)
     return out
+
+
+def completed_ids(path, seed):
+    """Toy ids with a record for `seed` in the JSONL file (none if absent); a
+    torn last line (an interrupted write) is ignored."""
+    done = set()
+    if not os.path.exists(path):
+        return done
+    with open(path) as fh:
+        for line in fh:
+            try:
+                rec = json.loads(line)
+            except ValueError:
+                continue
+            if rec.get("seed") == seed:
+                done.add(int(rec["toy_id"]))
+    return done
+
+
+def study(ipx, ctx, model, theta_gen, seed, ntoys, path, batch=64, start_offset=0.5, errors=True, flags=0,
+          limit=None, **fit_kw):
+    """Toy study with checkpoints: toys 0 .. ntoys - 1 of (seed, model) are
+    generated, fitted from theta_gen + start_offset x steps and written to
+    `path` (JSONL, one record per toy: seed, toy_id, n, theta, errors, nll,
+    edm, converged, evals), `batch` toys at a time, each batch appended and
+    flushed before the next.  Toys already recorded for this seed are
+    skipped, so a study interrupted at any point resumes where it stopped:
+    the counter-based stream regenerates a toy exactly from (seed, toy_id),
+    and a toy's fit does not depend on which toys share its batch, so the
+    records are those of an uninterrupted run.  limit: fit at most this
+    many toys in this call.  Returns the number of toys fitted by this
+    call."""
+    from . import fit
+    theta_gen = np.asarray(theta_gen, np.float64)
+    _, sizes = toy_sizes(seed, ntoys)
+    todo = [j for j in range(ntoys) if j not in completed_ids(path, seed)]
+    if limit is not None:
+        todo = todo[:max(int(limit), 0)]
+    fitted = 0
+    for b0 in range(0, len(todo), batch):
+        ids = np.array(todo[b0:b0 + batch])
+        n = sizes[ids]
+        ds, stats = ipx.toy_generate_batch(ctx, model, theta_gen, seed, ids, n, flags)
+        try:
+            for j, st in zip(ids, stats):
+                if st["n_violations"]:
+                    raise RuntimeError("acceptance bound violated in toy %d" % j)
+            steps = steps_for(model, n)
+            theta0 = theta_gen[None, :] + start_offset * steps
+            plan = ipx.ipx_plan_create(ctx, ds)
+            try:
+                ev = batched_evaluator(ipx, ctx, plan)
+                res = fit.bfgs(ev, theta0, steps, **fit_kw)
+                err = fit.errors(ev, res["theta"], steps) if errors else np.full_like(res["theta"], np.nan)
+            finally:
+                ipx.ipx_plan_destroy(plan)
+        finally:
+            for d in ds:
+                ipx.ipx_dataset_destroy(ctx, d)
+        with open(path, "a+") as fh:
+            # a torn last line (an interrupted write) is closed off first
+            if fh.tell() > 0:
+                fh.seek(fh.tell() - 1)
+                if fh.read(1) != "\n":
+                    fh.write("\n")
+            for k, j in enumerate(ids):
+                rec = {"seed": int(seed), "model": int(model), "toy_id": int(j), "n": int(n[k]),
+                       "theta": res["theta"][k].tolist(), "errors": err[k].tolist(), "nll": float(res["f"][k]),
+                       "edm": float(res["edm"][k]), "converged": bool(res["converged"][k]),
+                       "evals": int(res["evals"][k])}
+                fh.write(json.dumps(rec) + "\n")
+            fh.flush()
+            os.fsync(fh.fileno())
+        fitted += len(ids)
+    return fitted

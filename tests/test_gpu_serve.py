@@ -179,6 +179,43 @@ def test_errors_stay_with_their_request_and_idle_relaunch(lib, ctx, datasets):
         lib.ipx_server_stop(srv)
 
 
+def test_cancel_withdraws_waiting_requests(lib, ctx, datasets):
+    """One slot and a queue of large gradient requests: the late ones are
+    still waiting when cancelled (IPX_OK, result status IPX_ECANCELED); a
+    request on the device or finished is not (IPX_EBUSY) and completes with
+    the plain call's result; a taken ticket is unknown (IPX_ENOTFOUND)."""
+    model, d = max(datasets, key=lambda md: (md[0] == 3, lib.ipx_dataset_size(md[1])))
+    th = np.array(M.THETA_GEN[model])
+    f, g = lib.nll_grad(ctx, d, th)
+    srv = lib.ipx_server_start(ctx, slots=1)
+    try:
+        say("serve cancel")
+        tickets = [lib.ipx_submit(srv, d, th, True) for _ in range(12)]
+        cancelled = []
+        for t in tickets[::-1][:6]:
+            try:
+                lib.ipx_cancel(srv, t)
+                cancelled.append(t)
+            except lib.IpxError as err:
+                assert err.status == lib.IPX_EBUSY
+        assert cancelled, "every request had reached the device"
+        with pytest.raises(lib.IpxError) as e:
+            lib.ipx_cancel(srv, tickets[0])          # on the device or finished
+        assert e.value.status == lib.IPX_EBUSY
+        for t in tickets:
+            r = lib.ipx_wait(srv, t, 60.0)
+            if t in cancelled:
+                assert r["status"] == lib.IPX_ECANCELED and r["nll"] == np.inf
+            else:
+                assert r["status"] == 0 and r["nll"] == f and np.array_equal(r["grad"], g)
+        with pytest.raises(lib.IpxError) as e:
+            lib.ipx_cancel(srv, tickets[-1])         # taken
+        assert e.value.status == lib.IPX_ENOTFOUND
+        assert lib.ipx_server_stats_read(srv)["cancelled"] == len(cancelled)
+    finally:
+        lib.ipx_server_stop(srv)
+
+
 def test_drain_then_stop_with_blocked_waiters(lib, ctx, datasets):
     """ipx_server_drain finishes every request submitted before it (with two
     slots, most of the six wait for a slot when it is called): afterwards
