@@ -279,9 +279,9 @@ def cpu_baseline(cols, w, theta, reps=5, ntoys=16, nreq=16):
     # batched-toy fits: the same toys (seed, ids, sizes) and start points
     seed = 170601424
     _, sizes = toys.toy_sizes(seed, 512)
-    sizes = sizes[:ntoys]
     steps = toys.steps_for(3, sizes)
-    start = np.array(theta)[None, :] + 0.5 * steps
+    start = fit_start(np.array(theta), steps, seed)[:ntoys]   # the GPU study's first toys
+    sizes, steps = sizes[:ntoys], steps[:ntoys]
     _CPU["gen"] = (list(theta), seed, sizes)
     with fork.Pool(workers) as pool:
         _CPU["toys"] = pool.map(_cpu_gen_toy, range(ntoys))
@@ -340,12 +340,21 @@ def served_mix(ndatasets=64, nclients=256, nreq=600, seed=170601425):
     return sizes, models, reqs
 
 
+def fit_start(theta, steps, seed):
+    """Start points of the study's fits: theta + 2 steps with seeded signs."""
+    import numpy as np
+    signs = np.random.default_rng(seed).choice(np.array([-1.0, 1.0]), size=steps.shape)
+    return np.asarray(theta, np.float64)[None, :] + 2.0 * signs * steps
+
+
 def bench_batched_fits(ipx, ctx, ntoys=512, plain_subset=64, seed=170601424):
     """512 pseudo-experiments of the angular model, sizes Poisson(mu), mu
     log-uniform in [1e4, 2e5]; generated on the device, each fitted by the
     lockstep BFGS with the analytic gradient: all toys through one batched
     evaluation per round (graph replay) versus the plain per-toy loop (one
-    nll_grad call per evaluation), same algorithm and stopping rule."""
+    nll_grad call per evaluation), same algorithm and stopping rule.  Each
+    fit starts two parameter steps (about two statistical errors) from the
+    generation point in every parameter, with seeded random signs."""
     import numpy as np
     import torch
     from paper_1706_01420_amd import fit, toys, workloads
@@ -357,7 +366,7 @@ def bench_batched_fits(ipx, ctx, ntoys=512, plain_subset=64, seed=170601424):
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t0
     steps = toys.steps_for(3, sizes)
-    start = theta[None, :] + 0.5 * steps
+    start = fit_start(theta, steps, seed)
     plan = None
     try:
         # launch schedule: the autotuner times its candidates on this plan
