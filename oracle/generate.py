@@ -34,7 +34,8 @@ Per model (every acceptance test is "u M < R" with a strict '<'):
      phi = pi (2 u4 - 1); accept iff
          u5 M3 < e^{Gamma_min t0} sum_k f_k(Omega) sum_j C_kj h_j(t0)
      (the unconvolved time-angular density; h = e^{-Gamma t}(cosh, sinh,
-     cos, sin)), M3 = sum_k max|f_k| sum_j |C_kj|; then Box-Muller with u6, u7:
+     cos, sin)), M3 of bound_angtime (about 15 % acceptance at the
+     generation point); then Box-Muller with u6, u7:
      t = t0 + sigma_t g1 kept in [0.3, 15], m = mu_m + sigma_m g2 kept in
      [5200, 5500]; weight w = 0.8 + 0.2 u8.
 
@@ -95,9 +96,29 @@ def bound_masstime(theta):
 
 
 def bound_angtime(theta):
+    """M3 = (1 + 1e-12) [max(S0, S1 / 2) + S2], over k = 0 .. 9 with
+    m_k = max|f_k|:
+        S0 = sum m_k |C_k0|,  S1 = sum m_k |C_k0 + s C_k1|  (s = sign of DeltaGamma, + for 0),
+        S2 = sum m_k sqrt(C_k2^2 + C_k3^2).
+    Why it bounds the ratio: with x = e^{-|DeltaGamma| t0} in (0, 1], the time
+    functions times e^{Gamma_min t0} are h0 = (1 + x)/2, h1 = s (1 - x)/2 and
+    (h2, h3) of length sqrt(x) <= 1; with A_j = sum_k f_k C_kj the ratio is
+    [(A0 + s A1) + x (A0 - s A1)]/2 + A2 h2 + A3 h3, whose first part is linear
+    in x (largest modulus at x = 0 or 1: |A0 + s A1|/2 or |A0|) and whose
+    second part is at most |(A2, A3)|; then |A0| <= S0, |A0 + s A1| <= S1 and
+    |(A2, A3)| <= S2 (triangle inequalities).  The factor covers the rounding
+    of the sums.  Sums in increasing k."""
     fL, fpe, Fs, dpa, dpe, dS, G, DG, DM, phis = theta[:10]
-    C = np.array(Mo.time_coefficients(fL, fpe, Fs, dpa, dpe, dS, phis), dtype=np.float64)
-    return float(np.sum(ANG_MAX * np.sum(np.abs(C), axis=1)))
+    C = Mo.time_coefficients(fL, fpe, Fs, dpa, dpe, dS, phis)
+    s = -1.0 if DG < 0.0 else 1.0
+    S0 = S1 = S2 = 0.0
+    for k in range(10):
+        c0, c1, c2, c3 = (float(C[k][j]) for j in range(4))
+        m = float(ANG_MAX[k])
+        S0 += m * abs(c0)
+        S1 += m * abs(c0 + s * c1)
+        S2 += m * float(np.sqrt(c2 * c2 + c3 * c3))
+    return (1.0 + 1e-12) * (max(S0, 0.5 * S1) + S2)
 
 
 # ---------------------------------------------------------------------------

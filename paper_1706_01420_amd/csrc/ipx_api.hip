@@ -638,6 +638,7 @@ static double host_conv_integral(double G, double sig) {
   return (dphi - F(kTHi) + F(kTLo)) / G;
 }
 
+static double g_DG_sign(double dg) { return dg < 0.0 ? -1.0 : 1.0; }
 static const double kAngMax[10] = {2.0, 1.0, 1.0, 1.0, 0.70710678118654752440, 0.70710678118654752440,
                                    2.0 / 3.0, 0.81649658092772603273, 0.81649658092772603273,
                                    2.3094010767585030580};
@@ -676,16 +677,22 @@ static void gen_setup(int model, const double* th, uint64_t seed, uint64_t toy, 
   } else {
     AngTimeHoist a;
     hoist_angtime(th, ang_settings_default(), a);
-    double M = 0.0;
+    // M3 = (1 + 1e-12) [max(S0, S1 / 2) + S2]: with x = e^{-|DeltaGamma| t0},
+    // e^{Gamma_min t0} times the time functions are (1 + x)/2, s (1 - x)/2
+    // (s the sign of DeltaGamma) and a pair of length sqrt(x) <= 1; the
+    // cosh / sinh part is linear in x, largest at x = 0 or 1; S0, S1, S2
+    // bound |A_0|, |A_0 + s A_1| and |(A_2, A_3)| (A_j = sum_k f_k C_kj) by
+    // triangle inequalities with m_k = max|f_k|; the factor covers rounding
+    const double sg = g_DG_sign(th[7]);
+    double S0 = 0.0, S1 = 0.0, S2 = 0.0;
     for (int k = 0; k < 10; ++k) {
-      double s = 0.0;
-      for (int j = 0; j < 4; ++j) {
-        h.C[4 * k + j] = a.k.C[k][j];
-        s += std::fabs(a.k.C[k][j]);
-      }
-      M += kAngMax[k] * s;
+      for (int j = 0; j < 4; ++j) h.C[4 * k + j] = a.k.C[k][j];
+      const double c0 = a.k.C[k][0], c1 = a.k.C[k][1], c2 = a.k.C[k][2], c3 = a.k.C[k][3];
+      S0 += kAngMax[k] * std::fabs(c0);
+      S1 += kAngMax[k] * std::fabs(c0 + sg * c1);
+      S2 += kAngMax[k] * std::sqrt(c2 * c2 + c3 * c3);
     }
-    g.M = M;
+    g.M = (1.0 + 1e-12) * (std::fmax(S0, 0.5 * S1) + S2);
     g.G = th[6]; g.DG = th[7]; g.DM = th[8];
     g.gmin = g.G - std::fabs(g.DG) / 2.0;
     g.mu3 = th[10]; g.sig3 = th[11];
@@ -707,7 +714,7 @@ struct GenScratch {
   }
 };
 
-static const double kGenEfficiency[4] = {0.0, 0.25, 0.5, 0.05};  // first-batch guesses
+static const double kGenEfficiency[4] = {0.0, 0.25, 0.5, 0.1};  // first-batch guesses
 static const int64_t kGenMaxBatch = 1 << 24;
 
 template <int MODEL>

@@ -407,6 +407,22 @@ def _phi_half_range(ua, ub, uc):
     return 2.0 * ua - 1.0, 2.0 * ub - 1.0, np.pi * uc                 # phi on [0, pi] only
 
 
+def _bound_ang_without_oscillation(theta):
+    """M3 missing S2, the bound of the cos / sin (Delta m) terms."""
+    fL, fpe, Fs, dpa, dpe, dS, g, dg, dm, phis = [float(x) for x in theta[:10]]
+    C = M.time_coefficients(fL, fpe, Fs, dpa, dpe, dS, phis)
+    sg = -1.0 if dg < 0.0 else 1.0
+    S0 = sum(float(G.ANG_MAX[k]) * abs(float(C[k][0])) for k in range(10))
+    S1 = sum(float(G.ANG_MAX[k]) * abs(float(C[k][0]) + sg * float(C[k][1])) for k in range(10))
+    return max(S0, 0.5 * S1)
+
+
+def _sup_check(model, theta):
+    def run():
+        return 1.0, int(sup_ratio(model, theta) > G.bound(model, [float(x) for x in theta]))
+    return run
+
+
 def _gen_check(model, theta, n):
     def run():
         r = G.generate(model, theta, SEED + 100 + model, 0, n)
@@ -434,6 +450,8 @@ MUTATIONS = [
     ("Gamma_min without the absolute value", "_envelope_rate", lambda o: (lambda g, dg: g - dg / 2.0),
      _viol_check(3, THETA_GRID[3][4])),
     ("phi proposed on [0, pi]", "_angles", lambda o: _phi_half_range, _gen_check(3, M.THETA_GEN[3], 60_000)),
+    ("M3 without the oscillating terms", "bound_angtime", lambda o: _bound_ang_without_oscillation,
+     _sup_check(3, THETA_GRID[3][2])),
 ]
 
 
