@@ -10,7 +10,10 @@
     where u is within 1e-12 of a CDF step, and there must be none here);
   * q of every toy (relative 1e-11) and the CL counts: equal, except for
     toys whose q is within 1e-10 of q_obs (none expected), at the workload
-    of 10^4 bins with 10^4 toys per hypothesis.
+    of 10^4 bins with 10^4 toys per hypothesis;
+  * binned fits (the lockstep BFGS on nll_binned) of toys generated at a
+    known point: convergence, pulls, and stationarity of the oracle's
+    likelihood at the fitted point.
 """
 import math
 import sys
@@ -144,4 +147,49 @@ def test_cls_matches_oracle_at_the_workload(lib, ctx):
         assert big["cl_s"] == pytest.approx(big["cl_sb"] / big["cl_b"])
         say("CL_b %.4f CL_s+b %.4f CL_s %.4f" % (big["cl_b"], big["cl_sb"], big["cl_s"]))
     finally:
+        lib.ipx_hist_destroy(ctx, H)
+
+
+def test_binned_fits_recover_the_generation_point(lib, ctx):
+    """The binned fit of Examples 3-4: 20 signal + background toys of 10^3
+    bins generated at theta_gen (ipx_binned_toy), each fitted with the
+    lockstep BFGS on nll_binned and its gradient, errors from the inverse
+    finite-difference Hessian; every fit converges to a stationary point and
+    the pulls of the three parameters have mean within 4/sqrt(k) of 0 and
+    width within 4/sqrt(2k) of 1."""
+    from paper_1706_01420_amd import fit
+    n, ntoys = 1000, 20
+    th0 = np.array([400.0, 20_000.0, 0.004])
+    H = lib.ipx_hist_create(ctx, n, LO, HI, MU, SCORE, SSMEAR)
+    hs = []
+    try:
+        say("binned fits", ntoys)
+        for j in range(ntoys):
+            c = lib.ipx_binned_toy(ctx, H, th0, 77, 1, j)
+            hs.append(lib.ipx_hist_create(ctx, n, LO, HI, MU, SCORE, SSMEAR, c))
+
+        def evaluate(theta, active):
+            f = np.full(theta.shape[0], np.inf)
+            g = np.full(theta.shape, np.nan)
+            for j in np.flatnonzero(active):
+                f[j], g[j] = lib.nll_binned(ctx, hs[j], theta[j], grad=True)
+            return f, g
+        steps = np.array([30.0, 150.0, 2e-4])
+        start = np.tile(th0 + 2.0 * steps * np.array([1.0, -1.0, 1.0]), (ntoys, 1))
+        res = fit.bfgs(evaluate, start, steps)
+        assert res["converged"].all(), res["converged"]
+        err = fit.errors(evaluate, res["theta"], steps)
+        pulls = (res["theta"] - th0) / err
+        assert np.all(np.isfinite(pulls))
+        k = ntoys
+        assert np.all(np.abs(pulls.mean(axis=0)) < 4.0 / np.sqrt(k)), pulls.mean(axis=0)
+        assert np.all(np.abs(pulls.std(axis=0, ddof=1) - 1.0) < 4.0 / np.sqrt(2 * k)), pulls.std(axis=0, ddof=1)
+        for j in range(ntoys):       # a stationary point of the oracle's likelihood too
+            x, dx, sig = _oracle_template(n)
+            counts = lib.ipx_hist_read(ctx, hs[j], 1)
+            _, gr = B.nll_grad(counts, sig, x, res["theta"][j])
+            assert np.all(np.abs(gr) * steps < 1e-2), (j, gr)
+    finally:
+        for h in hs:
+            lib.ipx_hist_destroy(ctx, h)
         lib.ipx_hist_destroy(ctx, H)
