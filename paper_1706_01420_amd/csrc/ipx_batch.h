@@ -64,9 +64,9 @@ constexpr int kOuterCapTag = ((kOuterBlockTag + kRedPitch - 1) / kRedPitch + 1) 
 // each round of 64 events a wave forms the 40 coefficient adjoints of those
 // events from its LDS block, so the per-event factors never leave the chip:
 // lane 8b + g (b = 4h + j) sums f_k tau_j over the events 8g .. 8g + 7 for
-// the five k = 5h .. 5h + 4 (one tau read serves five products), the eight
-// lanes of b add their sums (xor butterfly, the same total in each), and lane
-// 8b + g, g < 5, keeps the running total of coefficient (5h + g, j).  Lanes
+// the five k = 5h .. 5h + 4 (one tau read serves five products), and lane
+// 8b + g, g < 5, adds sum g of the eight lanes of b (through the block) to
+// its running total of coefficient (5h + g, j).  Lanes
 // without an event write zeros to the block.  The block is the wave's part of
 // the reduction buffer, which the tile reduction reuses afterwards.
 template <bool GRAD, bool COH, int CAP, bool TAG = false>
@@ -122,12 +122,19 @@ __device__ __forceinline__ void tile_angtime(const SegInfo& S, const AngTimeCons
         for (int r = 0; r < 5; ++r) a[r] = fma(fr[r * kOuterPitch + c], t, a[r]);
       }
       wave_lds_sync();
+      // the eight lanes of b add their sums through the block: each lane
+      // puts its five in rows 0 .. 4 (column = lane), and lane 8b + g, g < 5,
+      // adds row g over the lanes 8b .. 8b + 7 pairwise, in the order of an
+      // xor butterfly
 #pragma unroll
-      for (int off = 1; off < 8; off <<= 1)
-#pragma unroll
-        for (int r = 0; r < 5; ++r) a[r] += __shfl_xor(a[r], off, 64);
-      const double mine = g == 0 ? a[0] : g == 1 ? a[1] : g == 2 ? a[2] : g == 3 ? a[3] : a[4];
-      if (g < 5) outer += mine;
+      for (int r = 0; r < 5; ++r) blk[r * kOuterPitch + lane] = a[r];
+      wave_lds_sync();
+      if (g < 5) {
+        const double2* q = reinterpret_cast<const double2*>(blk + g * kOuterPitch + 8 * b);
+        const double2 c01 = q[0], c23 = q[1], c45 = q[2], c67 = q[3];
+        outer += ((c01.x + c01.y) + (c23.x + c23.y)) + ((c45.x + c45.y) + (c67.x + c67.y));
+      }
+      wave_lds_sync();
     }
   }
   if constexpr (GRAD) {
