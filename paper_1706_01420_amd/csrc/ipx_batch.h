@@ -60,7 +60,8 @@ __device__ __forceinline__ void wave_lds_sync() {
 constexpr int kOuterCap = ((kOuterBlock + kRedPitch - 1) / kRedPitch + 1) & ~1;
 constexpr int kOuterCapTag = ((kOuterBlockTag + kRedPitch - 1) / kRedPitch + 1) & ~1;
 
-// Angular model; C is the coefficient table in LDS.  For the gradient, after
+// Angular model; C is the coefficient table (device memory read with uniform
+// addresses, or LDS).  For the gradient, after
 // each round of 64 events a wave forms the 40 coefficient adjoints of those
 // events from its LDS block, so the per-event factors never leave the chip:
 // lane 8b + g (b = 4h + j) sums f_k tau_j over the events 8g .. 8g + 7 for
@@ -85,8 +86,8 @@ __device__ __forceinline__ void tile_angtime(const SegInfo& S, const AngTimeCons
 #pragma unroll 1
   for (int e = 0; e < kEventsPerLane; ++e) {
     const unsigned j = threadIdx.x + (unsigned)e * kThreads;
-    // keeps the LDS table reads inside the loop (re-read per event rather
-    // than pinned in 80 registers)
+    // keeps the table reads inside the loop (re-read per event rather than
+    // pinned in 80 registers)
     asm volatile("" ::: "memory");
     if (base + j < S.cols.n) {
       const EventCols& cl = S.cols;
@@ -180,17 +181,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(WPE > 
                                                             const AngTimeConst* __restrict__ consts,
                                                             const unsigned char* __restrict__ active) {
   constexpr int kCap = GRAD ? (TAG ? kOuterCapTag : kOuterCap) : 1;
-  __shared__ double sC[40];
   __shared__ RedBuf<kCap> red;
   for (int64_t g = blockIdx.x; g < n_tiles; g += gridDim.x) {
     const TileRef tr = tiles[g];
     if (!active[tr.seg]) continue;
+    // the coefficient table is read where it is used, with uniform addresses
+    // (scalar loads: the contraction's operands come straight from scalar
+    // registers)
     const AngTimeConst& k = consts[tr.seg];
-    unsigned tid = threadIdx.x;
-    asm volatile("" : "+v"(tid));  // (the address is derived per tile, not kept live across tiles)
-    if (tid < 40) sC[tid] = (&k.C[0][0])[tid];
-    __syncthreads();
-    tile_angtime<GRAD, false, kCap, TAG>(segs[tr.seg], k, sC, tr.tile, red);
+    tile_angtime<GRAD, false, kCap, TAG>(segs[tr.seg], k, &k.C[0][0], tr.tile, red);
   }
 }
 

@@ -368,7 +368,7 @@ constexpr int kOuterBlock = (kOuterRows + 1) * kOuterPitch;
 constexpr int kOuterBlockTag = (kOuterRows + 2) * kOuterPitch;
 __device__ __forceinline__ unsigned outer_col(unsigned e) { return e + ((e >> 5) << 1); }
 
-// One event.  C is the coefficient table in LDS (row-major 10 x 4).  For the
+// One event.  C is the coefficient table (row-major 10 x 4).  For the
 // gradient, writes f_k and tau_j = w T_j / num into the wave's block at column
 // ob, and takes the weight from the block's weight row (the caller puts it
 // there when it loads the columns), not from w: read back only where it is

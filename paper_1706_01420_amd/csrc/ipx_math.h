@@ -71,6 +71,13 @@ __device__ __forceinline__ cplx cdiv(cplx a, cplx b) {
 // over their stated domains (measured against correctly rounded values by the
 // math self-check entry point).
 // ---------------------------------------------------------------------------
+// Rare branches.  The functions below run their common path on every lane
+// and then recompute, inside a wave vote, the lanes outside its domain: a
+// wave where no lane needs the rare path pays one vote, not the exec-mask
+// bookkeeping of a divergent if/else, and each lane's result is the one its
+// own branch gives (the common path's values on such lanes are discarded).
+__device__ __forceinline__ bool any_lane(bool c) { return __any(c) != 0; }
+
 constexpr double kLn2Hi = 0x1.62e42fefa39efp-1;   // ln 2 rounded to double
 constexpr double kLn2Lo = 0x1.abc9e3b39803fp-56;  // ln 2 - kLn2Hi
 constexpr double kLog2E = 0x1.71547652b82fep+0;   // 1 / ln 2
@@ -107,7 +114,6 @@ __device__ __forceinline__ double exp_fast(double x) {
 // minimax_coeffs.h (approximation error below 5e-18 relative); ln x =
 // e ln2 + ln m with the product e kLn2Hi exact inside the fused multiply-add.
 __device__ __forceinline__ double log_fast(double x) {
-  if (!__builtin_amdgcn_class(x, 0x180)) return log(x);  // not positive normal/subnormal
   double m = __builtin_amdgcn_frexp_mant(x);  // [1/2, 1)
   int e = __builtin_amdgcn_frexp_exp(x);
   if (m < kSqrtHalf) {
@@ -123,7 +129,12 @@ __device__ __forceinline__ double log_fast(double x) {
   const double s2x = 2.0 * s;
   const double lm = fma(s2x * s2, q, s2x);
   const double ef = static_cast<double>(e);
-  return fma(ef, kLn2Hi, fma(ef, kLn2Lo, lm));
+  double r = fma(ef, kLn2Hi, fma(ef, kLn2Lo, lm));
+  const bool other = !__builtin_amdgcn_class(x, 0x180);  // not positive normal/subnormal
+  if (any_lane(other)) {
+    if (other) r = log(x);
+  }
+  return r;
 }
 
 // sin x and cos x for |x| <= 2^19 (the library sincos beyond): x = k pi/2 + r
@@ -133,10 +144,6 @@ __device__ __forceinline__ double log_fast(double x) {
 // minimax_coeffs.h (approximation errors below 3e-17 relative), then the
 // quadrant k mod 4.
 __device__ __forceinline__ void sincos_fast(double x, double* sn, double* cs) {
-  if (fabs(x) > 0x1p19) {
-    sincos(x, sn, cs);
-    return;
-  }
   const double k = rint(x * kTwoOverPi);
   const double r = fma(-k, kPio2Lo, fma(-k, kPio2Hi, x));
   const double r2 = r * r;
@@ -154,27 +161,39 @@ __device__ __forceinline__ void sincos_fast(double x, double* sn, double* cs) {
   const int q = static_cast<int>(k);
   const double a = (q & 1) ? c : s;   // sin of the quadrant's base
   const double b = (q & 1) ? s : c;
-  *sn = (q & 2) ? -a : a;
-  *cs = ((q + 1) & 2) ? -b : b;
+  double so = (q & 2) ? -a : a;
+  double co = ((q + 1) & 2) ? -b : b;
+  const bool big = fabs(x) > 0x1p19;
+  if (any_lane(big)) {
+    if (big) sincos(x, &so, &co);
+  }
+  *sn = so;
+  *cs = co;
 }
 
 // e^x with a short Taylor polynomial when |x| <= 2^-9 (through x^5:
 // truncation below 1e-19 relative), exp_fast otherwise.
 __device__ __forceinline__ double exp_small(double x) {
-  if (fabs(x) > 0x1p-9) return exp_fast(x);
-  return 1.0 + x * (1.0 + x * (0.5 + x * (1.0 / 6.0 + x * (1.0 / 24.0 + x * (1.0 / 120.0)))));
+  double r = 1.0 + x * (1.0 + x * (0.5 + x * (1.0 / 6.0 + x * (1.0 / 24.0 + x * (1.0 / 120.0)))));
+  const bool large = fabs(x) > 0x1p-9;
+  if (any_lane(large)) {
+    if (large) r = exp_fast(x);
+  }
+  return r;
 }
 
 // sin and cos with Taylor polynomials when |x| <= 0.05 (sin through x^9, cos
 // through x^8: truncation below 3e-20 relative), sincos_fast otherwise.
 __device__ __forceinline__ void sincos_small(double x, double* s, double* c) {
-  if (fabs(x) > 0.05) {
-    sincos_fast(x, s, c);
-    return;
-  }
   const double x2 = x * x;
-  *s = x * (1.0 - x2 * (1.0 / 6.0 - x2 * (1.0 / 120.0 - x2 * (1.0 / 5040.0 - x2 * (1.0 / 362880.0)))));
-  *c = 1.0 - x2 * (0.5 - x2 * (1.0 / 24.0 - x2 * (1.0 / 720.0 - x2 * (1.0 / 40320.0))));
+  double so = x * (1.0 - x2 * (1.0 / 6.0 - x2 * (1.0 / 120.0 - x2 * (1.0 / 5040.0 - x2 * (1.0 / 362880.0)))));
+  double co = 1.0 - x2 * (0.5 - x2 * (1.0 / 24.0 - x2 * (1.0 / 720.0 - x2 * (1.0 / 40320.0))));
+  const bool large = fabs(x) > 0.05;
+  if (any_lane(large)) {
+    if (large) sincos_fast(x, &so, &co);
+  }
+  *s = so;
+  *c = co;
 }
 
 // The depth thresholds of cf_depth.h are multiples of 1/8 in [1/8, 32): as
@@ -330,26 +349,36 @@ __device__ __noinline__ cplx faddeeva_series(cplx z) {
 // w(z) for Im z >= 0; depth as for faddeeva_cf (full precision by default).
 __device__ __forceinline__ cplx faddeeva_upper(cplx z, int depth = kCfMaxDepth) {
   const double r2 = z.re * z.re + z.im * z.im;
-  if (r2 > 1e12) {
-    // asymptotic i/(sqrt(pi) z) (1 + 1/(2 z^2)); relative error < 1e-24 here
-    const cplx iz = cdiv(cplx{0.0, kInvSqrtPi}, z);
-    const cplx z2i = cdiv(cplx{0.5, 0.0}, cmul(z, z));
-    return cmul(iz, cplx{1.0 + z2i.re, z2i.im});
+  cplx w = faddeeva_cf(z, depth);
+  const bool huge = r2 > 1e12;
+  const bool inner = !(z.im >= 3.4 || r2 >= 36.0);  // (NaN included)
+  if (any_lane(huge || inner)) {
+    if (huge) {
+      // asymptotic i/(sqrt(pi) z) (1 + 1/(2 z^2)); relative error < 1e-24 here
+      const cplx iz = cdiv(cplx{0.0, kInvSqrtPi}, z);
+      const cplx z2i = cdiv(cplx{0.5, 0.0}, cmul(z, z));
+      w = cmul(iz, cplx{1.0 + z2i.re, z2i.im});
+    } else if (inner) {
+      w = faddeeva_series(z);
+    }
   }
-  if (z.im >= 3.4 || r2 >= 36.0) return faddeeva_cf(z, depth);
-  return faddeeva_series(z);
+  return w;
 }
 
 // erfcx(y) = e^{y^2} erfc(y) = w(i y) for y >= 0: the continued fraction in
 // real arithmetic (depth as for faddeeva_cf) for y >= 3.4, the (out-of-line)
 // rational series otherwise.
 __device__ __forceinline__ double erfcx_pos(double y, int depth = kCfMaxDepth) {
-  if (y < 3.4) return faddeeva_series(cplx{0.0, y}).re;
-  if (y > 1e6) return kInvSqrtPi / y * (1.0 - 0.5 / (y * y));
   const double z2 = -y * y;
   double pm = 1.0, qm = 0.0, p = z2 - 0.5, q = 1.0;
   cf_levels(z2, p, q, pm, qm, depth);
-  return -y * q * kInvSqrtPi * rcp(p);
+  double r = -y * q * kInvSqrtPi * rcp(p);
+  const bool small = y < 3.4, huge = y > 1e6;
+  if (any_lane(small || huge)) {
+    if (small) r = faddeeva_series(cplx{0.0, y}).re;
+    else if (huge) r = kInvSqrtPi / y * (1.0 - 0.5 / (y * y));
+  }
+  return r;
 }
 
 }  // namespace ipx
