@@ -141,8 +141,8 @@ __device__ __forceinline__ double reduce_component(const double* __restrict__ p,
 template <bool GRAD>
 __device__ __forceinline__ void event_mass(const MassConst& k, double m, double w, double* acc) {
   const double d = m - k.mu;
-  const double G = exp_fast(-d * d * k.q);
-  const double E = exp_fast(-k.lam * (m - kMLo));
+  const double G = exp_lo(-d * d * k.q);
+  const double E = exp_lo(-k.lam * (m - kMLo));
   const double P = k.cS * G + k.cB * E;
   acc[0] += w * log_fast(P);
   if constexpr (GRAD) {
@@ -187,7 +187,7 @@ __device__ __forceinline__ TimePoint time_point(double tau, double gmax, double 
   // the depth search (four wave votes) only where some lane needs it
   p.depth = __any(p.need) ? cf_depth_wave(p.need ? E : kCfSkipE) : 1;
   const double a = tau * inv_r2s;
-  p.g = p.need ? exp_fast(-a * a) : 0.0;
+  p.g = p.need ? exp_lo(-a * a) : 0.0;
   return p;
 }
 
@@ -224,8 +224,8 @@ __device__ __forceinline__ RateTerms rate_terms(double t, double rate, double h2
                                                 const TimePoint& pt, const TimePoint& pa,
                                                 const TimePoint& pb, double dphi) {
   RateTerms r;
-  const double e2 = exp_fast(h2 * s2);
-  const double Ft = conv_real(t, rate, e2 * exp_fast(-rate * t), pt, s2, inv_r2s);
+  const double e2 = exp_lo(h2 * s2);
+  const double Ft = conv_real(t, rate, e2 * exp_lo(-rate * t), pt, s2, inv_r2s);
   const double Fa = conv_real(kTLo, rate, e2 * eA, pa, s2, inv_r2s);
   const double Fb = conv_real(kTHi, rate, e2 * eB, pb, s2, inv_r2s);
   r.F = Ft;
@@ -269,8 +269,8 @@ __device__ __forceinline__ void event_masstime(const MassTimeConst& k, double m,
   const RateTerms rs = rate_terms<GRAD>(t, k.gs, k.hs2, k.eAs, k.eBs, k.inv_gs, sig, s2, inv_r2s, pt, pa, pb, dphi);
   const RateTerms rb = rate_terms<GRAD>(t, k.gb, k.hb2, k.eAb, k.eBb, k.inv_gb, sig, s2, inv_r2s, pt, pa, pb, dphi);
   const double d = m - k.mu;
-  const double G = exp_fast(-d * d * k.q);
-  const double E = exp_fast(-k.lam * (m - kMLo));
+  const double G = exp_lo(-d * d * k.q);
+  const double E = exp_lo(-k.lam * (m - kMLo));
   const double hs = rs.F * rcp(rs.I), hb = rb.F * rcp(rb.I);
   const double P = k.cS * G * hs + k.cB * E * hb;
   acc[0] += w * log_fast(P);
@@ -387,15 +387,15 @@ __device__ __forceinline__ void event_angtime(const AngTimeConst& k, const doubl
   const double inv_sig = rcp(sig);
   const double inv_r2s = kInvSqrt2 * inv_sig;
   const double dmr = k.dm * sig * kInvSqrt2;
-  const double eH2 = exp_small(k.hH2 * s2), eL2 = exp_small(k.hL2 * s2), ec2 = exp_fast(k.hc2 * s2);
+  const double eH2 = exp_small(k.hH2 * s2), eL2 = exp_small(k.hL2 * s2), ec2 = exp_lo(k.hc2 * s2);
   double sc, cc;
   sincos_small(k.gdm * s2, &sc, &cc);
   double st, ct;
   sincos_fast(k.dm * t, &st, &ct);
   // exp(z^2 s^2/2 - z tau) for z = Gamma - i dm has phase dm (tau - Gamma s^2);
   // e^{-Gamma_H t} = e^{-Gamma t} e^{DeltaGamma t/2}, e^{-Gamma_L t} = e^{-Gamma t} / e^{DeltaGamma t/2}
-  const double eG = exp_fast(-k.g * t);
-  const double eD = exp_fast(k.hdg * t);
+  const double eG = exp_lo(-k.g * t);
+  const double eD = exp_lo(k.hdg * t);
   const double mt = ec2 * eG;
   const Conv3 Xt = conv3(t, eH2 * (eG * eD), eL2 * (eG * rcp(eD)),
                          cplx{mt * (ct * cc + st * sc), mt * (st * cc - ct * sc)}, k, s2, inv_r2s, dmr, 0.0);

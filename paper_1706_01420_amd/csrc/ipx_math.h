@@ -86,16 +86,15 @@ constexpr double kPio2Lo = 0x1.1a62633145c07p-54; // pi/2 - kPio2Hi
 constexpr double kTwoOverPi = 0x1.45f306dc9c883p-1;
 constexpr double kSqrtHalf = 0x1.6a09e667f3bcdp-1;
 
-// e^x.  x = k ln2 + r with k = rint(x / ln2): x - k kLn2Hi is exact under the
-// fused multiply-add (both are multiples of 2^-53 and the difference is below
-// 1/2), so |r| <= ln2/2 up to rounding; e^r = 1 + r + r^2/2 + r^3 E(r) with
-// the degree-8 near-minimax E of minimax_coeffs.h (approximation error below
-// 4e-17 relative), then scaled by 2^k.  Arguments are clamped to [-1100, 710]
-// (results 0 and +inf beyond); NaN propagates.
-__device__ __forceinline__ double exp_fast(double x) {
-  const double xc = fmin(fmax(x, -1100.0), 710.0);
-  const double k = rint(xc * kLog2E);
-  const double r = fma(-k, kLn2Lo, fma(-k, kLn2Hi, xc));
+// e^x for x in [-1100, 2^40] or NaN.  x = k ln2 + r with k = rint(x / ln2):
+// x - k kLn2Hi is exact under the fused multiply-add (both are multiples of
+// 2^-53 and the difference is below 1/2), so |r| <= ln2/2 up to rounding;
+// e^r = 1 + r + r^2/2 + r^3 E(r) with the degree-8 near-minimax E of
+// minimax_coeffs.h (approximation error below 4e-17 relative), then scaled by
+// 2^k (0 below about -745, +inf above about 709.8: the scale saturates).
+__device__ __forceinline__ double exp_core(double x) {
+  const double k = rint(x * kLog2E);
+  const double r = fma(-k, kLn2Lo, fma(-k, kLn2Hi, x));
   constexpr int n = sizeof(kExpPoly) / sizeof(double);
   double p = kExpPoly[n - 1];
 #pragma unroll
@@ -103,9 +102,23 @@ __device__ __forceinline__ double exp_fast(double x) {
   p = fma(p, r, 0.5);
   p = fma(p, r, 1.0);
   p = fma(p, r, 1.0);
-  const double y = ldexp(p, static_cast<int>(k));
+  return ldexp(p, static_cast<int>(k));
+}
+
+// e^x for every x: arguments clamped to [-1100, 710] (results 0 and +inf
+// beyond); NaN propagates.
+__device__ __forceinline__ double exp_fast(double x) {
+  const double y = exp_core(fmin(fmax(x, -1100.0), 710.0));
   return x == x ? y : x;
 }
+
+// e^x for x <= 2^40 (-inf and NaN included), the value exp_fast gives there,
+// with one select instead of the two clamps and the NaN test: arguments below
+// -1100 are raised to it (a comparison, so NaN passes through).  The event
+// loops use it where an argument can exceed 2^40 only for event values far
+// outside any physical range (then the event's term is not finite either
+// way).
+__device__ __forceinline__ double exp_lo(double x) { return exp_core(x < -1100.0 ? -1100.0 : x); }
 
 // ln x for x > 0 (positive normal or subnormal; other arguments go to the
 // library log, so 0 gives -inf and negative x NaN).  x = 2^e m with m in
