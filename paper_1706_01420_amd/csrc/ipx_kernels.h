@@ -191,18 +191,24 @@ __device__ __forceinline__ TimePoint time_point(double tau, double gmax, double 
   return p;
 }
 
-__device__ __forceinline__ double conv_real(double tau, double rate, double main, const TimePoint& p,
-                                            double s2, double inv_r2s) {
-  if (!p.need) return main;
+// F from its main term, where the time point needs the correction
+__device__ __forceinline__ double conv_real_needed(double tau, double rate, double main, const TimePoint& p,
+                                                   double s2, double inv_r2s) {
   const double y = (tau - rate * s2) * inv_r2s;  // -Im u
   const double c = 0.5 * p.g * erfcx_pos(fabs(y), p.depth);
   return y >= 0.0 ? main - c : c;
 }
 
-// complex rate Gamma - i dm; dmr = dm s / sqrt2 = Re u
-__device__ __forceinline__ cplx conv_cplx(double tau, double rate, double dmr, cplx main, const TimePoint& p,
-                                          double s2, double inv_r2s) {
+__device__ __forceinline__ double conv_real(double tau, double rate, double main, const TimePoint& p,
+                                            double s2, double inv_r2s) {
   if (!p.need) return main;
+  return conv_real_needed(tau, rate, main, p, s2, inv_r2s);
+}
+
+// complex rate Gamma - i dm; dmr = dm s / sqrt2 = Re u; where the time point
+// needs the correction
+__device__ __forceinline__ cplx conv_cplx_needed(double tau, double rate, double dmr, cplx main, const TimePoint& p,
+                                                 double s2, double inv_r2s) {
   const double y = (tau - rate * s2) * inv_r2s;
   // w(-u) for y >= 0 (then F = main - g w(-u)/2), w(u) otherwise (F = g w(u)/2)
   const bool lower = y >= 0.0;
@@ -218,16 +224,42 @@ struct RateTerms {
   double dlz, dls;  // d ln(F/I) / d rate, d ln(F/I) / d sigma
 };
 
+// One rate's F at t and at the range ends (main terms, corrected where the
+// time point needs it), the two rates side by side so that each time point's
+// corrections take one branch.
+struct RatePair {
+  double t[2], a[2], b[2];
+  double phi_a, phi_b;  // the Phi terms 1/2 g erfcx(T / (sqrt2 s)) at the range ends, 0 where not needed
+};
+
+__device__ __forceinline__ RatePair rate_pair(double t, const MassTimeConst& k, double s2, double inv_r2s,
+                                              const TimePoint& pt, const TimePoint& pa, const TimePoint& pb) {
+  const double e2s = exp_lo(k.hs2 * s2), e2b = exp_lo(k.hb2 * s2);
+  RatePair F{{e2s * exp_lo(-k.gs * t), e2b * exp_lo(-k.gb * t)}, {e2s * k.eAs, e2b * k.eAb}, {e2s * k.eBs, e2b * k.eBb},
+             0.0, 0.0};
+  if (pt.need) {
+    F.t[0] = conv_real_needed(t, k.gs, F.t[0], pt, s2, inv_r2s);
+    F.t[1] = conv_real_needed(t, k.gb, F.t[1], pt, s2, inv_r2s);
+  }
+  if (pa.need) {
+    F.a[0] = conv_real_needed(kTLo, k.gs, F.a[0], pa, s2, inv_r2s);
+    F.a[1] = conv_real_needed(kTLo, k.gb, F.a[1], pa, s2, inv_r2s);
+    F.phi_a = 0.5 * pa.g * erfcx_pos(kTLo * inv_r2s, pa.depth);
+  }
+  if (pb.need) {
+    F.b[0] = conv_real_needed(kTHi, k.gs, F.b[0], pb, s2, inv_r2s);
+    F.b[1] = conv_real_needed(kTHi, k.gb, F.b[1], pb, s2, inv_r2s);
+    F.phi_b = 0.5 * pb.g * erfcx_pos(kTHi * inv_r2s, pb.depth);
+  }
+  return F;
+}
+
 template <bool GRAD>
-__device__ __forceinline__ RateTerms rate_terms(double t, double rate, double h2, double eA, double eB,
-                                                double inv_rate, double sig, double s2, double inv_r2s,
+__device__ __forceinline__ RateTerms rate_terms(double t, double rate, double Ft, double Fa, double Fb,
+                                                double inv_rate, double sig, double s2,
                                                 const TimePoint& pt, const TimePoint& pa,
                                                 const TimePoint& pb, double dphi) {
   RateTerms r;
-  const double e2 = exp_lo(h2 * s2);
-  const double Ft = conv_real(t, rate, e2 * exp_lo(-rate * t), pt, s2, inv_r2s);
-  const double Fa = conv_real(kTLo, rate, e2 * eA, pa, s2, inv_r2s);
-  const double Fb = conv_real(kTHi, rate, e2 * eB, pb, s2, inv_r2s);
   r.F = Ft;
   r.I = (dphi + Fa - Fb) * inv_rate;
   if constexpr (GRAD) {
@@ -262,12 +294,11 @@ __device__ __forceinline__ void event_masstime(const MassTimeConst& k, double m,
   const TimePoint pt = time_point(t, k.gmax, s2, inv_r2s, 0.0, 0.0);
   const TimePoint pa = time_point(kTLo, k.gmax, s2, inv_r2s, 0.0, k.gmax * kTLo);
   const TimePoint pb = time_point(kTHi, k.gmax, s2, inv_r2s, 0.0, k.gmax * kTHi);
+  const RatePair F = rate_pair(t, k, s2, inv_r2s, pt, pa, pb);
   // Phi(T_HI) - Phi(T_LO) = 1/2 [g_a erfcx(T_LO/(sqrt2 s)) - g_b erfcx(T_HI/(sqrt2 s))]
-  double dphi = 0.0;
-  if (pa.need) dphi += 0.5 * pa.g * erfcx_pos(kTLo * inv_r2s, pa.depth);
-  if (pb.need) dphi -= 0.5 * pb.g * erfcx_pos(kTHi * inv_r2s, pb.depth);
-  const RateTerms rs = rate_terms<GRAD>(t, k.gs, k.hs2, k.eAs, k.eBs, k.inv_gs, sig, s2, inv_r2s, pt, pa, pb, dphi);
-  const RateTerms rb = rate_terms<GRAD>(t, k.gb, k.hb2, k.eAb, k.eBb, k.inv_gb, sig, s2, inv_r2s, pt, pa, pb, dphi);
+  const double dphi = F.phi_a - F.phi_b;
+  const RateTerms rs = rate_terms<GRAD>(t, k.gs, F.t[0], F.a[0], F.b[0], k.inv_gs, sig, s2, pt, pa, pb, dphi);
+  const RateTerms rb = rate_terms<GRAD>(t, k.gb, F.t[1], F.a[1], F.b[1], k.inv_gb, sig, s2, pt, pa, pb, dphi);
   const double d = m - k.mu;
   const double G = exp_lo(-d * d * k.q);
   const double E = exp_lo(-k.lam * (m - kMLo));
@@ -296,19 +327,23 @@ struct Conv3 {
   double FH, FL;
   cplx Fc;
   double g;
-  int depth;
+  double phi;   // PHI: 1/2 g erfcx(tau / (sqrt2 s)) where needed, else 0
 };
 
+// The three convolved exponentials at one time point (and, at the range ends,
+// the Phi term of the normalisation), their corrections in one branch.
+template <bool PHI>
 __device__ __forceinline__ Conv3 conv3(double tau, double mainH, double mainL, cplx mainC,
                                        const AngTimeConst& k, double s2, double inv_r2s, double dmr,
                                        double e_shift) {
   const TimePoint p = time_point(tau, k.gmax, s2, inv_r2s, dmr * dmr, e_shift);
-  Conv3 r;
-  r.FH = conv_real(tau, k.gH, mainH, p, s2, inv_r2s);
-  r.FL = conv_real(tau, k.gL, mainL, p, s2, inv_r2s);
-  r.Fc = conv_cplx(tau, k.g, dmr, mainC, p, s2, inv_r2s);
-  r.g = p.g;
-  r.depth = p.depth;
+  Conv3 r{mainH, mainL, mainC, p.g, 0.0};
+  if (p.need) {
+    r.FH = conv_real_needed(tau, k.gH, mainH, p, s2, inv_r2s);
+    r.FL = conv_real_needed(tau, k.gL, mainL, p, s2, inv_r2s);
+    r.Fc = conv_cplx_needed(tau, k.g, dmr, mainC, p, s2, inv_r2s);
+    if constexpr (PHI) r.phi = 0.5 * p.g * erfcx_pos(tau * inv_r2s, p.depth);
+  }
   return r;
 }
 
@@ -397,18 +432,17 @@ __device__ __forceinline__ void event_angtime(const AngTimeConst& k, const doubl
   const double eG = exp_lo(-k.g * t);
   const double eD = exp_lo(k.hdg * t);
   const double mt = ec2 * eG;
-  const Conv3 Xt = conv3(t, eH2 * (eG * eD), eL2 * (eG * rcp(eD)),
+  const Conv3 Xt = conv3<false>(t, eH2 * (eG * eD), eL2 * (eG * rcp(eD)),
                          cplx{mt * (ct * cc + st * sc), mt * (st * cc - ct * sc)}, k, s2, inv_r2s, dmr, 0.0);
   const double ma = ec2 * k.eAG, mb = ec2 * k.eBG;
-  const Conv3 Xa = conv3(kTLo, eH2 * k.eAH, eL2 * k.eAL,
+  const Conv3 Xa = conv3<true>(kTLo, eH2 * k.eAH, eL2 * k.eAL,
                          cplx{ma * (k.cA * cc + k.sA * sc), ma * (k.sA * cc - k.cA * sc)}, k, s2, inv_r2s, dmr,
                          k.gmax * kTLo);
-  const Conv3 Xb = conv3(kTHi, eH2 * k.eBH, eL2 * k.eBL,
+  const Conv3 Xb = conv3<true>(kTHi, eH2 * k.eBH, eL2 * k.eBL,
                          cplx{mb * (k.cB * cc + k.sB * sc), mb * (k.sB * cc - k.cB * sc)}, k, s2, inv_r2s, dmr,
                          k.gmax * kTHi);
-  double dphi = 0.0;
-  if (Xa.g != 0.0) dphi += 0.5 * Xa.g * erfcx_pos(kTLo * inv_r2s, Xa.depth);
-  if (Xb.g != 0.0) dphi -= 0.5 * Xb.g * erfcx_pos(kTHi * inv_r2s, Xb.depth);
+  // Phi(T_HI) - Phi(T_LO) = 1/2 [g_a erfcx(T_LO/(sqrt2 s)) - g_b erfcx(T_HI/(sqrt2 s))]
+  const double dphi = Xa.phi - Xb.phi;
   const double IH = (dphi + Xa.FH - Xb.FH) * k.inv_gH;
   const double IL = (dphi + Xa.FL - Xb.FL) * k.inv_gL;
   const cplx Ic = cmul(cplx{dphi + Xa.Fc.re - Xb.Fc.re, Xa.Fc.im - Xb.Fc.im}, cplx{k.izr, k.izi});
