@@ -115,7 +115,7 @@ __device__ __forceinline__ void tile_angtime(const SegInfo& S, const AngTimeCons
       const double* fr = blk + 5 * (b >> 2) * kOuterPitch;
       const double* tr = blk + (10 + (b & 3u)) * kOuterPitch;
       double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll 2
+#pragma unroll
       for (unsigned i = 0; i < 8; ++i) {
         const unsigned c = outer_col(8 * g + i);
         const double t = tr[c];
