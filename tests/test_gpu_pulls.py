@@ -23,6 +23,11 @@ CASES = {1: (200, 20000), 2: (200, 20000), 3: (160, 40000)}
 # exponential cancels between the per-event density and its normalisation, so
 # the samples carry almost no information on s and it is not fitted.
 FIXED = {1: (), 2: (6,), 3: ()}
+# With a resolution wide against the lower time bound the scale is
+# identifiable: generated at s = 4 (sigma = 0.12 .. 0.24 ps, T_LO / sigma =
+# 1.25 .. 2.5, the region where the resolution shapes the time density), the
+# mass x decay-time model is fitted with all seven parameters free.
+WIDE_S = 4.0
 
 
 def say(*a):
@@ -42,16 +47,21 @@ def ctx(lib):
     lib.ipx_destroy(c)
 
 
-@pytest.mark.parametrize("model", [1, 2, 3])
-def test_pulls(lib, ctx, model):
+@pytest.mark.parametrize("case", [1, 2, 3, "2-wide"])
+def test_pulls(lib, ctx, case):
+    wide = case == "2-wide"
+    model = 2 if wide else case
     ntoys, n = CASES[model]
     theta = np.array(M.THETA_GEN[model])
-    say("pulls model", model, "toys", ntoys, "events", n)
-    ds = toys.generate(lib, ctx, model, theta, 4242 + model, [n] * ntoys, flags=lib.IPX_NO_WEIGHTS)
+    if wide:
+        theta[6] = WIDE_S
+    say("pulls case", case, "toys", ntoys, "events", n)
+    ds = toys.generate(lib, ctx, model, theta, 4242 + model + (10 if wide else 0), [n] * ntoys,
+                       flags=lib.IPX_NO_WEIGHTS)
     plan = lib.ipx_plan_create(ctx, ds)
     try:
         free = np.ones(theta.size, bool)
-        free[list(FIXED[model])] = False
+        free[list(() if wide else FIXED[model])] = False
         ev = fit.restrict(toys.batched_evaluator(lib, ctx, plan), np.tile(theta, (ntoys, 1)), free)
         steps = toys.steps_for(model, [n] * ntoys)[:, free]
         start = np.tile(theta[free], (ntoys, 1)) + 0.5 * steps

@@ -324,7 +324,8 @@ THETA_GRID = {
     1: [M.THETA_GEN[1], (0.7, 5300.0, 25.0, -0.003), (0.1, 5450.0, 8.0, 0.0), (1.0, 5367.0, 15.0, 0.01),
         (0.0, 5367.0, 15.0, -0.01), (0.5, 5210.0, 40.0, 3e-6)],
     2: [M.THETA_GEN[2], (0.6, 5320.0, 20.0, 0.0, 2.0, 0.4, 1.6), (0.05, 5367.0, 15.0, -0.002, 1.2, 1.9, 0.7),
-        (0.3, 5367.0, 15.0, 0.002, 1.5, 0.7, 1.3), (1.0, 5400.0, 10.0, 0.01, 0.4, 3.0, 2.0)],
+        (0.3, 5367.0, 15.0, 0.002, 1.5, 0.7, 1.3), (1.0, 5400.0, 10.0, 0.01, 0.4, 3.0, 2.0),
+        (0.3, 5367.0, 15.0, 0.002, 1.5, 0.7, 4.0)],
     3: [M.THETA_GEN[3], THETA_ALT[3],
         (0.6, 0.1, 0.0, 3.0, 3.0, 0.0, 0.6, -0.05, 18.5, -0.7, 5360.0, 18.0),
         (0.3, 0.35, 0.6, -1.0, 2.0, 1.5, 0.9, 0.5, 0.5, 1.2, 5367.0, 15.0),
