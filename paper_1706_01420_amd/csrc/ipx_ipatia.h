@@ -38,16 +38,26 @@ namespace ipx {
 
 constexpr int kIpatiaGrid = 1 << 14;
 constexpr int kIpatiaGridWg = kIpatiaGrid / kThreads;   // 64 workgroups of grid points
+constexpr int kTemmeTerms = 60;   // Temme's series: terms k = 1 .. kTemmeTerms - 1 at most
+constexpr int kTrapNodes = 20;    // trapezoidal rule: nodes s_j = j h, j = 0 .. 19
+constexpr double kTrapStep = 0.35;
 
 struct IpatiaConst {
   double mu, beta;
   double a2s2;            // A^2 sigma^2
+  double inv_a2s2;        // 1 / (A^2 sigma^2)
   double pw;              // exponent of q: lambda - 1/2 (zeta > 0) or 2 lambda - 1 (zeta = 0)
   double zeta;            // 0: the Student-like limit, no Bessel function
   // Bessel order |lambda - 1/2| = m + tmu, |tmu| <= 1/2, and Temme's constants
   double tmu, g1, g2, gp, gm, fact;
+  double igp, igm;        // 1 / gp, 1 / gm
   int m;
   int pad;
+  // the series' divisors as reciprocals, row k: 1/k, 1/(k - tmu), 1/(k + tmu),
+  // 1/(k^2 - tmu^2) (row 0 unused)
+  double rk[kTemmeTerms][4];
+  // the trapezoidal rule's node weights (1/2 at j = 0) x 2 exp(-s_j^2) and s_j^2
+  double tw[kTrapNodes], ts2[kTrapNodes];
   // tails
   double dl, Al, Bl, nl;  // junction -a sigma, A_l, B_l, n
   double dr, Ar, Br, nr;  // junction a2 sigma, A_r, B_r, n2
@@ -57,65 +67,86 @@ struct IpatiaConst {
   const double* inv_norm; // device: 1 / N_I of this call (written by the grid pass)
 };
 
-// K_tmu(x), K_{tmu+1}(x), |tmu| <= 1/2, x > 0.
-__device__ __forceinline__ void bessel_k_pair(const IpatiaConst& c, double x, double* k0, double* k1) {
+// sinh(s) / s: its Taylor series through s^16 for |s| < 1/2 (truncation below
+// 1e-19 relative), (e^s - e^-s) / (2 s) from the given exponentials above.
+__device__ __forceinline__ double sinhc(double s, double es, double ies) {
+  if (fabs(s) >= 0.5) return 0.5 * (es - ies) * rcp(s);
+  const double t = s * s;
+  double p = 1.0 / 355687428096000.0;        // 1/17!
+  p = fma(p, t, 1.0 / 1307674368000.0);      // 1/15!
+  p = fma(p, t, 1.0 / 6227020800.0);         // 1/13!
+  p = fma(p, t, 1.0 / 39916800.0);           // 1/11!
+  p = fma(p, t, 1.0 / 362880.0);             // 1/9!
+  p = fma(p, t, 1.0 / 5040.0);
+  p = fma(p, t, 1.0 / 120.0);
+  p = fma(p, t, 1.0 / 6.0);
+  return fma(p, t, 1.0);
+}
+
+// K_tmu(x), K_{tmu+1}(x), |tmu| <= 1/2, x > 0; ix = 1/x.  The divisions of
+// both methods are products with reciprocals (the series' divisors hoisted
+// per call, the rest through the hardware reciprocal), and the elementary
+// functions are the event loops' own (ipx_math.h).
+__device__ __forceinline__ void bessel_k_pair(const IpatiaConst& c, double x, double ix, double* k0, double* k1) {
   const double mu = c.tmu;
   if (x <= 2.0) {
-    const double lx = log(2.0 / x);
+    const double lx = log_fast(2.0 * ix);
     const double s = mu * lx;
-    const double es = exp(s);
-    const double ch = 0.5 * (es + 1.0 / es);
-    const double shs = s == 0.0 ? 1.0 : sinh(s) / s;
+    const double es = exp_fast(s);
+    const double ies = rcp(es);
+    const double ch = 0.5 * (es + ies);
+    const double shs = sinhc(s, es, ies);
     double f = c.fact * (ch * c.g1 + shs * lx * c.g2);
-    double p = 0.5 * es / c.gp;
-    double q = 0.5 / (es * c.gm);
+    double p = 0.5 * es * c.igp;
+    double q = 0.5 * ies * c.igm;
     double cc = 1.0;
     const double d = 0.25 * x * x;
     double s0 = f, s1 = p;
-    for (int k = 1; k < 60; ++k) {
+    for (int k = 1; k < kTemmeTerms; ++k) {
       const double dk = (double)k;
-      f = (dk * f + p + q) / (dk * dk - mu * mu);
-      cc *= d / dk;
-      p /= dk - mu;
-      q /= dk + mu;
+      const double* r = c.rk[k];
+      f = (dk * f + p + q) * r[3];
+      cc *= d * r[0];
+      p *= r[1];
+      q *= r[2];
       const double t0 = cc * f, t1 = cc * (p - dk * f);
       s0 += t0;
       s1 += t1;
       if (fabs(t0) < 1e-17 * fabs(s0) && fabs(t1) < 1e-17 * fabs(s1)) break;
     }
     *k0 = s0;
-    *k1 = s1 * (2.0 / x);
+    *k1 = s1 * (2.0 * ix);
     return;
   }
-  constexpr double h = 0.35;
-  const double r2x = sqrt(2.0 * x), inv_r2x = 1.0 / r2x;
+  const double r2x = sqrt(2.0 * x), inv_r2x = rcp(r2x);
   double s0 = 0.0, s1 = 0.0;
 #pragma unroll 4
-  for (int j = 0; j < 20; ++j) {
-    const double sv = j * h;
+  for (int j = 0; j < kTrapNodes; ++j) {
+    const double sv = j * kTrapStep;
     const double y = sv * inv_r2x;
     const double r = sqrt(1.0 + y * y);
-    const double em = exp(2.0 * mu * log(y + r));   // e^{mu t}
-    const double iem = 1.0 / em;
+    const double em = exp_fast(2.0 * mu * log_fast(y + r));   // e^{mu t}
+    const double iem = rcp(em);
     const double cm = 0.5 * (em + iem), sm = 0.5 * (em - iem);
     const double c1 = cm * (1.0 + 2.0 * y * y) + sm * (2.0 * y * r);   // cosh((mu + 1) t)
-    const double wgt = (j == 0 ? 0.5 : 1.0) * exp(-sv * sv) * 2.0 / sqrt(2.0 * x + sv * sv);
+    const double wgt = c.tw[j] * rcp(sqrt(2.0 * x + c.ts2[j]));
     s0 += wgt * cm;
     s1 += wgt * c1;
   }
-  const double ex = exp(-x) * h;
+  const double ex = exp_fast(-x) * kTrapStep;
   *k0 = ex * s0;
   *k1 = ex * s1;
 }
 
 // K_{m + tmu}(x) by the upward recurrence.
 __device__ __forceinline__ double bessel_k(const IpatiaConst& c, double x) {
+  const double ix = rcp(x);
   double km, kp;
-  bessel_k_pair(c, x, &km, &kp);
+  bessel_k_pair(c, x, ix, &km, &kp);
   if (c.m == 0) return km;
   double v = c.tmu + 1.0;   // kp = K_v
   for (int j = 1; j < c.m; ++j) {
-    const double kn = km + (2.0 * v / x) * kp;
+    const double kn = km + (2.0 * v * ix) * kp;
     km = kp;
     kp = kn;
     v += 1.0;
@@ -123,11 +154,13 @@ __device__ __forceinline__ double bessel_k(const IpatiaConst& c, double x) {
   return kp;
 }
 
+// The shape: power-law tails, and the core q^pw e^{beta d} (one exponential
+// of pw ln q + beta d) times the Bessel factor.
 __device__ __forceinline__ double ipatia_shape(const IpatiaConst& c, double d) {
-  if (d < c.dl) return c.Al * pow(c.Bl - d, -c.nl);
-  if (d > c.dr) return c.Ar * pow(c.Br + d, -c.nr);
-  const double q = sqrt(1.0 + d * d / c.a2s2);
-  const double g = pow(q, c.pw) * exp(c.beta * d);
+  if (d < c.dl) return c.Al * exp_fast(-c.nl * log_fast(c.Bl - d));
+  if (d > c.dr) return c.Ar * exp_fast(-c.nr * log_fast(c.Br + d));
+  const double q = sqrt(fma(d * d, c.inv_a2s2, 1.0));
+  const double g = exp_fast(fma(c.pw, log_fast(q), c.beta * d));
   return c.zeta == 0.0 ? g : g * bessel_k(c, c.zeta * q);
 }
 
@@ -135,7 +168,7 @@ __device__ __forceinline__ double ipatia_shape(const IpatiaConst& c, double d) {
 __global__ __launch_bounds__(kThreads) void k_ipatia_grid(const IpatiaConst* __restrict__ kc,
                                                           double* __restrict__ part) {
   __shared__ double lds4[kThreads / 64];
-  const IpatiaConst c = *kc;
+  const IpatiaConst& c = *kc;
   const int g = blockIdx.x * kThreads + threadIdx.x;
   const double m = c.lo + ((double)g + 0.5) * c.dm;
   double v = ipatia_shape(c, m - c.mu);
@@ -155,8 +188,8 @@ __global__ __launch_bounds__(kThreads) void k_ipatia_norm(const IpatiaConst* __r
 // One event: acc[0] += w ln P.
 __device__ __forceinline__ void event_ipatia(const IpatiaConst& c, double inv_norm, double m, double w,
                                              double* acc) {
-  const double P = c.f * ipatia_shape(c, m - c.mu) * inv_norm + c.cB * exp(-c.k * (m - kMLo));
-  acc[0] += w * log(P);
+  const double P = c.f * ipatia_shape(c, m - c.mu) * inv_norm + c.cB * exp_fast(-c.k * (m - kMLo));
+  acc[0] += w * log_fast(P);
 }
 
 // Host: the per-call constants from theta = (f, mu, sigma, lambda, zeta,
@@ -210,6 +243,7 @@ inline bool hoist_ipatia(const double* th, IpatiaConst& c) {
   c.mu = mu;
   c.beta = beta;
   c.a2s2 = A2 * sigma * sigma;
+  c.inv_a2s2 = 1.0 / c.a2s2;
   c.zeta = zeta;
   c.pw = zeta == 0.0 ? 2.0 * lam - 1.0 : lam - 0.5;
   const double nu = std::fabs(lam - 0.5);
@@ -231,6 +265,22 @@ inline bool hoist_ipatia(const double* th, IpatiaConst& c) {
   c.g2 = g2;
   c.gp = gp;
   c.gm = gm;
+  c.igp = 1.0 / gp;
+  c.igm = 1.0 / gm;
+  c.pad = 0;
+  for (int j = 0; j < 4; ++j) c.rk[0][j] = 0.0;
+  for (int kk = 1; kk < kTemmeTerms; ++kk) {
+    const double dk = kk;
+    c.rk[kk][0] = 1.0 / dk;
+    c.rk[kk][1] = 1.0 / (dk - c.tmu);
+    c.rk[kk][2] = 1.0 / (dk + c.tmu);
+    c.rk[kk][3] = 1.0 / (dk * dk - c.tmu * c.tmu);
+  }
+  for (int j = 0; j < kTrapNodes; ++j) {
+    const double sv = j * kTrapStep;
+    c.ts2[j] = sv * sv;
+    c.tw[j] = (j == 0 ? 0.5 : 1.0) * std::exp(-sv * sv) * 2.0;
+  }
   c.fact = c.tmu == 0.0 ? 1.0 : M_PI * c.tmu / std::sin(M_PI * c.tmu);
   // tails
   double sl, sr;
