@@ -139,16 +139,32 @@ def calibration_copy(nbytes=512 << 20, reps=3):
     return {"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}
 
 
-def timed_rate(ipx, ctx, ds, theta, steps, warmup, grad):
+# Secondary legs warm the GPU up for this long before their timed calls: after
+# the host prepares a leg's data the GPU has idled and needs ~50 ms of work to
+# reach its steady clock again (the main leg reports its own cold start).
+SECONDARY_WARM_S = 0.06
+
+
+def _warm(call, warmup, warm_s):
+    """warmup calls, then more until warm_s seconds of calls have run."""
+    import torch
+    for _ in range(warmup):
+        call()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < warm_s:
+        call()
+        torch.cuda.synchronize()
+
+
+def timed_rate(ipx, ctx, ds, theta, steps, warmup, grad, warm_s=0.0):
     """(seconds per call, seconds per launch of the per-event kernel).  The
     call rate is timed with the library's kernel timing off; the kernel time
     comes from a second pass of the same calls with HIP events around the
     per-event kernel on its stream."""
     import torch
     call = (lambda: ipx.nll_grad(ctx, ds, theta)) if grad else (lambda: ipx.nll_eval(ctx, ds, theta))
-    for _ in range(warmup):
-        call()
-    torch.cuda.synchronize()
+    _warm(call, warmup, warm_s)
     t0 = time.perf_counter()
     for _ in range(steps):
         call()
@@ -515,12 +531,10 @@ def _served_rates(ipx, ctx, ds, models, reqs, plain_rate, policy, rates, seed):
     return out
 
 
-def _timed_calls(call, steps, warmup, ipx=None, ctx=None):
+def _timed_calls(call, steps, warmup, ipx=None, ctx=None, warm_s=SECONDARY_WARM_S):
     """(seconds per call, seconds per timed kernel launch or None)."""
     import torch
-    for _ in range(warmup):
-        call()
-    torch.cuda.synchronize()
+    _warm(call, warmup, warm_s)
     t0 = time.perf_counter()
     for _ in range(steps):
         call()
@@ -634,9 +648,7 @@ def bench_mass_batch(ipx, ctx, steps, warmup, nb=64):
             dsl.append(ipx.ipx_dataset_create(ctx, 1, c, None))
         plan = ipx.ipx_plan_create(ctx, dsl)
         th = np.tile(np.array(workloads.THETA_GEN[1]), (nb, 1))
-        for _ in range(warmup):
-            ipx.nll_eval_batch(ctx, plan, th)
-        torch.cuda.synchronize()
+        _warm(lambda: ipx.nll_eval_batch(ctx, plan, th), warmup, SECONDARY_WARM_S)
         t0 = time.perf_counter()
         for _ in range(steps):
             ipx.nll_eval_batch(ctx, plan, th)
@@ -690,7 +702,7 @@ def main():
         ipx.nll_grad(ctx, ds, theta)
         cold = []
         for _ in range(10):
-            cold.append(_timed_calls(lambda: ipx.nll_grad(ctx, ds, theta), 25, 0)[0])
+            cold.append(_timed_calls(lambda: ipx.nll_grad(ctx, ds, theta), 25, 0, warm_s=0.0)[0])
     step_s, kernel_s = timed_rate(ipx, ctx, ds, theta, args.steps, args.warmup, grad=True)
     value = 1.0 / step_s
     progress("angular nll_grad: %.4f ms per call, kernel %.1f us" % (step_s * 1e3, kernel_s * 1e6))
@@ -730,7 +742,8 @@ def main():
     }
     extra = {}
     if not args.no_extra:
-        e_step, e_kern = timed_rate(ipx, ctx, ds, theta, max(args.steps // 2, 5), max(args.warmup // 2, 2), grad=False)
+        e_step, e_kern = timed_rate(ipx, ctx, ds, theta, max(args.steps // 2, 5), max(args.warmup // 2, 2), grad=False,
+                                    warm_s=SECONDARY_WARM_S)
         fe = algorithmic_flops(model, cols[3], cols[4], theta, False)
         extra["angtime_nll_eval"] = {"evals_per_s": 1 / e_step, "kernel_us": e_kern * 1e6,
                                      "flop_per_event": fe / n, "tflops": fe / e_kern / 1e12}
@@ -742,7 +755,8 @@ def main():
             d = ipx.ipx_dataset_create(ctx, m, c, wm)
             th = np.array(workloads.THETA_GEN[m])
             for grad in (False, True):
-                s, k = timed_rate(ipx, ctx, d, th, max(args.steps // 2, 5), max(args.warmup // 2, 2), grad)
+                s, k = timed_rate(ipx, ctx, d, th, max(args.steps // 2, 5), max(args.warmup // 2, 2), grad,
+                                  warm_s=SECONDARY_WARM_S)
                 key = ("mass" if m == 1 else "masstime") + ("_nll_grad" if grad else "_nll_eval")
                 fm = algorithmic_flops(m, c[1], c[2], th, grad) if m == 2 else FLOP_BASE[(m, grad)] * nm
                 extra[key] = {"n_events": nm, "evals_per_s": 1 / s, "us_per_eval": s * 1e6,
@@ -753,6 +767,9 @@ def main():
         extra["mass_nll_eval_batch64"] = bench_mass_batch(ipx, ctx, max(args.steps // 2, 5),
                                                           max(args.warmup // 2, 2))
         extra.update(bench_next(ipx, ctx, max(args.steps // 2, 5), max(args.warmup // 2, 2)))
+        extra["warm_up"] = ("each secondary leg runs W/2 warm-up calls and then %.0f ms of further calls before "
+                            "its timed calls (the GPU idles while the host prepares a leg's data)"
+                            % (SECONDARY_WARM_S * 1e3))
         out["extra"] = extra
         progress("secondary rates done")
     if not args.no_batched and not args.profile:
