@@ -61,6 +61,36 @@ def test_ipatia_nll_and_events_match_oracle(lib, ctx, n):
         lib.ipx_dataset_destroy(ctx, ds)
 
 
+def test_ipatia_empty_sample(lib, ctx):
+    ds = lib.ipx_dataset_create(ctx, 5, [np.empty(0)], None)
+    try:
+        assert lib.nll_eval(ctx, ds, I.THETA_GEN) == 0.0
+        assert lib.ipx_event_logp(ctx, ds, I.THETA_GEN).numel() == 0
+    finally:
+        lib.ipx_dataset_destroy(ctx, ds)
+
+
+@pytest.mark.parametrize("n", [(1 << 19), (1 << 19) + 1])
+def test_ipatia_either_side_of_the_tile_switch(lib, ctx, n):
+    """One event per lane up to 2^19 events, four above: the NLL against the
+    oracle on both sides (the per-event terms as a sampled check)."""
+    cols, _ = W.events(5, n, seed=77)
+    m = cols[0]
+    ds = lib.ipx_dataset_create(ctx, 5, cols, None)
+    try:
+        th = THETAS[1]
+        f = lib.nll_eval(ctx, ds, th)
+        ref = I.nll(m, th, None)
+        say("ipatia n", n, f, ref)
+        assert math.isfinite(f) and abs(f - ref) <= 1e-10 * abs(ref), (f, ref)
+        got = lib.ipx_event_logp(ctx, ds, th).cpu().numpy()
+        idx = np.random.default_rng(n).choice(n, 4096, replace=False)
+        er = np.log(I.pdf(m[idx], th))
+        assert np.all(np.abs(got[idx] - er) <= 1e-12 * np.maximum(1.0, np.abs(er)))
+    finally:
+        lib.ipx_dataset_destroy(ctx, ds)
+
+
 def test_ipatia_domain_and_unsupported_forms(lib, ctx):
     cols, _ = W.events(5, 3000, seed=3)
     ds = lib.ipx_dataset_create(ctx, 5, cols, None)
