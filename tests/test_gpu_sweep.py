@@ -140,6 +140,27 @@ def test_per_event_terms_match_oracle_at_full_size(lib, ctx, model):
         lib.ipx_dataset_destroy(ctx, ds)
 
 
+@pytest.mark.parametrize("model", [2, 3])
+def test_per_event_terms_at_resolution_extremes(lib, ctx, model):
+    """sigma_t log-uniform over [0.002, 0.5] ps, in input order: every event's
+    term against the oracle where the corrections are skipped, at every
+    continued-fraction depth, on the rational-series branch (Im u < 3.4) and,
+    for the complex rate, at |u| >= 6 with E < 0."""
+    n = 20000
+    cols, w = W.events(model, n, seed=131)
+    scol = 2 if model == 2 else 4
+    cols = [c.copy() for c in cols]
+    cols[scol] = np.exp(np.random.default_rng(132).uniform(np.log(0.002), np.log(0.5), n))
+    ds = lib.ipx_dataset_create(ctx, model, cols, w, flags=lib.IPX_COPY_HOST | lib.IPX_KEEP_ORDER)
+    try:
+        for label, th in (("gen", M.THETA_GEN[model]), theta_sweep.points(model)[3][:2]):
+            say("per-event terms at resolution extremes, model", model, label)
+            got = lib.ipx_event_logp(ctx, ds, th).cpu().numpy()
+            _check_events(got, N.log_pdf(model, cols, th) * (1.0 if w is None else w), label)
+    finally:
+        lib.ipx_dataset_destroy(ctx, ds)
+
+
 @pytest.mark.parametrize("model", [1, 2, 3])
 @pytest.mark.parametrize("n", [0, 1, 63, 65, 1025])
 def test_per_event_terms_small_and_ragged(lib, ctx, model, n):
