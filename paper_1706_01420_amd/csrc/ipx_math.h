@@ -86,7 +86,7 @@ constexpr double kPio2Lo = 0x1.1a62633145c07p-54; // pi/2 - kPio2Hi
 constexpr double kTwoOverPi = 0x1.45f306dc9c883p-1;
 constexpr double kSqrtHalf = 0x1.6a09e667f3bcdp-1;
 
-// e^x for x in [-1100, 2^40] or NaN.  x = k ln2 + r with k = rint(x / ln2):
+// e^x for x in [-1100, 2^30] or NaN.  x = k ln2 + r with k = rint(x / ln2):
 // x - k kLn2Hi is exact under the fused multiply-add (both are multiples of
 // 2^-53 and the difference is below 1/2), so |r| <= ln2/2 up to rounding;
 // e^r = 1 + r + r^2/2 + r^3 E(r) with the degree-8 near-minimax E of
@@ -112,12 +112,13 @@ __device__ __forceinline__ double exp_fast(double x) {
   return x == x ? y : x;
 }
 
-// e^x for x <= 2^40 (-inf and NaN included), the value exp_fast gives there,
+// e^x for x <= 2^30 (-inf and NaN included), the value exp_fast gives there,
 // with one select instead of the two clamps and the NaN test: arguments below
-// -1100 are raised to it (a comparison, so NaN passes through).  The event
-// loops use it where an argument can exceed 2^40 only for event values far
-// outside any physical range (then the event's term is not finite either
-// way).
+// -1100 are raised to it (a comparison, so NaN passes through).  Above 2^30
+// the value is unspecified (the scale 2^k leaves the int range; this hardware's
+// conversion saturates, giving +inf).  The event loops use it where an
+// argument exceeds 2^30 only for event values far outside any physical range
+// (decay times beyond 10^9 ps, say).
 __device__ __forceinline__ double exp_lo(double x) { return exp_core(x < -1100.0 ? -1100.0 : x); }
 
 // ln x for x > 0 (positive normal or subnormal; other arguments go to the
