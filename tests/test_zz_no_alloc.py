@@ -60,7 +60,7 @@ def check_oracle(model, cols, w, theta, f, g):
     assert np.all(np.abs(g - gref) <= bound), (g, gref)
 
 
-@pytest.mark.parametrize("model", [1, 2, 3])
+@pytest.mark.parametrize("model", [1, 2, 3, 4])
 @pytest.mark.parametrize("grad", [False, True])
 def test_noalloc_equals_borrowed_dataset(lib, ctx, model, grad):
     theta = np.array(M.THETA_GEN[model]) * (1.0 + 0.01 * np.arange(1, len(M.THETA_GEN[model]) + 1) / 12.0)
@@ -68,7 +68,7 @@ def test_noalloc_equals_borrowed_dataset(lib, ctx, model, grad):
     # then fewer tiles than the first call left in the scratch)
     for n, seed in ((9 * 1024 + 333, 31), (2 * 1024 + 45, 32)):
         cols, w = W.events(model, n, seed=seed)
-        if model != 3:
+        if model not in (3, 4):
             w = None if seed == 31 else w
         dc, dw = device_cols(cols, w)
         say("nll_eval_noalloc model", model, "grad", grad, "n", n)
