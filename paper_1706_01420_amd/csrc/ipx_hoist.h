@@ -169,6 +169,9 @@ inline MassTimeHoist hoist_masstime(const double* th) {
   k.eBb = std::exp(-k.gb * kTHi);
   k.inv_gs = ts;
   k.inv_gb = tb;
+  k.shA = k.gmax * kTLo;
+  k.shB = k.gmax * kTHi;
+  k.q2 = 2.0 * k.q;
   return h;
 }
 inline void grad_masstime(const MassTimeHoist& h, const double* th, const double* a, double* g) {
@@ -291,6 +294,11 @@ inline void hoist_angtime_values(const double* th, const AngSettings& set, AngTi
   k.mu = mu;
   k.q = 1.0 / (2.0 * sig * sig);
   k.lnNG = std::log(ng.N);
+  k.shA = k.gmax * kTLo;
+  k.shB = k.gmax * kTHi;
+  k.Dp = 0.5 * (k.D[0] + k.D[1]);
+  k.Dm = 0.5 * (k.D[0] - k.D[1]);
+  k.q2 = 2.0 * k.q;
 }
 // Fills h (kernel constants, mass normalisation, the settings used).
 inline void hoist_angtime(const double* th, const AngSettings& set, AngTimeHoist& h) {

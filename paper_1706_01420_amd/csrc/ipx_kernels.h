@@ -292,8 +292,8 @@ __device__ __forceinline__ void event_masstime(const MassTimeConst& k, double m,
   const double s2 = sig * sig;
   const double inv_r2s = kInvSqrt2 * rcp(sig);
   const TimePoint pt = time_point(t, k.gmax, s2, inv_r2s, 0.0, 0.0);
-  const TimePoint pa = time_point(kTLo, k.gmax, s2, inv_r2s, 0.0, k.gmax * kTLo);
-  const TimePoint pb = time_point(kTHi, k.gmax, s2, inv_r2s, 0.0, k.gmax * kTHi);
+  const TimePoint pa = time_point(kTLo, k.gmax, s2, inv_r2s, 0.0, k.shA);
+  const TimePoint pb = time_point(kTHi, k.gmax, s2, inv_r2s, 0.0, k.shB);
   const RatePair F = rate_pair(t, k, s2, inv_r2s, pt, pa, pb);
   // Phi(T_HI) - Phi(T_LO) = 1/2 [g_a erfcx(T_LO/(sqrt2 s)) - g_b erfcx(T_HI/(sqrt2 s))]
   const double dphi = F.phi_a - F.phi_b;
@@ -311,7 +311,7 @@ __device__ __forceinline__ void event_masstime(const MassTimeConst& k, double m,
     const double pbk = k.cB * E * hb * iw;
     acc[1] += G * hs * iw;
     acc[2] += E * hb * iw;
-    acc[3] += ps * 2.0 * k.q * d;
+    acc[3] += ps * k.q2 * d;
     acc[4] -= ps * d * d;
     acc[5] -= pbk * (m - kMLo);
     acc[6] += ps * rs.dlz;
@@ -437,10 +437,10 @@ __device__ __forceinline__ void event_angtime(const AngTimeConst& k, const doubl
   const double ma = ec2 * k.eAG, mb = ec2 * k.eBG;
   const Conv3 Xa = conv3<true>(kTLo, eH2 * k.eAH, eL2 * k.eAL,
                          cplx{ma * (k.cA * cc + k.sA * sc), ma * (k.sA * cc - k.cA * sc)}, k, s2, inv_r2s, dmr,
-                         k.gmax * kTLo);
+                         k.shA);
   const Conv3 Xb = conv3<true>(kTHi, eH2 * k.eBH, eL2 * k.eBL,
                          cplx{mb * (k.cB * cc + k.sB * sc), mb * (k.sB * cc - k.cB * sc)}, k, s2, inv_r2s, dmr,
-                         k.gmax * kTHi);
+                         k.shB);
   // Phi(T_HI) - Phi(T_LO) = 1/2 [g_a erfcx(T_LO/(sqrt2 s)) - g_b erfcx(T_HI/(sqrt2 s))]
   const double dphi = Xa.phi - Xb.phi;
   const double IH = (dphi + Xa.FH - Xb.FH) * k.inv_gH;
@@ -516,11 +516,11 @@ __device__ __forceinline__ void event_angtime(const AngTimeConst& k, const doubl
     const cplx dFca = dconv_cplx(kTLo, k, Xa.Fc, s2, Ga);
     const cplx dFcb = dconv_cplx(kTHi, k, Xb.Fc, s2, Gb);
     const cplx dIc = cmul(cplx{-Ic.re + dFca.re - dFcb.re, -Ic.im + dFca.im - dFcb.im}, cplx{k.izr, k.izi});
-    acc[5] += 0.5 * (A[0] + A[1]) * dFHt * inum - 0.5 * (k.D[0] + k.D[1]) * dIH * iden;
-    acc[6] += 0.5 * (A[0] - A[1]) * dFLt * inum - 0.5 * (k.D[0] - k.D[1]) * dIL * iden;
+    acc[5] += 0.5 * (A[0] + A[1]) * dFHt * inum - k.Dp * dIH * iden;
+    acc[6] += 0.5 * (A[0] - A[1]) * dFLt * inum - k.Dm * dIL * iden;
     acc[7] += (A[2] * dFct.re + A[3] * dFct.im) * inum - (D2 * dIc.re + D3 * dIc.im) * iden;
     acc[8] += (A[2] * dFct.im - A[3] * dFct.re) * inum - (D2 * dIc.im - D3 * dIc.re) * iden;
-    acc[9] += w * 2.0 * k.q * d;
+    acc[9] += w * k.q2 * d;
     acc[10] -= w * d * d;
     acc[11] += w;
   }

@@ -45,6 +45,8 @@ struct MassTimeConst {
   double gmax;
   double eAs, eBs, eAb, eBb;  // exp(-gs T_LO), exp(-gs T_HI), exp(-gb T_LO), exp(-gb T_HI)
   double inv_gs, inv_gb;
+  double shA, shB;   // gmax T_LO, gmax T_HI (per-call products of the event loop)
+  double q2;         // 2 q
 };
 
 struct AngTimeConst {
@@ -59,6 +61,10 @@ struct AngTimeConst {
   double inv_gH, inv_gL;
   double izr, izi;             // 1 / (Gamma - i dm)
   double mu, q, lnNG;          // signal mass: mean, 1/(2 sigma^2), ln N_G
+  // per-call products the event loop would otherwise form on every event
+  double shA, shB;             // gmax T_LO, gmax T_HI
+  double Dp, Dm;               // (D_0 + D_1) / 2, (D_0 - D_1) / 2
+  double q2;                   // 2 q
 };
 
 }  // namespace ipx
